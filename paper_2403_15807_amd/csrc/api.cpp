@@ -1,0 +1,352 @@
+// api.cpp -- the C ABI of include/vrs.h: argument validation, table
+// ownership, the access-path planner, workspace carving and the launch
+// sequence of a scan.  Host code only; kernels live in k_*.hip.
+//
+// A scan of B queries runs, all asynchronously on the caller's stream:
+//   prep      -> pad queries, FP64 query norms, reset the fallback counter
+//   [select]  -> gather strategy only: predicate -> selection vector
+//   screen    -> per (query tile, row chunk): K smallest FP32 screening keys
+//   merge     -> per query: K smallest keys over all chunks
+//   rerank    -> per query: FP64 distances of the k' survivors, (dist, id)
+//                order, certificate against the (k'+1)-th screening key
+//   fallback  -> exact FP64 scan for the queries whose certificate failed
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <string>
+
+#include "internal.h"
+#include "planner.h"
+
+using namespace vrs;
+
+namespace {
+
+thread_local std::string g_err;
+
+vrs_status fail(vrs_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+vrs_status fail(vrs_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+vrs_status ok() {
+    g_err.clear();
+    return VRS_OK;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(VRS_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));             \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Host-side fold of an ABI predicate into inclusive int32 ranges.
+vrs_status fold_pred(const vrs_pred *p, int n_attr, PredDev *out) {
+    PredDev o{};
+    o.nterms = 0;
+    for (int t = 0; t < 4; ++t) {
+        o.col[t] = 0;
+        o.lo[t] = 0;
+        o.hi[t] = -1;
+    }
+    if (!p) {
+        *out = o;
+        return VRS_OK;
+    }
+    if (p->nterms < 0 || p->nterms > VRS_MAX_TERMS)
+        return fail(VRS_E_ARG, "pred.nterms=%d outside [0,%d]", p->nterms, VRS_MAX_TERMS);
+    bool empty = false;
+    for (int t = 0; t < p->nterms; ++t) {
+        const vrs_range &r = p->term[t];
+        if (r.col < 0 || r.col >= n_attr)
+            return fail(VRS_E_ARG, "pred.term[%d].col=%d outside [0,%d)", t, r.col, n_attr);
+        int64_t lo = r.lo, hi = r.hi;
+        if (hi <= lo || hi <= (int64_t)INT32_MIN || lo > (int64_t)INT32_MAX) {
+            empty = true;
+            continue;
+        }
+        o.col[t] = r.col;
+        o.lo[t] = (int32_t)std::max<int64_t>(lo, INT32_MIN);
+        o.hi[t] = (int32_t)std::min<int64_t>(hi - 1, INT32_MAX);
+    }
+    o.nterms = empty ? -1 : p->nterms;
+    *out = o;
+    return VRS_OK;
+}
+
+}  // namespace
+
+namespace vrs {
+
+int elem_bytes(vrs_dtype t) { return t == VRS_F32 ? 4 : (t == VRS_BF16 ? 2 : 1); }
+
+// Rows are zero-padded so that a row is a whole number of 128-byte blocks.
+int pad_dim(int d, vrs_dtype t) {
+    int per = 128 / elem_bytes(t);
+    return (d + per - 1) / per * per;
+}
+
+// Estimated fraction of rows satisfying `p` from the per-column histograms,
+// assuming independent columns.
+double estimate_selectivity(const vrs_table_s *t, const PredDev &p) {
+    if (p.nterms < 0) return 0.0;
+    double sel = 1.0;
+    for (int k = 0; k < p.nterms; ++k) {
+        int c = p.col[k];
+        const int64_t lo = t->amin[c], span = (int64_t)t->amax[c] - lo + 1;
+        double hit = 0.0, tot = 0.0;
+        for (int b = 0; b < HIST_BINS; ++b) {
+            // values v with floor((v - lo) * BINS / span) == b
+            int64_t v0 = lo + (b * span + HIST_BINS - 1) / HIST_BINS;
+            int64_t v1 = lo + ((b + 1) * span + HIST_BINS - 1) / HIST_BINS;  // exclusive
+            double cntb = t->hist[c][b];
+            tot += cntb;
+            if (v1 <= v0 || cntb == 0) continue;
+            int64_t a = std::max<int64_t>(v0, p.lo[k]), z = std::min<int64_t>(v1 - 1, p.hi[k]);
+            if (z >= a) hit += cntb * (double)(z - a + 1) / (double)(v1 - v0);
+        }
+        sel *= tot > 0 ? hit / tot : 0.0;
+    }
+    return sel;
+}
+
+}  // namespace vrs
+
+// ====================================================================== API
+extern "C" {
+
+const char *vrs_last_error(void) { return g_err.c_str(); }
+
+vrs_status vrs_build_table(const float *vec, int64_t n, int32_t d, const int32_t *attr,
+                           int32_t n_attr, vrs_dtype store, int32_t normalize, void *stream,
+                           vrs_table *out) {
+    if (!out) return fail(VRS_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!vec) return fail(VRS_E_ARG, "vec is NULL");
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(VRS_E_ARG, "n=%lld outside [1, 2^31)", (long long)n);
+    if (d < 1 || d > 4096) return fail(VRS_E_ARG, "d=%d outside [1, 4096]", d);
+    if (n_attr < 0 || n_attr > 64) return fail(VRS_E_ARG, "n_attr=%d outside [0, 64]", n_attr);
+    if (n_attr > 0 && !attr) return fail(VRS_E_ARG, "attr is NULL with n_attr=%d", n_attr);
+    if (store != VRS_F32 && store != VRS_BF16 && store != VRS_FP8E4M3)
+        return fail(VRS_E_ARG, "unknown storage dtype %d", (int)store);
+    hipStream_t s = (hipStream_t)stream;
+    auto *t = new vrs_table_s();
+    t->n = n;
+    t->d = d;
+    t->dp = pad_dim(d, store);
+    t->n_attr = n_attr;
+    t->store = store;
+    HIP_TRY(hipGetDevice(&t->device));
+    auto cleanup = [&]() { vrs_destroy_table(t); };
+    size_t rows_bytes = (size_t)n * t->dp * elem_bytes(store);
+    void *scratch = nullptr;
+    size_t hist_words = (size_t)std::max(n_attr, 1) * HIST_BINS;
+    size_t scratch_bytes = 16 + 16 + 2 * 4 * 64 + hist_words * 4;
+    if (hipMalloc(&t->rows, rows_bytes) != hipSuccess ||
+        hipMalloc((void **)&t->norm2, (size_t)n * 4) != hipSuccess ||
+        (store == VRS_FP8E4M3 && hipMalloc((void **)&t->scale, (size_t)n * 4) != hipSuccess) ||
+        (n_attr > 0 && hipMalloc((void **)&t->attr, (size_t)n * n_attr * 4) != hipSuccess) ||
+        hipMalloc(&scratch, scratch_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        if (scratch) (void)hipFree(scratch);
+        cleanup();
+        return fail(VRS_E_NOMEM, "device allocation of %zu bytes failed", rows_bytes);
+    }
+    unsigned long long *mx = (unsigned long long *)scratch;
+    int *bad = (int *)((char *)scratch + 16);
+    int32_t *amin = (int32_t *)((char *)scratch + 32);
+    int32_t *amax = amin + 64;
+    uint32_t *hist = (uint32_t *)(amax + 64);
+    hipError_t e = hipMemsetAsync(scratch, 0, 32, s);
+    if (e == hipSuccess && n_attr > 0)
+        e = hipMemcpyAsync(t->attr, attr, (size_t)n * n_attr * 4, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = launch_build_rows(vec, n, d, t->dp, store, normalize, t->rows, t->scale, t->norm2, mx,
+                              bad, s);
+    if (e == hipSuccess) e = launch_attr_stats(t->attr, n, n_attr, amin, amax, hist, s);
+    unsigned long long mxh = 0;
+    int badh = 0;
+    std::vector<int32_t> hmin(std::max(n_attr, 1)), hmax(std::max(n_attr, 1));
+    std::vector<uint32_t> hh(hist_words);
+    if (e == hipSuccess) e = hipMemcpyAsync(&mxh, mx, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&badh, bad, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && n_attr > 0) {
+        e = hipMemcpyAsync(hmin.data(), amin, 4 * n_attr, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(hmax.data(), amax, 4 * n_attr, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(hh.data(), hist, hist_words * 4, hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the library's only host sync
+    (void)hipFree(scratch);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(VRS_E_HIP, "table build failed: %s", hipGetErrorString(e));
+    }
+    if (badh) {
+        cleanup();
+        return fail(VRS_E_NONFINITE, "the table holds a non-finite value (or overflows the storage type)");
+    }
+    double mxd;
+    memcpy(&mxd, &mxh, 8);
+    t->max_norm = mxd;
+    for (int c = 0; c < n_attr; ++c) {
+        t->amin.push_back(hmin[c]);
+        t->amax.push_back(hmax[c]);
+        t->hist.emplace_back(hh.begin() + (size_t)c * HIST_BINS, hh.begin() + (size_t)(c + 1) * HIST_BINS);
+    }
+    *out = t;
+    return ok();
+}
+
+vrs_status vrs_destroy_table(vrs_table t) {
+    if (!t) return fail(VRS_E_ARG, "table is NULL");
+    if (t->rows) (void)hipFree(t->rows);
+    if (t->scale) (void)hipFree(t->scale);
+    if (t->norm2) (void)hipFree(t->norm2);
+    if (t->attr) (void)hipFree(t->attr);
+    delete t;
+    return ok();
+}
+
+vrs_status vrs_table_info(vrs_table t, int64_t *n, int32_t *d, int32_t *n_attr, vrs_dtype *store,
+                          double *max_row_norm) {
+    if (!t) return fail(VRS_E_ARG, "table is NULL");
+    if (n) *n = t->n;
+    if (d) *d = t->d;
+    if (n_attr) *n_attr = t->n_attr;
+    if (store) *store = t->store;
+    if (max_row_norm) *max_row_norm = t->max_norm;
+    return ok();
+}
+
+vrs_status vrs_table_export(vrs_table t, void *rows_out, float *scale_out, void *stream) {
+    if (!t) return fail(VRS_E_ARG, "table is NULL");
+    if (!rows_out) return fail(VRS_E_ARG, "rows_out is NULL");
+    if (t->store == VRS_FP8E4M3 && !scale_out) return fail(VRS_E_ARG, "scale_out is NULL for an FP8 table");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t eb = elem_bytes(t->store);
+    HIP_TRY(hipMemcpy2DAsync(rows_out, t->d * eb, t->rows, t->dp * eb, t->d * eb, t->n,
+                             hipMemcpyDeviceToDevice, s));
+    if (t->store == VRS_FP8E4M3)
+        HIP_TRY(hipMemcpyAsync(scale_out, t->scale, t->n * 4, hipMemcpyDeviceToDevice, s));
+    return ok();
+}
+
+vrs_status vrs_select_workspace_bytes(vrs_table t, size_t *bytes) {
+    if (!t || !bytes) return fail(VRS_E_ARG, "NULL argument");
+    int64_t nblk = (t->n + SEL_BLOCK_ROWS - 1) / SEL_BLOCK_ROWS;
+    *bytes = align256((t->n + 31) / 32 * 4) + align256(nblk * 4);
+    return ok();
+}
+
+vrs_status vrs_select(vrs_table t, const vrs_pred *pred, int32_t *ids_out, int64_t *count_out,
+                      void *ws, size_t ws_bytes, void *stream) {
+    if (!t) return fail(VRS_E_ARG, "table is NULL");
+    if (!ids_out || !count_out) return fail(VRS_E_ARG, "output is NULL");
+    size_t need;
+    vrs_select_workspace_bytes(t, &need);
+    if (!ws || ws_bytes < need) return fail(VRS_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    PredDev p;
+    vrs_status st = fold_pred(pred, t->n_attr, &p);
+    if (st != VRS_OK) return st;
+    uint32_t *bitmap = (uint32_t *)ws;
+    uint32_t *blk = (uint32_t *)((char *)ws + align256((t->n + 31) / 32 * 4));
+    HIP_TRY(launch_select(t->attr, t->n, p, bitmap, blk, ids_out, count_out, (hipStream_t)stream));
+    return ok();
+}
+
+int32_t vrs_num_tiles(void) { return planner_num_tiles(); }
+
+vrs_status vrs_profile(int32_t enable) {
+    prof_enable(enable != 0);
+    return ok();
+}
+
+vrs_status vrs_stage_times(double *ms, int64_t *calls) {
+    if (!ms || !calls) return fail(VRS_E_ARG, "NULL output");
+    hipError_t e = prof_collect(ms, calls);
+    if (e != hipSuccess) return fail(VRS_E_HIP, "stage timing failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+vrs_status vrs_chooser_load(const char *path) {
+    std::string err;
+    if (!chooser_load(path, &err)) return fail(VRS_E_ARG, "%s", err.c_str());
+    return ok();
+}
+
+vrs_status vrs_scan_workspace_bytes(vrs_table t, int32_t B, int32_t k_max, const vrs_opts *opts,
+                                    size_t *bytes) {
+    if (!t || !bytes) return fail(VRS_E_ARG, "NULL argument");
+    if (B < 1) return fail(VRS_E_ARG, "B=%d < 1", B);
+    if (k_max < 1 || k_max > 256) return fail(VRS_E_ARG, "k=%d outside [1, 256]", k_max);
+    *bytes = plan_workspace(t, B, k_max, opts);
+    return ok();
+}
+
+static vrs_status scan_common(vrs_table t, const float *q, int32_t B, const vrs_pred *pred,
+                              const vrs_pred *preds, const int32_t *ks, int32_t k,
+                              vrs_metric metric, int64_t *out_idx, float *out_dist, void *ws,
+                              size_t ws_bytes, const vrs_opts *opts, void *stream) {
+    if (!t) return fail(VRS_E_ARG, "table is NULL");
+    if (!q) return fail(VRS_E_ARG, "queries are NULL");
+    if (!out_idx || !out_dist) return fail(VRS_E_ARG, "outputs are NULL");
+    if (B < 1) return fail(VRS_E_ARG, "B=%d < 1", B);
+    if (k < 1 || k > 256) return fail(VRS_E_ARG, "k=%d outside [1, 256]", k);
+    if (metric != VRS_L2SQ && metric != VRS_IP) return fail(VRS_E_ARG, "unknown metric %d", (int)metric);
+    if (metric == VRS_L2SQ && t->store != VRS_F32)
+        return fail(VRS_E_UNSUPPORTED, "L2SQ needs a float32 table (bfloat16/FP8 tables support IP)");
+    if (opts && (opts->strategy < 0 || opts->strategy > 2))
+        return fail(VRS_E_ARG, "opts.strategy=%d outside [0, 2]", opts->strategy);
+    if (opts && (opts->tile < -1 || opts->tile >= planner_num_tiles()))
+        return fail(VRS_E_ARG, "opts.tile=%d outside [-1, %d)", opts->tile, planner_num_tiles());
+    if (opts && (opts->kprime_mult < 0 || opts->kprime_mult > 64))
+        return fail(VRS_E_ARG, "opts.kprime_mult=%d outside [0, 64]", opts->kprime_mult);
+    if (preds && !ks) return fail(VRS_E_ARG, "ks is NULL");
+    PredDev p;
+    if (!preds) {
+        vrs_status st = fold_pred(pred, t->n_attr, &p);
+        if (st != VRS_OK) return st;
+    } else {
+        fold_pred(nullptr, t->n_attr, &p);
+    }
+    size_t need = plan_workspace(t, B, k, opts);
+    if (!ws || ws_bytes < need)
+        return fail(VRS_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    if (((uintptr_t)ws & 255) != 0) return fail(VRS_E_WORKSPACE, "workspace not 256-byte aligned");
+    hipError_t e = run_scan(t, q, B, p, preds, ks, k, metric, out_idx, out_dist, ws, opts,
+                            (hipStream_t)stream);
+    if (e != hipSuccess) return fail(VRS_E_HIP, "scan launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+vrs_status vrs_scan_topk(vrs_table t, const float *q, int32_t B, const vrs_pred *pred, int32_t k,
+                         vrs_metric metric, int64_t *out_idx, float *out_dist, void *ws,
+                         size_t ws_bytes, const vrs_opts *opts, void *stream) {
+    return scan_common(t, q, B, pred, nullptr, nullptr, k, metric, out_idx, out_dist, ws, ws_bytes,
+                       opts, stream);
+}
+
+vrs_status vrs_scan_topk_batched(vrs_table t, const float *q, int32_t B, const vrs_pred *preds,
+                                 const int32_t *ks, int32_t k_max, vrs_metric metric,
+                                 int64_t *out_idx, float *out_dist, void *ws, size_t ws_bytes,
+                                 const vrs_opts *opts, void *stream) {
+    if (!preds) return fail(VRS_E_ARG, "preds is NULL");
+    return scan_common(t, q, B, nullptr, preds, ks, k_max, metric, out_idx, out_dist, ws, ws_bytes,
+                       opts, stream);
+}
+
+}  // extern "C"

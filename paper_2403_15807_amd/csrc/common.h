@@ -1,0 +1,190 @@
+// common.h -- device helpers shared by the gfx950 kernels of the filtered
+// top-k scan: sortable keys, storage decoders, the relational predicate and
+// the LDS top-k lists.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vrs {
+
+constexpr int WAVE = 64;
+constexpr uint64_t KEY_INF = ~0ull;
+
+// ---------------------------------------------------------------- keys
+// A candidate is the 64-bit key (order-preserving bits of the float32
+// screening distance) << 32 | row id, so that unsigned comparison orders by
+// (distance, id) -- ties go to the lower row id.  -0.0 is folded into +0.0
+// first, otherwise the bit trick would put -0 before +0.
+__device__ __forceinline__ uint32_t ord32(float f) {
+    f = (f == 0.0f) ? 0.0f : f;
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float unord32(uint32_t o) {
+    uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+    return __uint_as_float(u);
+}
+__device__ __forceinline__ uint64_t make_key(float d, uint32_t row) {
+    return ((uint64_t)ord32(d) << 32) | row;
+}
+__device__ __forceinline__ uint64_t ord64(double f) {
+    f = (f == 0.0) ? 0.0 : f;
+    uint64_t u = (uint64_t)__double_as_longlong(f);
+    return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double unord64(uint64_t o) {
+    uint64_t u = (o & 0x8000000000000000ull) ? (o & 0x7fffffffffffffffull) : ~o;
+    return __longlong_as_double((long long)u);
+}
+
+// Exact-distance key for the FP64 fallback: (ord64(dist64), row).
+struct Key128 {
+    uint64_t hi, lo;
+};
+
+template <typename K>
+struct KeyOps;
+template <>
+struct KeyOps<uint64_t> {
+    __device__ static uint64_t inf() { return KEY_INF; }
+    __device__ static bool less(uint64_t a, uint64_t b) { return a < b; }
+};
+template <>
+struct KeyOps<Key128> {
+    __device__ static Key128 inf() { return Key128{KEY_INF, KEY_INF}; }
+    __device__ static bool less(const Key128 &a, const Key128 &b) {
+        return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
+    }
+};
+
+// ---------------------------------------------------------------- decoders
+__device__ __forceinline__ float bf16_to_f32(uint32_t h16) { return __uint_as_float(h16 << 16); }
+
+// OCP e4m3fn -> float32, exact (every e4m3 value is a float32).
+__device__ __forceinline__ float e4m3_to_f32(uint32_t c) {
+    uint32_t s = (c & 0x80u) << 24, e = (c >> 3) & 15u, m = c & 7u;
+    float mag = (e == 0) ? (float)m * 0.001953125f /* 2^-9 */
+                         : __uint_as_float(((e + 120u) << 23) | (m << 20));
+    return __uint_as_float(__float_as_uint(mag) | s);
+}
+
+// ------------------------------------------------------------- predicate
+// Conjunction of inclusive int32 ranges (the host folds the ABI's int64
+// half-open bounds into these; an empty range is lo > hi; nterms < 0 means
+// the predicate selects nothing).
+struct PredDev {
+    int32_t nterms;
+    int32_t col[4];
+    int32_t lo[4];
+    int32_t hi[4];
+};
+
+__device__ __forceinline__ bool pred_eval(const PredDev &p, const int32_t *__restrict__ attr,
+                                          int64_t n, int64_t row) {
+    bool ok = p.nterms >= 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (t < p.nterms) {
+            int32_t a = attr[(int64_t)p.col[t] * n + row];
+            ok = ok && (a >= p.lo[t]) && (a <= p.hi[t]);
+        }
+    }
+    return ok;
+}
+
+// ------------------------------------------------------- LDS bitonic sort
+// Sort nseg independent segments of M keys (M a power of two) stored back
+// to back in LDS, ascending.  Every thread of the block must call it.
+template <typename K>
+__device__ void lds_bitonic_sort(K *a, int nseg, int M, int tid, int nthr) {
+    const int half = M >> 1;
+    const int lgh = __ffs(half) - 1;
+    const int total = nseg * half;
+    for (int size = 2; size <= M; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const int lgs = __ffs(stride) - 1;
+            for (int p = tid; p < total; p += nthr) {
+                int seg = p >> lgh, pi = p & (half - 1);
+                int i = ((pi >> lgs) << (lgs + 1)) + (pi & (stride - 1));
+                int j = i + stride;
+                bool up = (i & size) == 0;
+                K *s = a + (size_t)seg * M;
+                K x = s[i], y = s[j];
+                bool sw = up ? KeyOps<K>::less(y, x) : KeyOps<K>::less(x, y);
+                if (sw) {
+                    s[i] = y;
+                    s[j] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ------------------------------------------------------ LDS top-k lists
+// Per query: keys[0, Kp) is the current sorted list (only the first K are
+// kept), keys[Kp, Kp+CB) is an append buffer; thr = K-th smallest kept key
+// (KEY_INF while fewer than K are known).  A candidate is appended only when
+// it is below thr, so after the list fills up insertions become rare.
+template <typename K>
+struct TopkLds {
+    K *keys;      // [nq][Kp + CB]
+    int *cnt;     // [nq]
+    K *thr;       // [nq]
+    int nq, Kkeep, Kp, CB;
+
+    __device__ int M() const { return Kp + CB; }
+
+    __device__ void init(int tid, int nthr) {
+        for (int i = tid; i < nq * M(); i += nthr) keys[i] = KeyOps<K>::inf();
+        for (int b = tid; b < nq; b += nthr) {
+            cnt[b] = 0;
+            thr[b] = KeyOps<K>::inf();
+        }
+        __syncthreads();
+    }
+
+    // Called by one thread; the buffer must have room (see need_flush).
+    __device__ void push(int b, const K &key) {
+        if (KeyOps<K>::less(key, thr[b])) {
+            int s = atomicAdd(&cnt[b], 1);
+            keys[(size_t)b * M() + Kp + s] = key;
+        }
+    }
+
+    // Block-uniform: true if some buffer holds more than CB - room keys.
+    __device__ bool need_flush(int room) const {
+        bool f = false;
+        for (int b = 0; b < nq; ++b) f = f || (cnt[b] > CB - room);
+        return f;
+    }
+
+    // Merge every buffer into its list.  All threads must call it.
+    __device__ void flush(int tid, int nthr) {
+        for (int p = tid; p < nq * CB; p += nthr) {
+            int b = p / CB, i = p - b * CB;
+            if (i >= cnt[b]) keys[(size_t)b * M() + Kp + i] = KeyOps<K>::inf();
+        }
+        __syncthreads();
+        lds_bitonic_sort<K>(keys, nq, M(), tid, nthr);
+        for (int p = tid; p < nq * (Kp - Kkeep); p += nthr) {
+            int b = p / (Kp - Kkeep), i = p - b * (Kp - Kkeep);
+            keys[(size_t)b * M() + Kkeep + i] = KeyOps<K>::inf();
+        }
+        __syncthreads();
+        for (int b = tid; b < nq; b += nthr) {
+            thr[b] = keys[(size_t)b * M() + Kkeep - 1];
+            cnt[b] = 0;
+        }
+        __syncthreads();
+    }
+};
+
+__host__ __device__ inline int next_pow2(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+}  // namespace vrs

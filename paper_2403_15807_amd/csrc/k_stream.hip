@@ -1,0 +1,236 @@
+// k_stream.hip -- VALU screening kernel for small query batches (the 1:N
+// strategy of Section 3.1: one query against a batch of data vectors, with
+// the relational predicate either checked on the fly per row (mask) or
+// pushed down into a selection vector first (gather), eq. 3).
+//
+// A workgroup owns QT queries and one chunk of rows.  Rows stream from HBM
+// with 16-byte loads, 8 lanes per row, so every wave instruction reads eight
+// full 128-byte segments.  Each lane accumulates the FP32 distance of its
+// slice for every query of the tile; three xor-shuffles finish the row sums.
+// Candidates below the query's current threshold go to an LDS append buffer
+// that is merged into the query's sorted list when it fills (TopkLds).  The
+// chunk's K smallest keys are written out sorted for the cross-chunk merge.
+#include "internal.h"
+
+namespace vrs {
+
+namespace {
+
+constexpr int U = 2;                 // rows per lane-group per iteration
+constexpr int TILE = 4 * 8 * U;      // rows per workgroup iteration
+
+template <int STORE>
+struct Elem;
+template <>
+struct Elem<VRS_F32> {
+    static constexpr int V = 4;      // elements per 16-byte load
+    __device__ static void decode(const uint4 &w, float *x) {
+        x[0] = __uint_as_float(w.x);
+        x[1] = __uint_as_float(w.y);
+        x[2] = __uint_as_float(w.z);
+        x[3] = __uint_as_float(w.w);
+    }
+};
+template <>
+struct Elem<VRS_BF16> {
+    static constexpr int V = 8;
+    __device__ static void decode(const uint4 &w, float *x) {
+        const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            x[2 * i] = __uint_as_float(v[i] << 16);
+            x[2 * i + 1] = __uint_as_float(v[i] & 0xffff0000u);
+        }
+    }
+};
+template <>
+struct Elem<VRS_FP8E4M3> {
+    static constexpr int V = 16;
+    __device__ static void decode(const uint4 &w, float *x) {
+        const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) x[4 * i + j] = e4m3_to_f32((v[i] >> (8 * j)) & 0xffu);
+    }
+};
+
+template <int QT, int METRIC, int STORE, bool GATHER, bool BATCHED>
+__global__ __launch_bounds__(256) void screen_stream_kernel(ScreenArgs a) {
+    constexpr int V = Elem<STORE>::V;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane >> 3, s = lane & 7;
+    const int qt0 = blockIdx.y * QT;
+    const int chunk = blockIdx.x;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int M = a.Kp + a.CB;
+    uint64_t *keys = (uint64_t *)smem;
+    uint64_t *thr = keys + QT * M;
+    int *cnt = (int *)(thr + QT);
+    float *qs = (float *)(cnt + QT + 2);  // 8-byte aligned; [QT][dp]
+    qs = (float *)(((uintptr_t)qs + 15) & ~(uintptr_t)15);
+
+    TopkLds<uint64_t> tk{keys, cnt, thr, QT, a.K, a.Kp, a.CB};
+    for (int i = tid; i < QT * a.dp; i += 256) {
+        int b = i / a.dp, j = i - b * a.dp;
+        qs[i] = (qt0 + b < a.B) ? a.qp[(int64_t)(qt0 + b) * a.dp + j] : 0.0f;
+    }
+    tk.init(tid, 256);  // includes a barrier
+
+    PredDev qpred[QT];
+    if (BATCHED) {
+#pragma unroll
+        for (int b = 0; b < QT; ++b)
+            qpred[b] = (qt0 + b < a.B) ? a.preds[qt0 + b] : PredDev{0, {0}, {0}, {0}};
+    }
+
+    const int64_t total = GATHER ? *a.sel_count : a.n;
+    int64_t per = (total + a.n_chunks - 1) / a.n_chunks;
+    per = (per + TILE - 1) / TILE * TILE;
+    const int64_t c0 = (int64_t)chunk * per;
+    const int64_t c1 = min(total, c0 + per);
+    const int eb = (STORE == VRS_F32) ? 4 : (STORE == VRS_BF16 ? 2 : 1);
+    const int64_t row_bytes = (int64_t)a.dp * eb;
+    const int nblk = (int)(row_bytes / 128);   // 128-byte column blocks per row
+    const char *base = (const char *)a.rows;
+
+    for (int64_t t0 = c0; t0 < c1; t0 += TILE) {
+        int64_t row[U];
+        bool qual[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int64_t pos = t0 + u * 32 + wave * 8 + r;
+            bool valid = pos < c1;
+            row[u] = GATHER ? (valid ? (int64_t)a.sel_ids[pos] : 0) : pos;
+            qual[u] = valid && (GATHER || BATCHED || pred_eval(a.pred, a.attr, a.n, row[u]));
+        }
+        bool any = false;
+#pragma unroll
+        for (int u = 0; u < U; ++u) any = any || qual[u];
+        if (__ballot(any) != 0) {
+            float acc[U][QT];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int b = 0; b < QT; ++b) acc[u][b] = 0.0f;
+            for (int cb = 0; cb < nblk; ++cb) {
+                uint4 w[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (qual[u])
+                        w[u] = *(const uint4 *)(base + row[u] * row_bytes + cb * 128 + s * 16);
+                    else
+                        w[u] = make_uint4(0, 0, 0, 0);
+                }
+                const int e0 = (cb * 128 + s * 16) / eb;  // first element of this lane's slice
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    float x[V];
+                    Elem<STORE>::decode(w[u], x);
+#pragma unroll
+                    for (int b = 0; b < QT; ++b) {
+                        const float *qb = qs + b * a.dp + e0;
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            if (METRIC == VRS_L2SQ) {
+                                float t = qb[v] - x[v];
+                                acc[u][b] = fmaf(t, t, acc[u][b]);
+                            } else {
+                                acc[u][b] = fmaf(qb[v], x[v], acc[u][b]);
+                            }
+                        }
+                    }
+                }
+            }
+            // finish the row sums across the 8 lanes of each row
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int b = 0; b < QT; ++b) {
+                    float v = acc[u][b];
+                    v += __shfl_xor(v, 1);
+                    v += __shfl_xor(v, 2);
+                    v += __shfl_xor(v, 4);
+                    acc[u][b] = v;
+                }
+            // lane s of each row pushes query s
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                float mine = 0.0f;
+#pragma unroll
+                for (int b = 0; b < QT; ++b)
+                    if (b == s) mine = acc[u][b];
+                bool ok = qual[u] && s < QT && qt0 + s < a.B;
+                if (BATCHED && ok) {
+#pragma unroll
+                    for (int b = 0; b < QT; ++b)
+                        if (b == s) ok = pred_eval(qpred[b], a.attr, a.n, row[u]);
+                }
+                if (ok) {
+                    float dist;
+                    if (METRIC == VRS_L2SQ)
+                        dist = mine;
+                    else if (STORE == VRS_FP8E4M3)
+                        dist = -(a.scale[row[u]] * mine);
+                    else
+                        dist = -mine;
+                    tk.push(s, make_key(dist, (uint32_t)row[u]));
+                }
+            }
+        }
+        __syncthreads();
+        if (tk.need_flush(TILE)) tk.flush(tid, 256);
+    }
+    if (tk.need_flush(a.CB)) tk.flush(tid, 256);  // any pending candidate
+    for (int i = tid; i < QT * a.K; i += 256) {
+        int b = i / a.K, j = i - b * a.K;
+        if (qt0 + b < a.B)
+            a.partials[((int64_t)(qt0 + b) * a.n_chunks + chunk) * a.K + j] = keys[b * M + j];
+    }
+}
+
+template <int QT, int METRIC, int STORE>
+hipError_t launch_q(const ScreenArgs &a, hipStream_t s) {
+    dim3 grid(a.n_chunks, (a.B + QT - 1) / QT), block(256);
+    size_t lds = screen_stream_lds(QT, a.Kp, a.CB, a.dp);
+    if (a.preds) {
+        if (a.gather) return hipErrorInvalidValue;
+        screen_stream_kernel<QT, METRIC, STORE, false, true><<<grid, block, lds, s>>>(a);
+    } else if (a.gather) {
+        screen_stream_kernel<QT, METRIC, STORE, true, false><<<grid, block, lds, s>>>(a);
+    } else {
+        screen_stream_kernel<QT, METRIC, STORE, false, false><<<grid, block, lds, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+template <int QT>
+hipError_t launch_qt(const ScreenArgs &a, hipStream_t s) {
+    if (a.metric == VRS_L2SQ) {
+        if (a.store != VRS_F32) return hipErrorInvalidValue;
+        return launch_q<QT, VRS_L2SQ, VRS_F32>(a, s);
+    }
+    switch (a.store) {
+    case VRS_F32: return launch_q<QT, VRS_IP, VRS_F32>(a, s);
+    case VRS_BF16: return launch_q<QT, VRS_IP, VRS_BF16>(a, s);
+    default: return launch_q<QT, VRS_IP, VRS_FP8E4M3>(a, s);
+    }
+}
+
+}  // namespace
+
+size_t screen_stream_lds(int qt, int Kp, int CB, int dp) {
+    return (size_t)qt * (Kp + CB) * 8 + qt * 8 + (qt + 2) * 4 + 16 + (size_t)qt * dp * 4;
+}
+
+hipError_t launch_screen_stream(const ScreenArgs &a, int qt, hipStream_t s) {
+    switch (qt) {
+    case 1: return launch_qt<1>(a, s);
+    case 2: return launch_qt<2>(a, s);
+    case 4: return launch_qt<4>(a, s);
+    default: return launch_qt<8>(a, s);
+    }
+}
+
+}  // namespace vrs

@@ -1,0 +1,308 @@
+// planner.cpp -- workspace layout, access-path choice and the launch
+// sequence of one scan (see api.cpp for the ABI checks around it).
+#include "planner.h"
+
+#include <math.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+namespace vrs {
+
+namespace {
+
+const TileCfg kTiles[] = {
+    {0, 1, 2048},
+    {0, 2, 2048},
+    {0, 4, 2048},
+    {0, 8, 2048},
+};
+constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+constexpr size_t LDS_BUDGET = 64 * 1024;  // several workgroups per CU
+
+size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+double gamma_n(double n, double u) { return n * u / (1.0 - n * u); }
+
+int screen_cb(int Kp) { return next_pow2(std::max(2 * Kp, Kp + 256)) - Kp; }
+
+// Largest tile-compatible query count per workgroup that fits the LDS budget.
+int fit_qt(int qt, int Kp, int CB, int dp) {
+    while (qt > 1 && screen_stream_lds(qt, Kp, CB, dp) > LDS_BUDGET) qt >>= 1;
+    return qt;
+}
+
+Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int tile,
+               int strategy) {
+    Plan P{};
+    P.strategy = strategy;
+    P.tile = tile;
+    const int kmult = opts ? opts->kprime_mult : 0;
+    P.kprime = kprime_rule(kmax, t->store, kmult);
+    P.K = P.kprime + 1;
+    P.Kp = next_pow2(P.K);
+    P.CB = screen_cb(P.Kp);
+    const TileCfg &cfg = kTiles[tile];
+    P.qt = fit_qt(std::min(cfg.qt, next_pow2(B)), P.Kp, P.CB, t->dp);
+    P.n_qtiles = (B + P.qt - 1) / P.qt;
+    int64_t max_chunks = std::max<int64_t>(1, (t->n + 1023) / 1024);
+    P.n_chunks = (int)std::max<int64_t>(1, std::min<int64_t>(max_chunks, cfg.wg_target / P.n_qtiles));
+    // exact fallback: about 64K rows per task, bounded scratch
+    const size_t fb_cap = (size_t)256 << 20;
+    int64_t want = std::max<int64_t>(1, (t->n + 65535) / 65536);
+    int64_t cap = std::max<int64_t>(1, (int64_t)(fb_cap / ((size_t)B * kmax * 16)));
+    P.fb_chunks = (int)std::min(want, cap);
+    P.fb_rows_per_chunk = (int)((t->n + P.fb_chunks - 1) / P.fb_chunks);
+    // workspace layout
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += a256(bytes);
+        return r;
+    };
+    P.o_qp = take((size_t)B * t->dp * 4);
+    P.o_qnorm = take((size_t)B * 8);
+    P.o_bitmap = take((size_t)(t->n + 31) / 32 * 4);
+    P.o_blk = take((size_t)((t->n + SEL_BLOCK_ROWS - 1) / SEL_BLOCK_ROWS) * 4);
+    P.o_sel = take((size_t)t->n * 4);
+    P.o_selcnt = take(8);
+    P.o_part = take((size_t)B * P.n_chunks * P.K * 8);
+    P.o_mid = take((size_t)B * ((P.n_chunks + 31) / 32) * P.K * 8);
+    P.o_merged = take((size_t)B * P.K * 8);
+    P.o_fail = take((size_t)B * 4);
+    P.o_failcnt = take(8);
+    P.o_fb = take((size_t)B * P.fb_chunks * kmax * 16);
+    P.o_preds = take((size_t)B * sizeof(PredDev));
+    P.o_kc = take((size_t)B * 4);
+    P.o_kps = take((size_t)B * 4);
+    P.total = o;
+    return P;
+}
+
+int default_tile(int B) {
+    if (B <= 1) return 0;
+    if (B <= 2) return 1;
+    if (B <= 4) return 2;
+    return 3;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ stage timing
+namespace {
+struct ProfRec {
+    int stage;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_recs;
+std::vector<hipEvent_t> g_prof_pool;
+hipEvent_t g_prof_open[VRS_NUM_STAGES];
+
+hipEvent_t prof_event() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+void prof_begin(int stage, hipStream_t s) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (!g_prof_on) return;
+    hipEvent_t e = prof_event();
+    if (e && hipEventRecord(e, s) == hipSuccess) g_prof_open[stage] = e;
+}
+
+void prof_end(int stage, hipStream_t s) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (!g_prof_on || !g_prof_open[stage]) return;
+    hipEvent_t e = prof_event();
+    if (e && hipEventRecord(e, s) == hipSuccess) g_prof_recs.push_back({stage, g_prof_open[stage], e});
+    g_prof_open[stage] = nullptr;
+}
+
+void prof_enable(bool on) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_on = on;
+}
+
+hipError_t prof_collect(double *ms, int64_t *calls) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (int i = 0; i < VRS_NUM_STAGES; ++i) {
+        ms[i] = 0.0;
+        calls[i] = 0;
+    }
+    hipError_t err = hipSuccess;
+    for (auto &r : g_prof_recs) {
+        float t = 0.0f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+        if (e != hipSuccess) err = e;
+        ms[r.stage] += t;
+        calls[r.stage] += 1;
+        g_prof_pool.push_back(r.a);
+        g_prof_pool.push_back(r.b);
+    }
+    g_prof_recs.clear();
+    return err;
+}
+
+int planner_num_tiles() { return kNumTiles; }
+const TileCfg &planner_tile(int id) { return kTiles[id]; }
+
+int kprime_rule(int k, vrs_dtype store, int kmult) {
+    int kp;
+    if (kmult > 0)
+        kp = k * kmult;
+    else if (store == VRS_F32)
+        kp = std::max(2 * k, k + 32);
+    else
+        kp = 4 * k;
+    return std::min(std::max(kp, k), 1024);
+}
+
+size_t plan_workspace(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts) {
+    size_t m = 0;
+    for (int tile = 0; tile < kNumTiles; ++tile)
+        m = std::max(m, make_plan(t, B, kmax, opts, tile, VRS_STRATEGY_GATHER).total);
+    return m;
+}
+
+hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &p,
+                    const vrs_pred *preds, const int32_t *ks, int k, vrs_metric metric,
+                    int64_t *out_idx, float *out_dist, void *ws, const vrs_opts *opts,
+                    hipStream_t s) {
+    const bool batched = preds != nullptr;
+    int tile = (opts && opts->tile >= 0) ? opts->tile : default_tile(B);
+    int strategy = opts ? opts->strategy : VRS_STRATEGY_AUTO;
+    if (batched) strategy = VRS_STRATEGY_MASK;  // per-query predicates are checked per row
+    if (strategy == VRS_STRATEGY_AUTO) {
+        double sel = estimate_selectivity(t, p);
+        strategy = sel < 0.5 ? VRS_STRATEGY_GATHER : VRS_STRATEGY_MASK;
+        if (p.nterms == 0) strategy = VRS_STRATEGY_MASK;
+    }
+    Plan P = make_plan(t, B, k, opts, tile, strategy);
+    char *w = (char *)ws;
+    float *qp = (float *)(w + P.o_qp);
+    double *qnorm = (double *)(w + P.o_qnorm);
+    int32_t *fail_count = (int32_t *)(w + P.o_failcnt);
+    prof_begin(0, s);
+    hipError_t e = launch_prep_queries(q, B, t->d, t->dp, qp, qnorm, fail_count, s);
+    if (e != hipSuccess) return e;
+    PredDev *pdev = (PredDev *)(w + P.o_preds);
+    int32_t *kc = (int32_t *)(w + P.o_kc), *kps = (int32_t *)(w + P.o_kps);
+    if (batched) {
+        e = launch_prep_batched(preds, ks, B, k, t->n_attr, opts ? opts->kprime_mult : 0,
+                                t->store == VRS_F32, pdev, kc, kps, s);
+        if (e != hipSuccess) return e;
+    }
+    prof_end(0, s);
+    const bool gather = strategy == VRS_STRATEGY_GATHER;
+    int32_t *sel = (int32_t *)(w + P.o_sel);
+    int64_t *selcnt = (int64_t *)(w + P.o_selcnt);
+    if (gather) {
+        prof_begin(1, s);
+        e = launch_select(t->attr, t->n, p, (uint32_t *)(w + P.o_bitmap), (uint32_t *)(w + P.o_blk),
+                          sel, selcnt, s);
+        if (e != hipSuccess) return e;
+        prof_end(1, s);
+    }
+    ScreenArgs sa{};
+    sa.rows = t->rows;
+    sa.scale = t->scale;
+    sa.n = t->n;
+    sa.dp = t->dp;
+    sa.store = t->store;
+    sa.attr = t->attr;
+    sa.pred = p;
+    sa.preds = batched ? pdev : nullptr;
+    sa.sel_ids = sel;
+    sa.sel_count = selcnt;
+    sa.gather = gather;
+    sa.qp = qp;
+    sa.B = B;
+    sa.metric = metric;
+    sa.K = P.K;
+    sa.Kp = P.Kp;
+    sa.CB = P.CB;
+    sa.n_chunks = P.n_chunks;
+    sa.partials = (uint64_t *)(w + P.o_part);
+    prof_begin(2, s);
+    e = launch_screen_stream(sa, P.qt, s);
+    if (e != hipSuccess) return e;
+    prof_end(2, s);
+
+    FinishArgs fa{};
+    fa.rows = t->rows;
+    fa.scale = t->scale;
+    fa.n = t->n;
+    fa.d = t->d;
+    fa.dp = t->dp;
+    fa.store = t->store;
+    fa.attr = t->attr;
+    fa.pred = p;
+    fa.preds = batched ? pdev : nullptr;
+    fa.q = q;
+    fa.qnorm = qnorm;
+    fa.B = B;
+    fa.metric = metric;
+    fa.k = k;
+    fa.ks = batched ? kc : nullptr;
+    fa.kmax = k;
+    fa.kprime = P.kprime;
+    fa.kps = batched ? kps : nullptr;
+    fa.K = P.K;
+    fa.n_chunks = P.n_chunks;
+    fa.partials = sa.partials;
+    fa.merge_mid = (uint64_t *)(w + P.o_mid);
+    fa.merged = (uint64_t *)(w + P.o_merged);
+    // Screening error bound (VALU kernel, FP32 accumulation in any order):
+    //   L2SQ: sum of dp non-negative rounded terms -> relative gamma_{dp+3};
+    //   IP:   |error| <= gamma_{dp+3} * ||q|| * max_i ||x_i||.
+    // Both sides of the certificate also carry the FP64 sum's own error.
+    const double u32 = ldexp(1.0, -24), u64 = ldexp(1.0, -53);
+    const double g = (gamma_n(t->dp + 3, u32) + gamma_n(t->dp + 3, u64)) * 1.001;
+    fa.rel = metric == VRS_L2SQ ? g : 0.0;
+    fa.abs_ip = metric == VRS_IP ? g : 0.0;
+    fa.abs_l2 = 0.0;
+    fa.max_norm = t->max_norm;
+    fa.fail_list = (int32_t *)(w + P.o_fail);
+    fa.fail_count = fail_count;
+    fa.out_idx = out_idx;
+    fa.out_dist = out_dist;
+    fa.n_valid = opts ? opts->n_valid : nullptr;
+    fa.certified = opts ? opts->certified : nullptr;
+    fa.fb_rows_per_chunk = P.fb_rows_per_chunk;
+    fa.fb_chunks = P.fb_chunks;
+    fa.fb_slots = B;
+    fa.fb_partials = (uint64_t *)(w + P.o_fb);
+    prof_begin(3, s);
+    e = launch_merge(fa, s);
+    if (e != hipSuccess) return e;
+    prof_end(3, s);
+    prof_begin(4, s);
+    e = launch_rerank(fa, s);
+    if (e != hipSuccess) return e;
+    prof_end(4, s);
+    prof_begin(5, s);
+    e = launch_fallback(fa, s);
+    prof_end(5, s);
+    return e;
+}
+
+// ------------------------------------------------------------- chooser stub
+bool chooser_load(const char *path, std::string *err) {
+    *err = std::string("chooser weights not supported yet: ") + (path ? path : "(null)");
+    return false;
+}
+bool chooser_ready() { return false; }
+int chooser_pick(const float *, const bool *, int) { return -1; }
+
+}  // namespace vrs

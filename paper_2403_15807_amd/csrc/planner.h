@@ -1,0 +1,58 @@
+// planner.h -- access-path planning for one scan call: strategy (mask vs
+// gather, eq. 3), kernel configuration ("tile"), list sizes, workspace
+// layout, and the launch sequence.
+#pragma once
+
+#include <string>
+
+#include "internal.h"
+
+namespace vrs {
+
+// Kernel configurations the planner and the chooser pick from.
+struct TileCfg {
+    int kind;       // 0 = VALU streaming kernel, 1 = MFMA kernel
+    int qt;         // queries per workgroup
+    int wg_target;  // workgroups to aim for (fills 256 CUs several times)
+};
+int planner_num_tiles();
+const TileCfg &planner_tile(int id);
+
+// k' = screening survivors per query.
+int kprime_rule(int k, vrs_dtype store, int kmult);
+
+struct Plan {
+    int strategy;        // VRS_STRATEGY_MASK or VRS_STRATEGY_GATHER
+    int tile;            // index into the tile table
+    int qt, n_qtiles, n_chunks;
+    int kprime, K, Kp, CB;
+    int fb_chunks, fb_rows_per_chunk;
+    // workspace offsets (bytes)
+    size_t o_qp, o_qnorm, o_bitmap, o_blk, o_sel, o_selcnt, o_part, o_mid, o_merged, o_fail,
+        o_failcnt, o_fb, o_preds, o_kc, o_kps, total;
+};
+
+double estimate_selectivity(const vrs_table_s *t, const PredDev &p);
+
+// Workspace bytes covering every plan the planner may pick for (B, k_max, opts).
+size_t plan_workspace(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts);
+
+hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &p,
+                    const vrs_pred *preds, const int32_t *ks, int k, vrs_metric metric,
+                    int64_t *out_idx, float *out_dist, void *ws, const vrs_opts *opts,
+                    hipStream_t s);
+
+// Stage timing (vrs_profile / vrs_stage_times).
+void prof_begin(int stage, hipStream_t s);
+void prof_end(int stage, hipStream_t s);
+void prof_enable(bool on);
+hipError_t prof_collect(double *ms, int64_t *calls);
+
+// Learned chooser (host inference of the MLP; see chooser.cpp).
+bool chooser_load(const char *path, std::string *err);
+bool chooser_ready();
+// Returns the arm index (strategy * num_tiles + tile) with the lowest
+// predicted time among the allowed arms, or -1.
+int chooser_pick(const float feats[6], const bool *allowed, int n_arms);
+
+}  // namespace vrs

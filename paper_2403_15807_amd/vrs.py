@@ -1,0 +1,273 @@
+"""ctypes binding of ``libvrs.so`` (include/vrs.h), same names as the C ABI.
+
+Argument marshalling only: every step of a scan runs in the library's gfx950
+kernels.  PyTorch supplies device memory (queries, outputs, workspace through
+its caching allocator) and the HIP stream.  There is no CPU fallback: if the
+library is missing or no GPU is visible, calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvrs.so")
+
+VRS_OK, VRS_E_ARG, VRS_E_NONFINITE, VRS_E_NOMEM, VRS_E_UNSUPPORTED, VRS_E_HIP, VRS_E_WORKSPACE = range(7)
+L2SQ, IP = 0, 1
+F32, BF16, FP8E4M3 = 0, 1, 2
+STRATEGY_AUTO, STRATEGY_MASK, STRATEGY_GATHER = 0, 1, 2
+CHOOSER_LEARNED, CHOOSER_HEURISTIC = 0, 1
+MAX_TERMS = 4
+
+EXPORTS = [
+    "vrs_build_table", "vrs_destroy_table", "vrs_table_info", "vrs_table_export",
+    "vrs_scan_workspace_bytes", "vrs_select_workspace_bytes", "vrs_select", "vrs_scan_topk",
+    "vrs_scan_topk_batched", "vrs_num_tiles", "vrs_chooser_load", "vrs_last_error",
+    "vrs_profile", "vrs_stage_times",
+]
+NUM_STAGES = 6
+STAGES = ["prep", "select", "screen", "merge", "rerank", "fallback"]
+
+
+class VrsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"vrs status {status}: {msg}")
+        self.status = status
+
+
+class vrs_range(C.Structure):
+    _fields_ = [("col", C.c_int32), ("_pad", C.c_int32), ("lo", C.c_int64), ("hi", C.c_int64)]
+
+
+class vrs_pred(C.Structure):
+    _fields_ = [("nterms", C.c_int32), ("_pad", C.c_int32), ("term", vrs_range * MAX_TERMS)]
+
+
+class vrs_opts(C.Structure):
+    _fields_ = [("strategy", C.c_int32), ("tile", C.c_int32), ("chooser", C.c_int32),
+                ("kprime_mult", C.c_int32), ("n_valid", C.c_void_p), ("certified", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libvrs.so (built by ``paper_2403_15807_amd._build.build()``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, S = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        sig = {
+            "vrs_build_table": [P, I64, I32, P, I32, I32, I32, P, P],
+            "vrs_destroy_table": [P],
+            "vrs_table_info": [P, P, P, P, P, P],
+            "vrs_table_export": [P, P, P, P],
+            "vrs_scan_workspace_bytes": [P, I32, I32, P, P],
+            "vrs_select_workspace_bytes": [P, P],
+            "vrs_select": [P, P, P, P, P, S, P],
+            "vrs_scan_topk": [P, P, I32, P, I32, I32, P, P, P, S, P, P],
+            "vrs_scan_topk_batched": [P, P, I32, P, P, I32, I32, P, P, P, S, P, P],
+            "vrs_num_tiles": [],
+            "vrs_chooser_load": [C.c_char_p],
+            "vrs_last_error": [],
+            "vrs_profile": [I32],
+            "vrs_stage_times": [P, P],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int32
+        L.vrs_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != VRS_OK:
+        raise VrsError(st, lib().vrs_last_error().decode())
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(stream=None) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def make_pred(terms) -> vrs_pred:
+    """``terms``: iterable of ``(col, lo, hi)`` meaning ``lo <= A[col][i] < hi``."""
+    terms = list(terms or [])
+    if len(terms) > MAX_TERMS:
+        raise ValueError(f"at most {MAX_TERMS} terms")
+    p = vrs_pred()
+    p.nterms = len(terms)
+    for i, (c, lo, hi) in enumerate(terms):
+        p.term[i].col, p.term[i].lo, p.term[i].hi = int(c), int(lo), int(hi)
+    return p
+
+
+def preds_tensor(pred_list, device="cuda") -> torch.Tensor:
+    """Pack a list of predicates into a device byte tensor of ``vrs_pred``."""
+    n = len(pred_list)
+    buf = (vrs_pred * max(n, 1))()
+    for i, terms in enumerate(pred_list):
+        buf[i] = make_pred(terms)
+    raw = bytes(C.string_at(C.addressof(buf), C.sizeof(vrs_pred) * n))
+    return torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+
+
+@dataclass
+class ScanResult:
+    idx: torch.Tensor
+    dist: torch.Tensor
+    n_valid: torch.Tensor
+    certified: torch.Tensor
+
+
+class Table:
+    """A library-owned table (``vrs_build_table``)."""
+
+    def __init__(self, vec: torch.Tensor, attr: torch.Tensor | None = None, store: int = F32,
+                 normalize: bool = False, stream=None):
+        if not (vec.is_cuda and vec.dtype == torch.float32 and vec.dim() == 2):
+            raise ValueError("vec must be a float32 [n, d] CUDA tensor")
+        vec = vec.contiguous()
+        n, d = vec.shape
+        if attr is not None:
+            if attr.dim() == 1:
+                attr = attr[None, :]
+            if not (attr.is_cuda and attr.dtype == torch.int32 and attr.shape[1] == n):
+                raise ValueError("attr must be an int32 [n_attr, n] CUDA tensor")
+            attr = attr.contiguous()
+        n_attr = 0 if attr is None else attr.shape[0]
+        h = C.c_void_p()
+        _check(lib().vrs_build_table(_ptr(vec), n, d, _ptr(attr), n_attr, int(store),
+                                     int(bool(normalize)), _stream(stream), C.byref(h)))
+        self._h = h
+        self.n, self.d, self.n_attr, self.store = n, d, n_attr, int(store)
+        mx = C.c_double()
+        _check(lib().vrs_table_info(h, None, None, None, None, C.byref(mx)))
+        self.max_norm = mx.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().vrs_destroy_table(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().vrs_destroy_table(self._h)
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- helpers
+    def export(self, stream=None):
+        dt = {F32: torch.float32, BF16: torch.int16, FP8E4M3: torch.uint8}[self.store]
+        rows = torch.empty((self.n, self.d), dtype=dt, device="cuda")
+        scale = torch.empty(self.n, dtype=torch.float32, device="cuda") if self.store == FP8E4M3 else None
+        _check(lib().vrs_table_export(self._h, _ptr(rows), _ptr(scale), _stream(stream)))
+        return rows, scale
+
+    def workspace_bytes(self, B: int, k_max: int, opts: vrs_opts | None = None) -> int:
+        out = C.c_size_t()
+        _check(lib().vrs_scan_workspace_bytes(self._h, B, k_max, None if opts is None else C.byref(opts),
+                                              C.byref(out)))
+        return out.value
+
+    def workspace(self, B: int, k_max: int, opts: vrs_opts | None = None) -> torch.Tensor:
+        return torch.empty(max(self.workspace_bytes(B, k_max, opts), 256), dtype=torch.uint8, device="cuda")
+
+    def select(self, terms, stream=None):
+        nb = C.c_size_t()
+        _check(lib().vrs_select_workspace_bytes(self._h, C.byref(nb)))
+        ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device="cuda")
+        ids = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        p = make_pred(terms)
+        _check(lib().vrs_select(self._h, C.byref(p), _ptr(ids), _ptr(cnt), _ptr(ws), ws.numel(),
+                                _stream(stream)))
+        return ids[: int(cnt.item())]
+
+    def _opts(self, B, strategy, tile, chooser, kprime_mult, n_valid, certified):
+        o = vrs_opts()
+        o.strategy, o.tile, o.chooser, o.kprime_mult = strategy, tile, chooser, kprime_mult
+        o.n_valid = n_valid.data_ptr()
+        o.certified = certified.data_ptr()
+        return o
+
+    def scan_topk(self, q: torch.Tensor, terms, k: int, metric: int = L2SQ, strategy: int = STRATEGY_AUTO,
+                  tile: int = -1, chooser: int = CHOOSER_LEARNED, kprime_mult: int = 0,
+                  ws: torch.Tensor | None = None, out: tuple | None = None, stream=None) -> ScanResult:
+        """Filtered exact top-k of the queries ``q`` [B, d] (one predicate)."""
+        q = q.contiguous()
+        B = q.shape[0]
+        if out is None:
+            idx = torch.empty((B, k), dtype=torch.int64, device="cuda")
+            dist = torch.empty((B, k), dtype=torch.float32, device="cuda")
+            nv = torch.empty(B, dtype=torch.int32, device="cuda")
+            cert = torch.empty(B, dtype=torch.uint8, device="cuda")
+        else:
+            idx, dist, nv, cert = out
+        o = self._opts(B, strategy, tile, chooser, kprime_mult, nv, cert)
+        if ws is None:
+            ws = self.workspace(B, k, o)
+        p = make_pred(terms)
+        _check(lib().vrs_scan_topk(self._h, _ptr(q), B, C.byref(p), k, metric, _ptr(idx), _ptr(dist),
+                                   _ptr(ws), ws.numel(), C.byref(o), _stream(stream)))
+        return ScanResult(idx, dist, nv, cert)
+
+    def scan_topk_batched(self, q: torch.Tensor, preds: torch.Tensor, ks: torch.Tensor, k_max: int,
+                          metric: int = IP, tile: int = -1, kprime_mult: int = 0,
+                          ws: torch.Tensor | None = None, out: tuple | None = None,
+                          stream=None) -> ScanResult:
+        """Per-query predicates (``preds_tensor``) and k (int32 device tensor)."""
+        q = q.contiguous()
+        B = q.shape[0]
+        if out is None:
+            idx = torch.empty((B, k_max), dtype=torch.int64, device="cuda")
+            dist = torch.empty((B, k_max), dtype=torch.float32, device="cuda")
+            nv = torch.empty(B, dtype=torch.int32, device="cuda")
+            cert = torch.empty(B, dtype=torch.uint8, device="cuda")
+        else:
+            idx, dist, nv, cert = out
+        o = self._opts(B, STRATEGY_MASK, tile, CHOOSER_HEURISTIC, kprime_mult, nv, cert)
+        if ws is None:
+            ws = self.workspace(B, k_max, o)
+        _check(lib().vrs_scan_topk_batched(self._h, _ptr(q), B, _ptr(preds), _ptr(ks), k_max, metric,
+                                           _ptr(idx), _ptr(dist), _ptr(ws), ws.numel(), C.byref(o),
+                                           _stream(stream)))
+        return ScanResult(idx, dist, nv, cert)
+
+
+def profile(enable: bool):
+    _check(lib().vrs_profile(int(bool(enable))))
+
+
+def stage_times():
+    """Accumulated (ms, calls) per stage since the last read."""
+    ms = (C.c_double * NUM_STAGES)()
+    calls = (C.c_int64 * NUM_STAGES)()
+    _check(lib().vrs_stage_times(ms, calls))
+    return {STAGES[i]: (ms[i], calls[i]) for i in range(NUM_STAGES)}
+
+
+def num_tiles() -> int:
+    return int(lib().vrs_num_tiles())
+
+
+def chooser_load(path: str) -> bool:
+    return lib().vrs_chooser_load(path.encode()) == VRS_OK

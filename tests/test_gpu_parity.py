@@ -1,0 +1,242 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.  Ids must match exactly; distances within 1e-5 relative
+(the returned float is the FP64 distance rounded, so it is in fact expected
+to match bit for bit, which is checked too)."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2403_15807_amd import inputs, vrs
+
+pytestmark = pytest.mark.gpu
+
+I32_MIN = -(2 ** 31)
+RTOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _ready(oracle_lib):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return oracle_lib
+
+
+def _check(res, ref, what=""):
+    gi, gd = res.idx.cpu().numpy(), res.dist.cpu().numpy()
+    ri, rd = ref[0], ref[1]
+    assert gi.shape == ri.shape, what
+    bad = np.nonzero((gi != ri).any(axis=1))[0]
+    assert bad.size == 0, f"{what}: id mismatch in queries {bad[:8]}: gpu {gi[bad[0]][:12]} oracle {ri[bad[0]][:12]}"
+    fin = np.isfinite(rd)
+    assert np.array_equal(np.isfinite(gd), fin), what
+    rel = np.abs(gd[fin].astype(np.float64) - rd[fin]) / np.maximum(np.abs(rd[fin]), 1e-30)
+    assert (rel <= RTOL).all() or rd[fin].size == 0, f"{what}: max rel {rel.max()}"
+    zero = rd[fin] == 0
+    assert np.all(gd[fin][zero] == 0)
+    assert np.array_equal(gd, rd), f"{what}: distances not bit-identical"
+    nv = res.n_valid.cpu().numpy()
+    assert np.array_equal(nv, ref[3]), what
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+# ------------------------------------------------------------------ build
+@pytest.mark.parametrize("store", [vrs.F32, vrs.BF16, vrs.FP8E4M3])
+@pytest.mark.parametrize("normalize", [False, True])
+def test_build_table_bit_exact(store, normalize):
+    rng = np.random.default_rng(1)
+    n, d = 3001, 100
+    x = (rng.standard_normal((n, d)) * rng.uniform(0.01, 30, (n, 1))).astype(np.float32)
+    x[5] = 0.0
+    x[6, :7] = [1e-30, -1e-30, 3e-39, -0.0, 448.0, 1e-8, -5e-9]
+    a = rng.integers(0, 10, (1, n)).astype(np.int32)
+    T = vrs.Table(_dev(x), _dev(a), store=store, normalize=normalize)
+    rows, scale = T.export()
+    torch.cuda.synchronize()
+    ot = O.Table.build(x, a, {vrs.F32: O.F32, vrs.BF16: O.BF16, vrs.FP8E4M3: O.FP8}[store], normalize)
+    got = rows.cpu().numpy()
+    if store == vrs.F32:
+        assert np.array_equal(got.view(np.uint32), ot.rows.view(np.uint32))
+    elif store == vrs.BF16:
+        assert np.array_equal(got.view(np.uint16), ot.rows)
+    else:
+        assert np.array_equal(got, ot.rows)
+        assert np.array_equal(scale.cpu().numpy().view(np.uint32), ot.scale.view(np.uint32))
+    T.close()
+
+
+def test_build_rejects_nonfinite():
+    x = np.ones((100, 8), np.float32)
+    x[3, 2] = np.nan
+    with pytest.raises(vrs.VrsError) as e:
+        vrs.Table(_dev(x), None)
+    assert e.value.status == vrs.VRS_E_NONFINITE
+    x[3, 2] = 3.4e38  # finite in float32, rounds past the largest bfloat16
+    vrs.Table(_dev(x), None).close()
+    with pytest.raises(vrs.VrsError) as e:
+        vrs.Table(_dev(x), None, store=vrs.BF16)
+    assert e.value.status == vrs.VRS_E_NONFINITE
+
+
+# -------------------------------------------------------------- predicate
+def test_select_matches_oracle():
+    rng = np.random.default_rng(2)
+    n = 70001  # several selection blocks and a ragged tail
+    a = np.stack([rng.integers(0, 100, n), rng.integers(-5, 5, n)]).astype(np.int32)
+    a[1, :3] = [I32_MIN, 2 ** 31 - 1, 0]
+    T = vrs.Table(_dev(np.zeros((n, 4), np.float32)), _dev(a))
+    ot = O.Table(O.F32, np.zeros((n, 4), np.float32), a)
+    for pred in ([], [(0, 0, 10)], [(0, 10, 10)], [(0, 50, 40)], [(1, I32_MIN, I32_MIN + 1)],
+                 [(1, 2 ** 31 - 1, 2 ** 40)], [(0, -2 ** 40, 2 ** 40), (1, 0, 3)],
+                 [(0, 3, 97), (1, -4, 4), (0, 5, 90)]):
+        got = T.select(pred).cpu().numpy()
+        assert np.array_equal(got, O.select(ot, pred)), pred
+
+
+# ------------------------------------------------------------------ scans
+def _config0(n=100_000, d=128, C=100, B=16, seed_cfg=0):
+    x = inputs.table(seed_cfg, n, d, C)
+    a = inputs.attributes(seed_cfg, n, 1, 100)
+    q = inputs.queries(seed_cfg, B, d, C)
+    return x, a, q
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    x, a, q = _config0()
+    T = vrs.Table(_dev(x), _dev(a))
+    ot = O.Table(O.F32, x, a)
+    pred = [(0, I32_MIN, 10)]
+    ref = O.scan_topk(ot, q, pred, 10, O.L2SQ)
+    return x, a, q, T, ot, pred, ref
+
+
+@pytest.mark.parametrize("strategy", [vrs.STRATEGY_AUTO, vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER])
+@pytest.mark.parametrize("tile", [-1, 0, 1, 2, 3])
+def test_config0_l2_top10(cfg0, strategy, tile):
+    x, a, q, T, ot, pred, ref = cfg0
+    r = T.scan_topk(_dev(q), pred, 10, vrs.L2SQ, strategy=strategy, tile=tile)
+    torch.cuda.synchronize()
+    _check(r, ref, f"strategy {strategy} tile {tile}")
+
+
+def test_config0_deterministic_and_strategy_invariant(cfg0):
+    x, a, q, T, ot, pred, ref = cfg0
+    outs = []
+    for strategy in (vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER, vrs.STRATEGY_MASK):
+        r = T.scan_topk(_dev(q), pred, 10, vrs.L2SQ, strategy=strategy)
+        outs.append((r.idx.cpu().numpy(), r.dist.cpu().numpy().view(np.uint32)))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+def test_query_alone_equals_query_in_batch(cfg0):
+    x, a, q, T, ot, pred, ref = cfg0
+    full = T.scan_topk(_dev(q), pred, 10, vrs.L2SQ)
+    for b in (0, 7, 15):
+        one = T.scan_topk(_dev(q[b:b + 1]), pred, 10, vrs.L2SQ)
+        assert torch.equal(one.idx[0], full.idx[b]) and torch.equal(one.dist[0], full.dist[b])
+
+
+@pytest.mark.parametrize("metric", [vrs.L2SQ, vrs.IP])
+@pytest.mark.parametrize("k", [1, 100, 256])
+def test_ragged_shapes_and_k(metric, k):
+    rng = np.random.default_rng(3)
+    n, d, B = 33333, 100, 5  # d pads to 128, n is ragged for every tile
+    x = inputs.table(1, n, d, 50)
+    a = inputs.attributes(1, n, 2, 1000)
+    q = inputs.queries(1, B, d, 50)
+    T = vrs.Table(_dev(x), _dev(a), normalize=(metric == vrs.IP))
+    ot = O.Table.build(x, a, O.F32, normalize=(metric == vrs.IP))
+    pred = [(0, 100, 900), (1, 0, 700)]
+    ref = O.scan_topk(ot, q, pred, k, metric)
+    for strategy in (vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER):
+        r = T.scan_topk(_dev(q), pred, k, metric, strategy=strategy)
+        _check(r, ref, f"metric {metric} k {k} strategy {strategy}")
+
+
+def test_fewer_qualifying_rows_than_k_and_empty():
+    x, a, q = _config0(n=5000, B=3)
+    T = vrs.Table(_dev(x), _dev(a))
+    ot = O.Table(O.F32, x, a)
+    for pred in ([(0, 7, 8)], [(0, 200, 300)], [(0, 0, 0)]):
+        # attr==7 keeps ~50 rows < k=100
+        ref = O.scan_topk(ot, q, pred, 100, O.L2SQ)
+        for strategy in (vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER):
+            r = T.scan_topk(_dev(q), pred, 100, vrs.L2SQ, strategy=strategy)
+            _check(r, ref, f"pred {pred}")
+
+
+def test_planted_duplicates_and_queries():
+    x, a, q = _config0(n=20000, B=4)
+    sel = np.nonzero(a[0] < 10)[0]
+    outside = np.nonzero(a[0] >= 10)[0]
+    x = x.copy()
+    for j in range(1, 40):                 # 40 identical rows -> 40-way tie at distance 0
+        x[sel[j * 3]] = x[sel[0]]
+    q = q.copy()
+    q[0] = x[sel[0]]
+    q[1] = x[outside[5]]                    # planted in a non-qualifying row
+    T = vrs.Table(_dev(x), _dev(a))
+    ot = O.Table(O.F32, x, a)
+    pred = [(0, 0, 10)]
+    ref = O.scan_topk(ot, q, pred, 10, O.L2SQ)
+    assert ref[1][0, 0] == 0 and ref[1][0, 9] == 0
+    r = T.scan_topk(_dev(q), pred, 10, vrs.L2SQ)
+    _check(r, ref, "planted")
+    assert int(outside[5]) not in r.idx[1].tolist()
+
+
+@pytest.mark.parametrize("store", [vrs.BF16, vrs.FP8E4M3, vrs.F32])
+def test_ip_quantised_storage(store):
+    x = inputs.table(2, 40000, 256, 200)
+    a = inputs.attributes(2, 40000, 2, 10 ** 6)
+    q = inputs.queries(2, 8, 256, 200)
+    T = vrs.Table(_dev(x), _dev(a), store=store, normalize=True)
+    ot = O.Table.build(x, a, {vrs.F32: O.F32, vrs.BF16: O.BF16, vrs.FP8E4M3: O.FP8}[store], True)
+    w = inputs.two_term_width(0.3, 10 ** 6)
+    pred = [(0, 0, w), (1, 0, w)]
+    for k in (10, 100):
+        ref = O.scan_topk(ot, q, pred, k, O.IP)
+        r = T.scan_topk(_dev(q), pred, k, vrs.IP)
+        _check(r, ref, f"store {store} k {k}")
+
+
+def test_forced_certificate_failure_uses_exact_fallback():
+    # k' = k and a 200-way exact tie around the k-th position: the screening
+    # lists cannot certify, the FP64 fallback must produce the exact answer
+    x, a, q = _config0(n=30000, B=4)
+    x = x.copy()
+    sel = np.nonzero(a[0] < 10)[0]
+    for j in range(1, 200):
+        x[sel[j * 7]] = x[sel[0]]
+    q = q.copy()
+    q[:2] = x[sel[0]] + np.float32(0.01)
+    T = vrs.Table(_dev(x), _dev(a))
+    ot = O.Table(O.F32, x, a)
+    pred = [(0, 0, 10)]
+    ref = O.scan_topk(ot, q, pred, 50, O.L2SQ)
+    r = T.scan_topk(_dev(q), pred, 50, vrs.L2SQ, kprime_mult=1)
+    _check(r, ref, "fallback")
+    assert r.certified[:2].sum().item() == 0
+
+
+def test_batched_per_query_predicates_and_k():
+    n, d, B = 50000, 64, 37
+    x = inputs.table(3, n, d, 100)
+    a = inputs.attributes(3, n, 2, 10 ** 6)
+    q = inputs.queries(3, B, d, 100)
+    bp = inputs.batched_predicates(3, B, 10 ** 6, s_min=1e-3)
+    preds = [[(0, int(bp.lo[b, 0]), int(bp.hi[b, 0])), (1, int(bp.lo[b, 1]), int(bp.hi[b, 1]))]
+             for b in range(B)]
+    preds[3] = []                       # no predicate
+    preds[4] = [(0, 10, 5)]             # empty
+    T = vrs.Table(_dev(x), _dev(a), normalize=True)
+    ot = O.Table.build(x, a, O.F32, normalize=True)
+    kmax = int(bp.k.max())
+    ref = O.scan_topk(ot, q, preds, bp.k, O.IP, out_stride=kmax)
+    r = T.scan_topk_batched(_dev(q), vrs.preds_tensor(preds), _dev(bp.k), kmax, vrs.IP)
+    _check(r, ref, "batched")
