@@ -50,6 +50,8 @@ def main():
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--cpu-queries", type=int, default=0, help="oracle sample size (0 = #cores)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -138,6 +140,16 @@ def main():
     roof["kernel_ms"] = round(screen_ms, 4)
     roof["alg_bytes_per_launch"] = int(bytes_alg)
     roof["alg_flops_per_launch"] = int(flops_alg)
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {args.copy_calibration} MiB")
+        del src, dst
 
     cpu = None
     if not args.no_cpu:

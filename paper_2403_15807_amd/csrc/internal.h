@@ -99,7 +99,7 @@ struct FinishArgs {
     int32_t K;                     // list length = max k' + 1
     int32_t n_chunks;
     const uint64_t *partials;
-    uint64_t *merge_mid;           // [B][ceil(n_chunks/32)][K] (two-level merge)
+    uint64_t *merge_mid;           // [B][ceil(n_chunks/2048)][K] (two-level merge)
     uint64_t *merged;              // [B][K]
     double rel, abs_ip, abs_l2, max_norm;  // screening error model
     int32_t *fail_list;            // [B]

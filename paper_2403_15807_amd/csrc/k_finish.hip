@@ -37,33 +37,66 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, 
     if (threadIdx.x == 0) qnorm[b] = sqrt(red[0]) * (1.0 + 0x1p-40);
 }
 
-// FP64 value of stored element j of row `row` as the exact formula uses it:
-// the float32 / bfloat16 value, or the unscaled e4m3 code value.
+// Exact distance of the definition: coordinates in ascending order, one
+// fused multiply-add each, accumulator from +0.0; IP applies the FP8 row
+// scale to the finished sum; zero is returned as +0.0.  The row is read in
+// 16-byte blocks up to the padded width dp; `qrow` holds the query padded
+// with zeros to dp, and a padded coordinate adds an exact zero (+0 + +0 or
+// acc + 0), so the value equals the sum over the first d coordinates.
 template <int STORE>
-__device__ __forceinline__ double code_at(const void *rows, int64_t row, int dp, int j) {
-    if (STORE == VRS_F32) return (double)((const float *)rows)[row * dp + j];
-    if (STORE == VRS_BF16) return (double)bf16_to_f32(((const uint16_t *)rows)[row * dp + j]);
-    return (double)e4m3_to_f32(((const uint8_t *)rows)[row * dp + j]);
+__device__ __forceinline__ void decode16(const uint4 &w, float *x);
+template <>
+__device__ __forceinline__ void decode16<VRS_F32>(const uint4 &w, float *x) {
+    x[0] = __uint_as_float(w.x);
+    x[1] = __uint_as_float(w.y);
+    x[2] = __uint_as_float(w.z);
+    x[3] = __uint_as_float(w.w);
+}
+template <>
+__device__ __forceinline__ void decode16<VRS_BF16>(const uint4 &w, float *x) {
+    const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        x[2 * i] = __uint_as_float(v[i] << 16);
+        x[2 * i + 1] = __uint_as_float(v[i] & 0xffff0000u);
+    }
+}
+template <>
+__device__ __forceinline__ void decode16<VRS_FP8E4M3>(const uint4 &w, float *x) {
+    const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[4 * i + j] = e4m3_to_f32((v[i] >> (8 * j)) & 0xffu);
 }
 
-// Exact distance of the definition: j ascending, one fma per coordinate,
-// accumulator from +0.0; IP applies the FP8 row scale to the finished sum;
-// zero is returned as +0.0.
 template <int STORE, int METRIC>
-__device__ double exact_dist(const void *rows, const float *scale, int64_t row, int d, int dp,
-                             const float *qrow /* LDS or global, d floats */) {
+__device__ double exact_dist(const void *rows, const float *scale, int64_t row, int dp,
+                             const float *qrow /* dp floats, zero padded */) {
+    constexpr int V = STORE == VRS_F32 ? 4 : (STORE == VRS_BF16 ? 8 : 16);
+    constexpr int EB = 16 / V;
+    const uint4 *p = (const uint4 *)((const char *)rows + row * (int64_t)dp * EB);
+    const int nb = dp / V;
+    const double sc = (STORE == VRS_FP8E4M3) ? (double)scale[row] : 1.0;
     double acc = 0.0;
-    if (METRIC == VRS_L2SQ) {
-        double sc = (STORE == VRS_FP8E4M3) ? (double)scale[row] : 1.0;
-        for (int j = 0; j < d; ++j) {
-            double t = (double)qrow[j] - sc * code_at<STORE>(rows, row, dp, j);
-            acc = fma(t, t, acc);
+    for (int c = 0; c < nb; c += 2) {
+        uint4 w0 = p[c];
+        uint4 w1 = (c + 1 < nb) ? p[c + 1] : make_uint4(0, 0, 0, 0);
+        float x[2 * V];
+        decode16<STORE>(w0, x);
+        decode16<STORE>(w1, x + V);
+        const int jn = min(2 * V, dp - c * V);
+        for (int j = 0; j < jn; ++j) {
+            const double qj = (double)qrow[c * V + j];
+            if (METRIC == VRS_L2SQ) {
+                double t = qj - sc * (double)x[j];
+                acc = fma(t, t, acc);
+            } else {
+                acc = fma(qj, (double)x[j], acc);
+            }
         }
-    } else {
-        for (int j = 0; j < d; ++j) acc = fma((double)qrow[j], code_at<STORE>(rows, row, dp, j), acc);
-        double sc = (STORE == VRS_FP8E4M3) ? (double)scale[row] : 1.0;
-        acc = -(sc * acc);
     }
+    if (METRIC == VRS_IP) acc = -(sc * acc);
     return acc == 0.0 ? 0.0 : acc;
 }
 
@@ -74,68 +107,176 @@ __device__ __forceinline__ int kp_of(const FinishArgs &a, int b) {
 
 // ------------------------------------------------------------------ merge
 // Workgroup (g, b) merges lists [g*G, (g+1)*G) of query b from `src` (each K
-// sorted keys) into list g of `dst`.
-constexpr int MERGE_PER_THREAD = 8;
+// sorted keys, KEY_INF padded) into list g of `dst`.
+//
+// Every list is sorted, so the K-th smallest of the lists' first m entries
+// ("heads") is an upper bound on the K-th smallest key overall: K keys at or
+// below it exist.  Only the list prefixes at or below that bound are read
+// and merged; with the chunk lists of a scan that is a few keys per list.
+constexpr int MERGE_THREADS = 512;
+constexpr int MERGE_HMAX = 4096;
 
-__global__ __launch_bounds__(256) void merge_kernel(const uint64_t *__restrict__ src, int n_lists,
-                                                    int G, int K, int Kp, int CB,
-                                                    uint64_t *__restrict__ dst, int n_out) {
+__global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__restrict__ src,
+                                                              int n_lists, int G, int K, int Kp,
+                                                              int CB, uint64_t *__restrict__ dst,
+                                                              int n_out) {
+    constexpr int T = MERGE_THREADS;
     const int g = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
     extern __shared__ __align__(16) unsigned char smem[];
-    uint64_t *keys = (uint64_t *)smem;
-    uint64_t *thr = keys + (Kp + CB);
+    const int l0 = g * G, l1 = min(n_lists, l0 + G), L = l1 - l0;
+    const uint64_t *lists = src + ((int64_t)b * n_lists + l0) * K;
+    const int M = Kp + CB;
+    uint64_t *keys = (uint64_t *)smem;                         // heads, then the top-k list
+    const int region = max(M, MERGE_HMAX);
+    uint64_t *thr = keys + region;
     int *cnt = (int *)(thr + 1);
+    __shared__ uint64_t bound_s;
+
+    // phase 1: bound from the heads
+    int m = max(1, min(K, (2 * K + L - 1) / L));
+    if (L * m > MERGE_HMAX) m = max(1, MERGE_HMAX / L);
+    const int H = min(L * m, MERGE_HMAX);
+    const int HP = next_pow2(max(H, 2));
+    for (int i = tid; i < HP; i += T) keys[i] = i < H ? lists[(int64_t)(i / m) * K + (i % m)] : KEY_INF;
+    __syncthreads();
+    lds_bitonic_sort<uint64_t>(keys, 1, HP, tid, T);
+    if (tid == 0) bound_s = (H >= K) ? keys[K - 1] : KEY_INF;
+    __syncthreads();
+    const uint64_t bound = bound_s;
+
+    // phase 2: merge every list prefix at or below the bound.  Thread tid owns
+    // lists tid + j*T (j < 4, since G <= 4T); each round it reads the next two
+    // entries of up to two of its lists, so most lists cost one round.
     TopkLds<uint64_t> tk{keys, cnt, thr, 1, K, Kp, CB};
-    tk.init(tid, 256);
-    const int l0 = g * G, l1 = min(n_lists, l0 + G);
-    const int64_t tot = (int64_t)(l1 - l0) * K;
-    const uint64_t *s = src + ((int64_t)b * n_lists + l0) * K;
-    constexpr int BATCH = 256 * MERGE_PER_THREAD;
-    for (int64_t p0 = 0; p0 < tot; p0 += BATCH) {
-        uint64_t v[MERGE_PER_THREAD];
+    tk.init(tid, T);
+    int pos[4] = {0, 0, 0, 0};
+    bool live[4];
 #pragma unroll
-        for (int e = 0; e < MERGE_PER_THREAD; ++e) {
-            int64_t p = p0 + e * 256 + tid;
-            v[e] = p < tot ? s[p] : KEY_INF;
+    for (int j = 0; j < 4; ++j) live[j] = tid + j * T < L;
+    for (;;) {
+        int sel0 = -1, sel1 = -1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (live[j] && sel0 < 0) sel0 = j;
+            else if (live[j] && sel1 < 0) sel1 = j;
+        }
+        uint64_t v[2][2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            const int j = x == 0 ? sel0 : sel1;
+            const int p = j >= 0 ? pos[j] : K;
+            const uint64_t *lp = lists + (int64_t)(tid + max(j, 0) * T) * K;
+            v[x][0] = (j >= 0 && p < K) ? lp[p] : KEY_INF;
+            v[x][1] = (j >= 0 && p + 1 < K) ? lp[p + 1] : KEY_INF;
         }
 #pragma unroll
-        for (int e = 0; e < MERGE_PER_THREAD; ++e)
-            if (v[e] != KEY_INF) tk.push(0, v[e]);
-        __syncthreads();
-        if (tk.need_flush(BATCH)) tk.flush(tid, 256);
+        for (int x = 0; x < 2; ++x) {
+            const int j = x == 0 ? sel0 : sel1;
+            if (j < 0) continue;
+            bool keep = true;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const uint64_t key = v[x][e];
+                if (keep && key != KEY_INF && key <= bound)
+                    tk.push(0, key);
+                else
+                    keep = false;
+            }
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+                if (jj == j) {
+                    pos[jj] += 2;
+                    live[jj] = keep && pos[jj] < K;
+                }
+        }
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) any = any || live[j];
+        const bool more = __syncthreads_or(any);
+        if (tk.need_flush(T * 4)) tk.flush(tid, T);
+        if (!more) break;
     }
-    if (tk.need_flush(CB)) tk.flush(tid, 256);
-    for (int i = tid; i < K; i += 256) dst[((int64_t)b * n_out + g) * K + i] = keys[i];
+    if (tk.need_flush(CB)) tk.flush(tid, T);
+    for (int i = tid; i < K; i += T) dst[((int64_t)b * n_out + g) * K + i] = keys[i];
 }
 
 // ----------------------------------------------------------------- rerank
+// One workgroup per query.  Each lane owns one candidate and runs the exact
+// FP64 formula over it in coordinate order; the rows themselves are loaded
+// cooperatively (8 lanes per 128-byte block of a row, 8 loads in flight per
+// lane) into LDS, one 128-byte column chunk of 64 rows per wave at a time.
+constexpr int RR_CHUNK = 8;  // 16-byte blocks per row per chunk
+
 template <int STORE, int METRIC>
 __global__ __launch_bounds__(256) void rerank_kernel(FinishArgs a) {
-    const int b = blockIdx.x, tid = threadIdx.x;
+    constexpr int V = STORE == VRS_F32 ? 4 : (STORE == VRS_BF16 ? 8 : 16);
+    constexpr int EB = 16 / V;
+    const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int kb = k_of(a, b), kpb = kp_of(a, b);
     extern __shared__ __align__(16) unsigned char smem[];
     const int Mc = next_pow2(max(kpb, 2));
-    Key128 *cand = (Key128 *)smem;                 // [Mc]
-    float *qrow = (float *)(cand + Mc);            // [d]
+    Key128 *cand = (Key128 *)smem;                           // [Mc]
+    uint4 *stage = (uint4 *)(cand + Mc);                     // [4][64][RR_CHUNK + 1]
+    float *qrow = (float *)(stage + 4 * 64 * (RR_CHUNK + 1)); // [dp], zero padded
     __shared__ int n_cand_s;
-    for (int j = tid; j < a.d; j += 256) qrow[j] = a.q[(int64_t)b * a.d + j];
+    for (int j = tid; j < a.dp; j += 256) qrow[j] = j < a.d ? a.q[(int64_t)b * a.d + j] : 0.0f;
     if (tid == 0) n_cand_s = 0;
     __syncthreads();
     const uint64_t *lst = a.merged + (int64_t)b * a.K;
+    const int nb16 = a.dp / V;                               // 16-byte blocks per row
+    const int64_t row_bytes = (int64_t)a.dp * EB;
+    uint4 *my_stage = stage + (wave * 64) * (RR_CHUNK + 1);
     int mycnt = 0;
-    for (int i = tid; i < Mc; i += 256) {
-        Key128 c = KeyOps<Key128>::inf();
-        if (i < kpb) {
-            uint64_t key = lst[i];
-            if (key != KEY_INF) {
-                int64_t row = (int64_t)(uint32_t)key;
-                double dv = exact_dist<STORE, METRIC>(a.rows, a.scale, row, a.d, a.dp, qrow);
-                c.hi = ord64(dv);
-                c.lo = (uint64_t)row;
+    for (int g0 = 0; g0 < Mc; g0 += 256) {
+        const int ci = g0 + tid;
+        int64_t myrow = -1;
+        if (ci < kpb) {
+            uint64_t key = lst[ci];
+            if (key != KEY_INF) myrow = (int64_t)(uint32_t)key;
+        }
+        double acc = 0.0;
+        const double sc = (STORE == VRS_FP8E4M3 && myrow >= 0) ? (double)a.scale[myrow] : 1.0;
+        for (int c0 = 0; c0 < nb16; c0 += RR_CHUNK) {
+            uint4 w[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int src = (lane >> 3) + 8 * i;
+                const int64_t rr = __shfl(myrow, src);
+                w[i] = rr >= 0 ? *(const uint4 *)((const char *)a.rows + rr * row_bytes +
+                                                  (int64_t)(c0 + (lane & 7)) * 16)
+                               : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) my_stage[((lane >> 3) + 8 * i) * (RR_CHUNK + 1) + (lane & 7)] = w[i];
+            __syncthreads();
+            if (myrow >= 0) {
+                for (int blk = 0; blk < RR_CHUNK; ++blk) {
+                    float x[V];
+                    decode16<STORE>(my_stage[lane * (RR_CHUNK + 1) + blk], x);
+                    const float *qj = qrow + (c0 + blk) * V;
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        if (METRIC == VRS_L2SQ) {
+                            double t = (double)qj[v] - sc * (double)x[v];
+                            acc = fma(t, t, acc);
+                        } else {
+                            acc = fma((double)qj[v], (double)x[v], acc);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (ci < Mc) {
+            Key128 c = KeyOps<Key128>::inf();
+            if (myrow >= 0) {
+                if (METRIC == VRS_IP) acc = -(sc * acc);
+                c.hi = ord64(acc == 0.0 ? 0.0 : acc);
+                c.lo = (uint64_t)myrow;
                 ++mycnt;
             }
+            cand[ci] = c;
         }
-        cand[i] = c;
     }
     atomicAdd(&n_cand_s, mycnt);
     __syncthreads();
@@ -196,7 +337,7 @@ __global__ __launch_bounds__(256) void fallback_scan_kernel(FinishArgs a) {
         const int kb = k_of(a, b);
         const PredDev p = a.preds ? a.preds[b] : a.pred;
         __syncthreads();  // previous task done with LDS
-        for (int j = tid; j < a.d; j += 256) qrow[j] = a.q[(int64_t)b * a.d + j];
+        for (int j = tid; j < a.dp; j += 256) qrow[j] = j < a.d ? a.q[(int64_t)b * a.d + j] : 0.0f;
         TopkLds<Key128> tk{keys, cnt, thr, 1, kb, Kp, CB};
         tk.init(tid, 256);
         const int64_t r0 = (int64_t)c * a.fb_rows_per_chunk;
@@ -204,7 +345,7 @@ __global__ __launch_bounds__(256) void fallback_scan_kernel(FinishArgs a) {
         for (int64_t t0 = r0; t0 < r1; t0 += 256) {
             int64_t row = t0 + tid;
             if (row < r1 && pred_eval(p, a.attr, a.n, row)) {
-                double dv = exact_dist<STORE, METRIC>(a.rows, a.scale, row, a.d, a.dp, qrow);
+                double dv = exact_dist<STORE, METRIC>(a.rows, a.scale, row, a.dp, qrow);
                 tk.push(0, Key128{ord64(dv), (uint64_t)row});
             }
             __syncthreads();
@@ -333,28 +474,30 @@ hipError_t launch_prep_batched(const vrs_pred *preds, const int32_t *ks, int32_t
     return hipGetLastError();
 }
 
-static int merge_cb(int Kp) { return next_pow2(Kp + 256 * MERGE_PER_THREAD) - Kp; }
+static int merge_cb(int Kp) { return next_pow2(Kp + MERGE_THREADS * 4) - Kp; }
 
 hipError_t launch_merge(const FinishArgs &a, hipStream_t s) {
     const int Kp = next_pow2(a.K), CB = merge_cb(Kp);
-    const size_t lds = (size_t)(Kp + CB) * 8 + 8 + 16;
-    const int G = 32;
+    const size_t lds = (size_t)std::max(Kp + CB, MERGE_HMAX) * 8 + 8 + 16;
+    const int G = 2048;
     if (a.n_chunks <= G) {
-        merge_kernel<<<dim3(1, a.B), 256, lds, s>>>(a.partials, a.n_chunks, G, a.K, Kp, CB,
-                                                    a.merged, 1);
+        merge_kernel<<<dim3(1, a.B), MERGE_THREADS, lds, s>>>(a.partials, a.n_chunks, G, a.K, Kp,
+                                                             CB, a.merged, 1);
         return hipGetLastError();
     }
     // two levels: groups of G lists, then the group results
     const int ng = (a.n_chunks + G - 1) / G;
     uint64_t *mid = a.merge_mid;
-    merge_kernel<<<dim3(ng, a.B), 256, lds, s>>>(a.partials, a.n_chunks, G, a.K, Kp, CB, mid, ng);
-    merge_kernel<<<dim3(1, a.B), 256, lds, s>>>(mid, ng, ng, a.K, Kp, CB, a.merged, 1);
+    merge_kernel<<<dim3(ng, a.B), MERGE_THREADS, lds, s>>>(a.partials, a.n_chunks, G, a.K, Kp, CB,
+                                                          mid, ng);
+    merge_kernel<<<dim3(1, a.B), MERGE_THREADS, lds, s>>>(mid, ng, ng, a.K, Kp, CB, a.merged, 1);
     return hipGetLastError();
 }
 
 template <int STORE, int METRIC>
 static hipError_t rerank_t(const FinishArgs &a, hipStream_t s, int kpmax) {
-    size_t lds = (size_t)next_pow2(std::max(kpmax, 2)) * sizeof(Key128) + (size_t)a.d * 4 + 16;
+    size_t lds = (size_t)next_pow2(std::max(kpmax, 2)) * sizeof(Key128) +
+                 (size_t)4 * 64 * (RR_CHUNK + 1) * 16 + (size_t)a.dp * 4 + 16;
     rerank_kernel<STORE, METRIC><<<a.B, 256, lds, s>>>(a);
     return hipGetLastError();
 }
@@ -385,7 +528,7 @@ static void fallback_t(const FinishArgs &a, hipStream_t s, size_t lds_scan, size
 hipError_t launch_fallback(const FinishArgs &a, hipStream_t s) {
     const int Kp = next_pow2(a.kmax), M = next_pow2(Kp + 256);
     const size_t lds_merge = (size_t)M * sizeof(Key128) + sizeof(Key128) + 16;
-    const size_t lds_scan = lds_merge + (size_t)a.d * 4 + 16;
+    const size_t lds_scan = lds_merge + (size_t)a.dp * 4 + 16;
     const int grid = FB_GRID;
     if (a.metric == VRS_L2SQ) {
         switch (a.store) {

@@ -18,6 +18,13 @@ namespace {
 
 constexpr int U = 2;                 // rows per lane-group per iteration
 constexpr int TILE = 4 * 8 * U;      // rows per workgroup iteration
+constexpr int NB = 4;                // 128-byte column blocks loaded together
+
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 load_nt(const uint4 *p) {
+    v4u32 v = __builtin_nontemporal_load((const v4u32 *)p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
 
 template <int STORE>
 struct Elem;
@@ -95,16 +102,45 @@ __global__ __launch_bounds__(256) void screen_stream_kernel(ScreenArgs a) {
     const int nblk = (int)(row_bytes / 128);   // 128-byte column blocks per row
     const char *base = (const char *)a.rows;
 
-    for (int64_t t0 = c0; t0 < c1; t0 += TILE) {
-        int64_t row[U];
-        bool qual[U];
+    // Row ids and raw predicate columns of a tile are fetched one tile ahead,
+    // so their latency overlaps the current tile's vector loads.
+    auto fetch = [&](int64_t t0, int64_t(&rw)[U], bool(&vd)[U], int32_t(&av)[U][4]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             int64_t pos = t0 + u * 32 + wave * 8 + r;
-            bool valid = pos < c1;
-            row[u] = GATHER ? (valid ? (int64_t)a.sel_ids[pos] : 0) : pos;
-            qual[u] = valid && (GATHER || BATCHED || pred_eval(a.pred, a.attr, a.n, row[u]));
+            vd[u] = pos < c1;
+            rw[u] = GATHER ? (vd[u] ? (int64_t)a.sel_ids[pos] : 0) : pos;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                av[u][t] = (!GATHER && !BATCHED && vd[u] && t < a.pred.nterms)
+                               ? a.attr[(int64_t)a.pred.col[t] * a.n + rw[u]]
+                               : 0;
         }
+    };
+    auto decide = [&](const bool(&vd)[U], const int32_t(&av)[U][4], bool(&ql)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            bool ok = vd[u];
+            if (!GATHER && !BATCHED) {
+                ok = ok && a.pred.nterms >= 0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (t < a.pred.nterms) ok = ok && av[u][t] >= a.pred.lo[t] && av[u][t] <= a.pred.hi[t];
+            }
+            ql[u] = ok;
+        }
+    };
+    int64_t row[U], nrow[U];
+    bool qual[U], nvd[U];
+    int32_t nav[U][4];
+    {
+        bool vd[U];
+        int32_t av[U][4];
+        fetch(c0, row, vd, av);
+        decide(vd, av, qual);
+    }
+    for (int64_t t0 = c0; t0 < c1; t0 += TILE) {
+        fetch(t0 + TILE, nrow, nvd, nav);
         bool any = false;
 #pragma unroll
         for (int u = 0; u < U; ++u) any = any || qual[u];
@@ -114,30 +150,39 @@ __global__ __launch_bounds__(256) void screen_stream_kernel(ScreenArgs a) {
             for (int u = 0; u < U; ++u)
 #pragma unroll
                 for (int b = 0; b < QT; ++b) acc[u][b] = 0.0f;
-            for (int cb = 0; cb < nblk; ++cb) {
-                uint4 w[U];
+            // Issue the loads of NB column blocks of every row before using
+            // any of them, so each lane keeps U*NB 16-byte loads in flight.
+            // Rows are read once per scan: non-temporal loads.
+            for (int cg = 0; cg < nblk; cg += NB) {
+                uint4 w[U][NB];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (qual[u])
-                        w[u] = *(const uint4 *)(base + row[u] * row_bytes + cb * 128 + s * 16);
-                    else
-                        w[u] = make_uint4(0, 0, 0, 0);
-                }
-                const int e0 = (cb * 128 + s * 16) / eb;  // first element of this lane's slice
+                for (int c = 0; c < NB; ++c)
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    float x[V];
-                    Elem<STORE>::decode(w[u], x);
+                    for (int u = 0; u < U; ++u) {
+                        if (qual[u] && cg + c < nblk)
+                            w[u][c] = load_nt((const uint4 *)(base + row[u] * row_bytes + (cg + c) * 128 + s * 16));
+                        else
+                            w[u][c] = make_uint4(0, 0, 0, 0);
+                    }
 #pragma unroll
-                    for (int b = 0; b < QT; ++b) {
-                        const float *qb = qs + b * a.dp + e0;
+                for (int c = 0; c < NB; ++c) {
+                    if (cg + c >= nblk) break;
+                    const int e0 = ((cg + c) * 128 + s * 16) / eb;  // first element of the slice
 #pragma unroll
-                        for (int v = 0; v < V; ++v) {
-                            if (METRIC == VRS_L2SQ) {
-                                float t = qb[v] - x[v];
-                                acc[u][b] = fmaf(t, t, acc[u][b]);
-                            } else {
-                                acc[u][b] = fmaf(qb[v], x[v], acc[u][b]);
+                    for (int u = 0; u < U; ++u) {
+                        float x[V];
+                        Elem<STORE>::decode(w[u][c], x);
+#pragma unroll
+                        for (int b = 0; b < QT; ++b) {
+                            const float *qb = qs + b * a.dp + e0;
+#pragma unroll
+                            for (int v = 0; v < V; ++v) {
+                                if (METRIC == VRS_L2SQ) {
+                                    float t = qb[v] - x[v];
+                                    acc[u][b] = fmaf(t, t, acc[u][b]);
+                                } else {
+                                    acc[u][b] = fmaf(qb[v], x[v], acc[u][b]);
+                                }
                             }
                         }
                     }
@@ -179,6 +224,9 @@ __global__ __launch_bounds__(256) void screen_stream_kernel(ScreenArgs a) {
                 }
             }
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) row[u] = nrow[u];
+        decide(nvd, nav, qual);
         __syncthreads();
         if (tk.need_flush(TILE)) tk.flush(tid, 256);
     }

@@ -13,10 +13,10 @@ namespace vrs {
 namespace {
 
 const TileCfg kTiles[] = {
-    {0, 1, 2048},
-    {0, 2, 2048},
-    {0, 4, 2048},
-    {0, 8, 2048},
+    {0, 1, 1024},
+    {0, 2, 1024},
+    {0, 4, 1024},
+    {0, 8, 1024},
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 constexpr size_t LDS_BUDGET = 64 * 1024;  // several workgroups per CU
@@ -68,7 +68,7 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
     P.o_sel = take((size_t)t->n * 4);
     P.o_selcnt = take(8);
     P.o_part = take((size_t)B * P.n_chunks * P.K * 8);
-    P.o_mid = take((size_t)B * ((P.n_chunks + 31) / 32) * P.K * 8);
+    P.o_mid = take((size_t)B * ((P.n_chunks + 2047) / 2048) * P.K * 8);
     P.o_merged = take((size_t)B * P.K * 8);
     P.o_fail = take((size_t)B * 4);
     P.o_failcnt = take(8);
