@@ -188,3 +188,53 @@ __host__ __device__ inline int next_pow2(int x) {
 }
 
 }  // namespace vrs
+
+namespace vrs {
+
+// ------------------------------------------------- wave-level bitonic sort
+// 64*E keys held E per lane (element index lane*E + e), sorted ascending by
+// one wave without LDS or barriers: strides below E are swaps inside a lane,
+// larger strides exchange with lane ^ (stride / E) through cross-lane moves.
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    lo = __shfl_xor(lo, m);
+    hi = __shfl_xor(hi, m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int E>
+__device__ __forceinline__ void wave_sort_u64(uint64_t (&v)[E]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int size = 2; size <= 64 * E; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride < E) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    if ((e & stride) == 0) {
+                        const int i = lane * E + e;
+                        const bool up = (i & size) == 0;
+                        uint64_t x = v[e], y = v[e + stride];
+                        const bool sw = up ? (y < x) : (x < y);
+                        v[e] = sw ? y : x;
+                        v[e + stride] = sw ? x : y;
+                    }
+                }
+            } else {
+                const int ls = stride / E;
+                const bool lower = (lane & ls) == 0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int i = lane * E + e;
+                    const bool up = (i & size) == 0;
+                    const uint64_t p = shfl_xor_u64(v[e], ls);
+                    const bool take_min = (lower == up);
+                    v[e] = take_min ? (p < v[e] ? p : v[e]) : (p > v[e] ? p : v[e]);
+                }
+            }
+        }
+    }
+}
+
+}  // namespace vrs

@@ -48,7 +48,9 @@ hipError_t launch_select(const int32_t *attr, int64_t n, const PredDev &p, uint3
 
 // ---- query preparation (k_finish.hip)
 hipError_t launch_prep_queries(const float *q, int32_t B, int32_t d, int32_t dp, float *qp,
-                               double *qnorm, int32_t *fail_count, hipStream_t s);
+                               double *qnorm, float *qn2, uint64_t *gthr, int32_t *fail_count,
+                               hipStream_t s);
+int screen_mfma_occupancy(int Kp, int CB);
 hipError_t launch_prep_batched(const vrs_pred *preds, const int32_t *ks, int32_t B, int32_t kmax,
                                int32_t n_attr, int kmult, int f32_rule, PredDev *out,
                                int32_t *kc, int32_t *kps, hipStream_t s);
@@ -68,14 +70,21 @@ struct ScreenArgs {
     const int64_t *sel_count;
     int gather;
     const float *qp;               // [B][dp]
+    const float *qn2;              // [B] ||q||^2 (float32 of the FP64 sum)
+    const float *norm2;            // [n] ||x_i||^2 of stored rows
     int32_t B;
     int metric;
     int32_t K, Kp, CB;
     int32_t n_chunks;
     uint64_t *partials;            // [B][n_chunks][K]
+    uint64_t *cbuf;                // [B][n_chunks][CB] candidate buffers (MFMA kernels)
+    uint64_t *gthr;                // [B] smallest K-th key published by any chunk
 };
 hipError_t launch_screen_stream(const ScreenArgs &a, int qt, hipStream_t s);
 size_t screen_stream_lds(int qt, int Kp, int CB, int dp);
+hipError_t launch_screen_mfma(const ScreenArgs &a, hipStream_t s);
+size_t screen_mfma_lds(int dp);
+bool screen_mfma_supported(int dp, vrs_dtype store, int Kp, int CB);
 
 // ---- merge, rerank, fallback (k_finish.hip)
 struct FinishArgs {

@@ -18,8 +18,11 @@ namespace {
 __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, int d, int dp,
                                                    float *__restrict__ qp,
                                                    double *__restrict__ qnorm,
+                                                   float *__restrict__ qn2,
+                                                   uint64_t *__restrict__ gthr,
                                                    int32_t *__restrict__ fail_count) {
     const int b = blockIdx.x;
+    if (threadIdx.x == 0) gthr[b] = KEY_INF;
     if (b == 0 && threadIdx.x == 0) *fail_count = 0;
     __shared__ double red[256];
     double acc = 0.0;
@@ -34,7 +37,10 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, 
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) qnorm[b] = sqrt(red[0]) * (1.0 + 0x1p-40);
+    if (threadIdx.x == 0) {
+        qnorm[b] = sqrt(red[0]) * (1.0 + 0x1p-40);
+        qn2[b] = (float)red[0];
+    }
 }
 
 // Exact distance of the definition: coordinates in ascending order, one
@@ -415,8 +421,9 @@ __global__ __launch_bounds__(256) void fallback_merge_kernel(FinishArgs a) {
 }  // namespace
 
 hipError_t launch_prep_queries(const float *q, int32_t B, int32_t d, int32_t dp, float *qp,
-                               double *qnorm, int32_t *fail_count, hipStream_t s) {
-    prep_kernel<<<B, 256, 0, s>>>(q, d, dp, qp, qnorm, fail_count);
+                               double *qnorm, float *qn2, uint64_t *gthr, int32_t *fail_count,
+                               hipStream_t s) {
+    prep_kernel<<<B, 256, 0, s>>>(q, d, dp, qp, qnorm, qn2, gthr, fail_count);
     return hipGetLastError();
 }
 

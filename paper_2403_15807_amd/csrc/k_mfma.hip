@@ -1,0 +1,346 @@
+// k_mfma.hip -- MFMA screening for query batches (the N:N strategy and its
+// tensor formulation, Section 3.1: a batch of queries against a batch of
+// data vectors as one matrix product Q X^T), float32 tables.
+//
+// Workgroup = 4 waves = 64 queries (16 per wave) x one chunk of rows.
+//   - Each wave keeps its 16 queries as MFMA A-operands in registers for the
+//     whole row width (v_mfma_f32_16x16x4_f32; the coordinate order inside a
+//     lane is permuted identically for queries and rows, which leaves the
+//     dot products unchanged).
+//   - Rows arrive in tiles of 64: every thread issues its non-temporal 16-byte
+//     loads for the tile, then writes them into a padded LDS tile; rows that
+//     fail the predicate (mask strategy) are neither loaded nor computed, and
+//     a tile without any qualifying row is skipped.
+//   - Epilogue per (query, row): distance (L2: |q|^2 + |x|^2 - 2 q.x, IP: -q.x),
+//     predicate, threshold test against the query's current K-th key.
+//   - The candidates of a query are produced only by the wave that owns the
+//     query, so its top-k state is wave-private: an append buffer in global
+//     memory (L2-resident workspace) plus the sorted list, merged by the
+//     owning wave with a register bitonic sort when the buffer fills.
+#include "internal.h"
+
+namespace vrs {
+
+namespace {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float4 load_nt_f4(const float4 *p) {
+    v4u32 v = __builtin_nontemporal_load((const v4u32 *)p);
+    return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
+                       __uint_as_float(v.w));
+}
+
+constexpr int QM = 64;  // queries per workgroup
+constexpr int BR = 64;  // rows per tile
+
+// Merge the append buffer of one query into its sorted list (one wave).
+template <int E>
+__device__ void flush_one(uint64_t *list, const uint64_t *buf, int n, int K, int Kp,
+                          uint64_t *thr_out, uint64_t *gthr) {
+    const int lane = threadIdx.x & 63;
+    uint64_t v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = lane * E + e;
+        uint64_t x = KEY_INF;
+        if (i < Kp) {
+            if (i < K) x = list[i];
+        } else if (i - Kp < n) {
+            x = buf[i - Kp];
+        }
+        v[e] = x;
+    }
+    wave_sort_u64<E>(v);
+    uint64_t kth = KEY_INF;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = lane * E + e;
+        if (i < K) list[i] = v[e];
+        if (i == K - 1) kth = v[e];
+    }
+    // broadcast the K-th key from the lane that holds it, publish it as a
+    // bound for every chunk of this query and take the best bound known
+    const int src = (K - 1) / E;
+    kth = (uint64_t)__shfl((long long)kth, src);
+    if (lane == 0) {
+        uint64_t best = kth;
+        if (kth != KEY_INF) {
+            const uint64_t prev = atomicMin((unsigned long long *)gthr, (unsigned long long)kth);
+            best = prev < kth ? prev : kth;
+        }
+        *thr_out = best;
+    }
+}
+
+template <int E>
+__device__ void flush_query(uint64_t *list, const uint64_t *buf, int n, int K, int Kp,
+                            uint64_t *thr_out, uint64_t *gthr) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    flush_one<E>(list, buf, n, K, Kp, thr_out, gthr);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
+// E = (Kp + CB) / 64 keys per lane in a flush (compile-time: sets the
+// register budget of the whole kernel).
+template <int DP, int METRIC, bool GATHER, bool BATCHED, int E>
+__global__ __launch_bounds__(256, E <= 8 ? 3 : 2) void screen_mfma_f32_kernel(ScreenArgs a) {
+    constexpr int NT4 = DP / 16;           // float4 A-fragments per lane
+    constexpr int LDX = DP + 4;            // padded LDS row stride (floats)
+    constexpr int NV4 = DP / 4;            // float4 per row
+    constexpr int RP = 256 / NV4;          // rows staged per pass
+    constexpr int PASSES = BR / RP;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int q0 = blockIdx.y * QM;
+    const int chunk = blockIdx.x;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *xs = (float *)smem;                                   // [BR][LDX]
+    int *rid = (int *)(xs + BR * LDX);                           // [BR]
+    int *rq = rid + BR;                                          // [BR] qualifies
+    float *xn2 = (float *)(rq + BR);                             // [BR]
+    float *qn2 = xn2 + BR;                                       // [QM]
+    int *cnt = (int *)(qn2 + QM);                                // [QM]
+    uint64_t *thr = (uint64_t *)(((uintptr_t)(cnt + QM) + 7) & ~(uintptr_t)7);  // [QM]
+    PredDev *qpred = (PredDev *)(thr + QM);                      // [QM] (batched form)
+
+    const int K = a.K, Kp = a.Kp, CBq = a.CB;
+
+    // A fragments: lane (m = lane % 16, kq = lane / 16) of wave w holds
+    // query q0 + 16w + m, coordinates 16t + 4kq + c at (t, c).
+    const int mq = q0 + wave * 16 + (lane & 15);
+    float4 af[NT4];
+#pragma unroll
+    for (int t = 0; t < NT4; ++t)
+        af[t] = mq < a.B ? *(const float4 *)(a.qp + (int64_t)mq * DP + 16 * t + 4 * (lane >> 4))
+                         : make_float4(0.f, 0.f, 0.f, 0.f);
+    if (BATCHED && tid < QM) qpred[tid] = q0 + tid < a.B ? a.preds[q0 + tid] : PredDev{-1, {0}, {0}, {0}};
+    // per-query state (wave-private) and list initialisation
+    for (int i = lane; i < 16; i += 64) {
+        const int q = wave * 16 + i;
+        cnt[q] = 0;
+        thr[q] = KEY_INF;
+        const int qa = q0 + q;
+        qn2[q] = qa < a.B ? a.qn2[qa] : 0.0f;
+    }
+    for (int i = lane; i < 16 * K; i += 64) {
+        const int qa = q0 + wave * 16 + i / K;
+        if (qa < a.B) a.partials[((int64_t)qa * a.n_chunks + chunk) * K + (i % K)] = KEY_INF;
+    }
+    __syncthreads();
+
+    const int64_t total = GATHER ? *a.sel_count : a.n;
+    int64_t per = (total + a.n_chunks - 1) / a.n_chunks;
+    per = (per + BR - 1) / BR * BR;
+    const int64_t c0 = (int64_t)chunk * per;
+    const int64_t c1 = min(total, c0 + per);
+    const float *X = (const float *)a.rows;
+
+    // Tile pipeline: the row ids of tile t+1 (gather: sid) and the per-row
+    // record of tile t+1 (thread r < 64 holds row r's id, predicate columns
+    // and squared norm: ri_*) are fetched while tile t is multiplied, so the
+    // vector loads of a tile never wait on another load.  The vector loads
+    // themselves overlap the other workgroups resident on the CU.
+    const int sr = tid / NV4, sc = tid % NV4;  // staging: row within pass, float4 column
+    int sid[PASSES];
+    int64_t ri_row = 0;
+    bool ri_ok = false;
+    int32_t ri_av[4] = {0, 0, 0, 0};
+    float ri_n2 = 0.0f;
+
+    auto issue_ids = [&](int64_t t0) {
+#pragma unroll
+        for (int p = 0; p < PASSES; ++p) {
+            const int64_t pos = t0 + p * RP + sr;
+            sid[p] = (GATHER && pos < c1) ? a.sel_ids[pos] : 0;
+        }
+    };
+    auto issue_rowinfo = [&](int64_t t0) {
+        if (tid < BR) {
+            const int64_t pos = t0 + tid;
+            ri_ok = pos < c1;
+            ri_row = ri_ok ? (GATHER ? (int64_t)a.sel_ids[pos] : pos) : 0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                ri_av[t] = (!GATHER && !BATCHED && ri_ok && t < a.pred.nterms)
+                               ? a.attr[(int64_t)a.pred.col[t] * a.n + ri_row]
+                               : 0;
+            ri_n2 = (METRIC == VRS_L2SQ && ri_ok) ? a.norm2[ri_row] : 0.0f;
+        }
+    };
+    if (GATHER) issue_ids(c0);
+    issue_rowinfo(c0);
+
+    for (int64_t t0 = c0; t0 < c1; t0 += BR) {
+        // ---- tile t0: vector loads (rows known), per-row record -> LDS
+        float4 w[PASSES];
+#pragma unroll
+        for (int p = 0; p < PASSES; ++p) {
+            const int64_t pos = t0 + p * RP + sr;
+            const int64_t row = GATHER ? (int64_t)sid[p] : pos;
+            w[p] = pos < c1 ? load_nt_f4((const float4 *)(X + row * DP) + sc)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        if (GATHER && t0 + BR < c1) issue_ids(t0 + BR);
+        bool mine = false;
+        if (tid < BR) {
+            bool ok = ri_ok;
+            if (!GATHER && !BATCHED) {
+                ok = ok && a.pred.nterms >= 0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (t < a.pred.nterms) ok = ok && ri_av[t] >= a.pred.lo[t] && ri_av[t] <= a.pred.hi[t];
+            }
+            rid[tid] = (int)ri_row;
+            rq[tid] = ok;
+            xn2[tid] = ri_n2;
+            mine = ok;
+        }
+        if (t0 + BR < c1) issue_rowinfo(t0 + BR);
+#pragma unroll
+        for (int p = 0; p < PASSES; ++p) *(float4 *)(xs + (p * RP + sr) * LDX + 4 * sc) = w[p];
+        if (!__syncthreads_or(mine)) continue;
+
+        // ---- Q X^T for the wave's 16 queries x 64 rows
+        f4v acc[4];
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[nb] = (f4v){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < NT4; ++t) {
+            float4 bv[4];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+                bv[nb] = *(const float4 *)(xs + (nb * 16 + (lane & 15)) * LDX + 16 * t + 4 * (lane >> 4));
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) {
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[t].x, bv[nb].x, acc[nb], 0, 0, 0);
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[t].y, bv[nb].y, acc[nb], 0, 0, 0);
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[t].z, bv[nb].z, acc[nb], 0, 0, 0);
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[t].w, bv[nb].w, acc[nb], 0, 0, 0);
+            }
+        }
+
+        // ---- epilogue: lane holds queries 16w + 4(lane/16) + i, rows 16nb + lane%16
+        if ((((t0 - c0) / BR) & 15) == 15 && lane < 16) {
+            const int qa = q0 + wave * 16 + lane;
+            if (qa < a.B) {
+                const uint64_t g = __atomic_load_n((const unsigned long long *)(a.gthr + qa), __ATOMIC_RELAXED);
+                if (g < thr[wave * 16 + lane]) thr[wave * 16 + lane] = g;
+            }
+        }
+        uint64_t th[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) th[i] = thr[wave * 16 + 4 * (lane >> 4) + i];
+        float qn[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) qn[i] = qn2[wave * 16 + 4 * (lane >> 4) + i];
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            const int r = nb * 16 + (lane & 15);
+            if (!rq[r]) continue;
+            const int row = rid[r];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int q = wave * 16 + 4 * (lane >> 4) + i;
+                const int qa = q0 + q;
+                if (qa >= a.B) continue;
+                if (BATCHED && !pred_eval(qpred[q], a.attr, a.n, row)) continue;
+                const float dist = METRIC == VRS_L2SQ ? fmaf(-2.0f, acc[nb][i], qn[i] + xn2[r]) : -acc[nb][i];
+                const uint64_t key = make_key(dist, (uint32_t)row);
+                if (key < th[i]) {
+                    const int slot = atomicAdd(&cnt[q], 1);
+                    a.cbuf[((int64_t)qa * a.n_chunks + chunk) * CBq + slot] = key;
+                }
+            }
+        }
+        // ---- flush the wave's queries whose buffer could overflow next tile
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        const int myc = cnt[wave * 16 + (lane & 15)];
+        uint64_t full = __ballot(lane < 16 && myc > CBq - BR);
+        while (full) {
+            const int j = __ffsll((long long)full) - 1;
+            full &= full - 1;
+            const int q = wave * 16 + j, qa = q0 + q;
+            const int64_t base = (int64_t)qa * a.n_chunks + chunk;
+            flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, cnt[q], K, Kp, &thr[q],
+                           a.gthr + qa);
+            if (lane == 0) cnt[q] = 0;
+        }
+        __syncthreads();  // the LDS tile is reused
+    }
+    // ---- final flush of every pending buffer
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    const int myc = cnt[wave * 16 + (lane & 15)];
+    uint64_t pend = __ballot(lane < 16 && myc > 0 && q0 + wave * 16 + lane < a.B);
+    while (pend) {
+        const int j = __ffsll((long long)pend) - 1;
+        pend &= pend - 1;
+        const int q = wave * 16 + j, qa = q0 + q;
+        const int64_t base = (int64_t)qa * a.n_chunks + chunk;
+        flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, cnt[q], K, Kp, &thr[q],
+                       a.gthr + qa);
+    }
+}
+
+template <int DP, int METRIC, int E>
+hipError_t launch_e(const ScreenArgs &a, hipStream_t s) {
+    dim3 grid(a.n_chunks, (a.B + QM - 1) / QM), block(256);
+    const size_t lds = screen_mfma_lds(DP);
+    if (a.preds) {
+        auto k = screen_mfma_f32_kernel<DP, METRIC, false, true, E>;
+        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        k<<<grid, block, lds, s>>>(a);
+    } else if (a.gather) {
+        auto k = screen_mfma_f32_kernel<DP, METRIC, true, false, E>;
+        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        k<<<grid, block, lds, s>>>(a);
+    } else {
+        auto k = screen_mfma_f32_kernel<DP, METRIC, false, false, E>;
+        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        k<<<grid, block, lds, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+template <int DP, int METRIC>
+hipError_t launch_dp(const ScreenArgs &a, hipStream_t s) {
+    switch ((a.Kp + a.CB) / 64) {
+    case 4: return launch_e<DP, METRIC, 4>(a, s);
+    case 8: return launch_e<DP, METRIC, 8>(a, s);
+    case 16: return launch_e<DP, METRIC, 16>(a, s);
+    default: return launch_e<DP, METRIC, 32>(a, s);
+    }
+}
+
+template <int METRIC>
+hipError_t launch_m(const ScreenArgs &a, hipStream_t s) {
+    switch (a.dp) {
+    case 32: return launch_dp<32, METRIC>(a, s);
+    case 64: return launch_dp<64, METRIC>(a, s);
+    case 128: return launch_dp<128, METRIC>(a, s);
+    case 256: return launch_dp<256, METRIC>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+size_t screen_mfma_lds(int dp) {
+    return (size_t)BR * (dp + 4) * 4 + BR * 12 + QM * 8 + 8 + QM * 8 + QM * sizeof(PredDev) + 16;
+}
+
+// Resident workgroups per CU (register budget of the kernel, set by E).
+int screen_mfma_occupancy(int Kp, int CB) { return (Kp + CB) / 64 <= 8 ? 3 : 2; }
+
+bool screen_mfma_supported(int dp, vrs_dtype store, int Kp, int CB) {
+    const int E = (Kp + CB) / 64;
+    return store == VRS_F32 && (dp == 32 || dp == 64 || dp == 128 || dp == 256) &&
+           (E == 4 || E == 8 || E == 16 || E == 32) && (Kp + CB) == 64 * E;
+}
+
+hipError_t launch_screen_mfma(const ScreenArgs &a, hipStream_t s) {
+    return a.metric == VRS_L2SQ ? launch_m<VRS_L2SQ>(a, s) : launch_m<VRS_IP>(a, s);
+}
+
+}  // namespace vrs

@@ -228,7 +228,16 @@ __global__ __launch_bounds__(256) void screen_stream_kernel(ScreenArgs a) {
         for (int u = 0; u < U; ++u) row[u] = nrow[u];
         decide(nvd, nav, qual);
         __syncthreads();
-        if (tk.need_flush(TILE)) tk.flush(tid, 256);
+        if (tk.need_flush(TILE)) {
+            tk.flush(tid, 256);
+            // publish this chunk's K-th key per query and adopt the best one
+            if (tid < QT && qt0 + tid < a.B && thr[tid] != KEY_INF) {
+                const uint64_t prev = atomicMin((unsigned long long *)(a.gthr + qt0 + tid),
+                                                (unsigned long long)thr[tid]);
+                if (prev < thr[tid]) thr[tid] = prev;
+            }
+            __syncthreads();
+        }
     }
     if (tk.need_flush(a.CB)) tk.flush(tid, 256);  // any pending candidate
     for (int i = tid; i < QT * a.K; i += 256) {

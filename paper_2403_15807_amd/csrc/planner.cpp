@@ -12,11 +12,12 @@ namespace vrs {
 
 namespace {
 
+// VALU streaming tiles (queries per workgroup 1..8; wg_target = workgroups)
+// and MFMA tiles (64 queries per workgroup; wg_target = quarter-rounds of
+// resident workgroups: 4 = one full round, 8 = two, 2 = half a round).
 const TileCfg kTiles[] = {
-    {0, 1, 1024},
-    {0, 2, 1024},
-    {0, 4, 1024},
-    {0, 8, 1024},
+    {0, 1, 1024}, {0, 2, 1024}, {0, 4, 1024}, {0, 8, 1024},
+    {1, 64, 4}, {1, 64, 8}, {1, 64, 2}, {1, 64, 16},
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 constexpr size_t LDS_BUDGET = 64 * 1024;  // several workgroups per CU
@@ -26,6 +27,7 @@ size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 double gamma_n(double n, double u) { return n * u / (1.0 - n * u); }
 
 int screen_cb(int Kp) { return next_pow2(std::max(2 * Kp, Kp + 256)) - Kp; }
+int mfma_cb(int Kp) { return next_pow2(std::max(2 * Kp, Kp + 128)) - Kp; }
 
 // Largest tile-compatible query count per workgroup that fits the LDS budget.
 int fit_qt(int qt, int Kp, int CB, int dp) {
@@ -33,8 +35,11 @@ int fit_qt(int qt, int Kp, int CB, int dp) {
     return qt;
 }
 
+// est_rows: rows the screening kernel is expected to visit (the qualifying
+// rows for gather, every row for mask); bounds the number of row chunks so
+// that a workgroup always has enough rows to amortise its top-k state.
 Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int tile,
-               int strategy) {
+               int strategy, int64_t est_rows = -1) {
     Plan P{};
     P.strategy = strategy;
     P.tile = tile;
@@ -42,12 +47,25 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
     P.kprime = kprime_rule(kmax, t->store, kmult);
     P.K = P.kprime + 1;
     P.Kp = next_pow2(P.K);
-    P.CB = screen_cb(P.Kp);
     const TileCfg &cfg = kTiles[tile];
-    P.qt = fit_qt(std::min(cfg.qt, next_pow2(B)), P.Kp, P.CB, t->dp);
-    P.n_qtiles = (B + P.qt - 1) / P.qt;
-    int64_t max_chunks = std::max<int64_t>(1, (t->n + 1023) / 1024);
-    P.n_chunks = (int)std::max<int64_t>(1, std::min<int64_t>(max_chunks, cfg.wg_target / P.n_qtiles));
+    P.mfma = cfg.kind == 1;
+    if (P.mfma) {
+        P.CB = mfma_cb(P.Kp);
+        P.qt = cfg.qt;
+        P.n_qtiles = (B + P.qt - 1) / P.qt;
+        const int64_t slots = (int64_t)256 * screen_mfma_occupancy(P.Kp, P.CB) * cfg.wg_target / 4;
+        const int64_t rows = est_rows < 0 ? t->n : std::max<int64_t>(est_rows, 1);
+        int64_t max_chunks = std::max<int64_t>(1, rows / 4096);
+        int64_t nc = std::max<int64_t>(1, std::min<int64_t>(max_chunks, slots / P.n_qtiles));
+        if (nc >= 8) nc = nc / 8 * 8;  // whole XCD groups: a row chunk's query tiles share an L2
+        P.n_chunks = (int)nc;
+    } else {
+        P.CB = screen_cb(P.Kp);
+        P.qt = fit_qt(std::min(cfg.qt, next_pow2(B)), P.Kp, P.CB, t->dp);
+        P.n_qtiles = (B + P.qt - 1) / P.qt;
+        int64_t max_chunks = std::max<int64_t>(1, (t->n + 1023) / 1024);
+        P.n_chunks = (int)std::max<int64_t>(1, std::min<int64_t>(max_chunks, cfg.wg_target / P.n_qtiles));
+    }
     // exact fallback: about 64K rows per task, bounded scratch
     const size_t fb_cap = (size_t)256 << 20;
     int64_t want = std::max<int64_t>(1, (t->n + 65535) / 65536);
@@ -63,6 +81,9 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
     };
     P.o_qp = take((size_t)B * t->dp * 4);
     P.o_qnorm = take((size_t)B * 8);
+    P.o_qn2 = take((size_t)B * 4);
+    P.o_gthr = take((size_t)B * 8);
+    P.o_cbuf = take(P.mfma ? (size_t)B * P.n_chunks * P.CB * 8 : 0);
     P.o_bitmap = take((size_t)(t->n + 31) / 32 * 4);
     P.o_blk = take((size_t)((t->n + SEL_BLOCK_ROWS - 1) / SEL_BLOCK_ROWS) * 4);
     P.o_sel = take((size_t)t->n * 4);
@@ -80,7 +101,15 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
     return P;
 }
 
-int default_tile(int B) {
+bool tile_ok(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int tile) {
+    if (kTiles[tile].kind == 0) return true;
+    const int kmult = opts ? opts->kprime_mult : 0;
+    const int Kp = next_pow2(kprime_rule(kmax, t->store, kmult) + 1);
+    return screen_mfma_supported(t->dp, t->store, Kp, mfma_cb(Kp));
+}
+
+int default_tile(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts) {
+    if (B >= 8 && tile_ok(t, B, kmax, opts, 4)) return 4;
     if (B <= 1) return 0;
     if (B <= 2) return 1;
     if (B <= 4) return 2;
@@ -171,8 +200,13 @@ int kprime_rule(int k, vrs_dtype store, int kmult) {
 size_t plan_workspace(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts) {
     size_t m = 0;
     for (int tile = 0; tile < kNumTiles; ++tile)
-        m = std::max(m, make_plan(t, B, kmax, opts, tile, VRS_STRATEGY_GATHER).total);
+        if (tile_ok(t, B, kmax, opts, tile))
+            m = std::max(m, make_plan(t, B, kmax, opts, tile, VRS_STRATEGY_GATHER).total);
     return m;
+}
+
+bool planner_tile_ok(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int tile) {
+    return tile_ok(t, B, kmax, opts, tile);
 }
 
 hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &p,
@@ -180,21 +214,26 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
                     int64_t *out_idx, float *out_dist, void *ws, const vrs_opts *opts,
                     hipStream_t s) {
     const bool batched = preds != nullptr;
-    int tile = (opts && opts->tile >= 0) ? opts->tile : default_tile(B);
+    int tile = (opts && opts->tile >= 0) ? opts->tile : default_tile(t, B, k, opts);
+    if (!tile_ok(t, B, k, opts, tile)) tile = default_tile(t, B, k, opts);
     int strategy = opts ? opts->strategy : VRS_STRATEGY_AUTO;
     if (batched) strategy = VRS_STRATEGY_MASK;  // per-query predicates are checked per row
+    const double est_sel = batched ? 1.0 : estimate_selectivity(t, p);
     if (strategy == VRS_STRATEGY_AUTO) {
-        double sel = estimate_selectivity(t, p);
-        strategy = sel < 0.5 ? VRS_STRATEGY_GATHER : VRS_STRATEGY_MASK;
+        strategy = est_sel < 0.5 ? VRS_STRATEGY_GATHER : VRS_STRATEGY_MASK;
         if (p.nterms == 0) strategy = VRS_STRATEGY_MASK;
     }
-    Plan P = make_plan(t, B, k, opts, tile, strategy);
+    const int64_t est_rows =
+        strategy == VRS_STRATEGY_GATHER ? (int64_t)(est_sel * (double)t->n * 1.25) + 4096 : t->n;
+    Plan P = make_plan(t, B, k, opts, tile, strategy, est_rows);
     char *w = (char *)ws;
     float *qp = (float *)(w + P.o_qp);
     double *qnorm = (double *)(w + P.o_qnorm);
+    float *qn2 = (float *)(w + P.o_qn2);
+    uint64_t *gthr = (uint64_t *)(w + P.o_gthr);
     int32_t *fail_count = (int32_t *)(w + P.o_failcnt);
     prof_begin(0, s);
-    hipError_t e = launch_prep_queries(q, B, t->d, t->dp, qp, qnorm, fail_count, s);
+    hipError_t e = launch_prep_queries(q, B, t->d, t->dp, qp, qnorm, qn2, gthr, fail_count, s);
     if (e != hipSuccess) return e;
     PredDev *pdev = (PredDev *)(w + P.o_preds);
     int32_t *kc = (int32_t *)(w + P.o_kc), *kps = (int32_t *)(w + P.o_kps);
@@ -227,6 +266,10 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     sa.sel_count = selcnt;
     sa.gather = gather;
     sa.qp = qp;
+    sa.qn2 = qn2;
+    sa.norm2 = t->norm2;
+    sa.cbuf = (uint64_t *)(w + P.o_cbuf);
+    sa.gthr = gthr;
     sa.B = B;
     sa.metric = metric;
     sa.K = P.K;
@@ -235,7 +278,7 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     sa.n_chunks = P.n_chunks;
     sa.partials = (uint64_t *)(w + P.o_part);
     prof_begin(2, s);
-    e = launch_screen_stream(sa, P.qt, s);
+    e = P.mfma ? launch_screen_mfma(sa, s) : launch_screen_stream(sa, P.qt, s);
     if (e != hipSuccess) return e;
     prof_end(2, s);
 
@@ -263,15 +306,18 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     fa.partials = sa.partials;
     fa.merge_mid = (uint64_t *)(w + P.o_mid);
     fa.merged = (uint64_t *)(w + P.o_merged);
-    // Screening error bound (VALU kernel, FP32 accumulation in any order):
-    //   L2SQ: sum of dp non-negative rounded terms -> relative gamma_{dp+3};
-    //   IP:   |error| <= gamma_{dp+3} * ||q|| * max_i ||x_i||.
-    // Both sides of the certificate also carry the FP64 sum's own error.
+    // Screening error bound, FP32 accumulation in any order (both sides of the
+    // certificate also carry the FP64 sum's own error):
+    //   VALU L2SQ: sum of dp non-negative rounded terms -> relative gamma_{dp+3};
+    //   MFMA L2SQ: |q|^2 + |x|^2 - 2 q.x with every product possibly rounded
+    //              -> absolute gamma_{dp+6} * (|q| + max|x|)^2;
+    //   IP:        |error| <= gamma_{dp+3} * |q| * max|x|.
     const double u32 = ldexp(1.0, -24), u64 = ldexp(1.0, -53);
     const double g = (gamma_n(t->dp + 3, u32) + gamma_n(t->dp + 3, u64)) * 1.001;
-    fa.rel = metric == VRS_L2SQ ? g : 0.0;
-    fa.abs_ip = metric == VRS_IP ? g : 0.0;
-    fa.abs_l2 = 0.0;
+    const double g6 = (gamma_n(t->dp + 6, u32) + gamma_n(t->dp + 3, u64)) * 1.001;
+    fa.rel = (metric == VRS_L2SQ && !P.mfma) ? g : 0.0;
+    fa.abs_ip = metric == VRS_IP ? g6 : 0.0;
+    fa.abs_l2 = (metric == VRS_L2SQ && P.mfma) ? g6 : 0.0;
     fa.max_norm = t->max_norm;
     fa.fail_list = (int32_t *)(w + P.o_fail);
     fa.fail_count = fail_count;

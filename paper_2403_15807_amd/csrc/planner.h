@@ -24,15 +24,18 @@ int kprime_rule(int k, vrs_dtype store, int kmult);
 struct Plan {
     int strategy;        // VRS_STRATEGY_MASK or VRS_STRATEGY_GATHER
     int tile;            // index into the tile table
+    bool mfma;           // MFMA screening kernel
     int qt, n_qtiles, n_chunks;
     int kprime, K, Kp, CB;
     int fb_chunks, fb_rows_per_chunk;
     // workspace offsets (bytes)
-    size_t o_qp, o_qnorm, o_bitmap, o_blk, o_sel, o_selcnt, o_part, o_mid, o_merged, o_fail,
+    size_t o_qp, o_qnorm, o_qn2, o_gthr, o_cbuf, o_bitmap, o_blk, o_sel, o_selcnt, o_part, o_mid, o_merged, o_fail,
         o_failcnt, o_fb, o_preds, o_kc, o_kps, total;
 };
 
 double estimate_selectivity(const vrs_table_s *t, const PredDev &p);
+
+bool planner_tile_ok(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int tile);
 
 // Workspace bytes covering every plan the planner may pick for (B, k_max, opts).
 size_t plan_workspace(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts);

@@ -115,7 +115,7 @@ def cfg0():
 
 
 @pytest.mark.parametrize("strategy", [vrs.STRATEGY_AUTO, vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER])
-@pytest.mark.parametrize("tile", [-1, 0, 1, 2, 3])
+@pytest.mark.parametrize("tile", list(range(-1, 8)))
 def test_config0_l2_top10(cfg0, strategy, tile):
     x, a, q, T, ot, pred, ref = cfg0
     r = T.scan_topk(_dev(q), pred, 10, vrs.L2SQ, strategy=strategy, tile=tile)
@@ -156,6 +156,25 @@ def test_ragged_shapes_and_k(metric, k):
     for strategy in (vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER):
         r = T.scan_topk(_dev(q), pred, k, metric, strategy=strategy)
         _check(r, ref, f"metric {metric} k {k} strategy {strategy}")
+
+
+@pytest.mark.parametrize("B", [8, 70, 130])
+@pytest.mark.parametrize("metric", [vrs.L2SQ, vrs.IP])
+def test_mfma_query_tiles(B, metric):
+    # several 64-query tiles with a ragged last tile, ragged row count
+    n, d = 50001, 128
+    x = inputs.table(4, n, d, 200)
+    a = inputs.attributes(4, n, 2, 1000)
+    q = inputs.queries(4, B, d, 200)
+    T = vrs.Table(_dev(x), _dev(a), normalize=(metric == vrs.IP))
+    ot = O.Table.build(x, a, O.F32, normalize=(metric == vrs.IP))
+    pred = [(0, 0, 600), (1, 100, 1000)]
+    for k in (1, 10, 100):
+        ref = O.scan_topk(ot, q, pred, k, metric)
+        for strategy in (vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER):
+            for tile in (4, 5, 6, 7):
+                r = T.scan_topk(_dev(q), pred, k, metric, strategy=strategy, tile=tile)
+                _check(r, ref, f"B {B} metric {metric} k {k} strategy {strategy} tile {tile}")
 
 
 def test_fewer_qualifying_rows_than_k_and_empty():
