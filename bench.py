@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MFMA_F32_PEAK_TFLOPS = 157.3
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
 def log(msg):
@@ -42,10 +43,16 @@ def main():
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--d", type=int, default=128)
     ap.add_argument("--clusters", type=int, default=1000)
+    ap.add_argument("--cfg", type=int, default=-1,
+                    help="seed configuration index (default: 1 for float32, 2 for bf16/fp8)")
     ap.add_argument("--batch", type=int, default=1)
     ap.add_argument("--sel", type=float, default=1.0)
     ap.add_argument("--k", type=int, default=100)
     ap.add_argument("--metric", choices=["l2", "ip"], default="l2")
+    ap.add_argument("--store", choices=["f32", "bf16", "fp8"], default="f32")
+    ap.add_argument("--recall", action="store_true",
+                    help="precision form: recall@k and max distance error of the stored-precision "
+                         "result against the FP64 oracle on the float32 rows (sampled queries)")
     ap.add_argument("--strategy", choices=["auto", "mask", "gather"], default="auto")
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--cpu-queries", type=int, default=0, help="oracle sample size (0 = #cores)")
@@ -68,7 +75,7 @@ def main():
     dev = torch.device("cuda:0")
     metric = vrs.L2SQ if args.metric == "l2" else vrs.IP
     strategy = {"auto": vrs.STRATEGY_AUTO, "mask": vrs.STRATEGY_MASK, "gather": vrs.STRATEGY_GATHER}[args.strategy]
-    cfg_id = 1
+    cfg_id = args.cfg if args.cfg >= 0 else (1 if args.store == "f32" else 2)
     t0 = time.time()
     x = inputs.table(cfg_id, args.n, args.d, args.clusters)
     attr = inputs.attributes(cfg_id, args.n, 2, 10 ** 6)
@@ -80,7 +87,8 @@ def main():
     xd = torch.from_numpy(x).to(dev)
     ad = torch.from_numpy(attr).to(dev)
     t0 = time.time()
-    T = vrs.Table(xd, ad, normalize=(metric == vrs.IP))
+    store = {"f32": vrs.F32, "bf16": vrs.BF16, "fp8": vrs.FP8E4M3}[args.store]
+    T = vrs.Table(xd, ad, store=store, normalize=(metric == vrs.IP))
     torch.cuda.synchronize()
     log(f"table built in {time.time() - t0:.2f}s")
     del xd
@@ -123,18 +131,19 @@ def main():
     # roofline of the dominant kernel (screening), algorithmic work per launch
     used_gather = stages["select"][1] > 0
     screen_ms = stages["screen"][0] / max(1, stages["screen"][1])
-    row_bytes = args.d * 4
+    row_bytes = args.d * {"f32": 4, "bf16": 2, "fp8": 1}[args.store] + (4 if args.store == "fp8" else 0)
     bytes_alg = n_sel * row_bytes + (n_sel * 4 if used_gather else args.n * 4 * len(pred)) + B * args.d * 4
     flops_alg = 2.0 * B * n_sel * args.d
     hbm_gbs = bytes_alg / (screen_ms * 1e-3) / 1e9
     tflops = flops_alg / (screen_ms * 1e-3) / 1e12
     intensity = flops_alg / bytes_alg
-    if intensity < MFMA_F32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9):
+    mfma_peak = MFMA_F32_PEAK_TFLOPS if args.store == "f32" else MFMA_BF16_PEAK_TFLOPS
+    if intensity < mfma_peak * 1e12 / (HBM_PEAK_GBS * 1e9):
         roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
     else:
-        roof = {"bound": "mfma", "achieved": round(tflops, 2), "peak": MFMA_F32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(tflops / MFMA_F32_PEAK_TFLOPS, 4)}
+        roof = {"bound": "mfma", "achieved": round(tflops, 2), "peak": mfma_peak,
+                "unit": "TFLOP/s", "frac": round(tflops / mfma_peak, 4)}
     roof["traffic"] = None
     roof["kernel"] = "screen"
     roof["kernel_ms"] = round(screen_ms, 4)
@@ -156,7 +165,8 @@ def main():
         import oracle as O
         cores = len(os.sched_getaffinity(0))
         nq = args.cpu_queries or min(cores, 16)
-        ot = O.Table.build(x, attr, O.F32, normalize=(metric == vrs.IP))
+        ot = O.Table.build(x, attr, {"f32": O.F32, "bf16": O.BF16, "fp8": O.FP8}[args.store],
+                           normalize=(metric == vrs.IP))
         qs = np.ascontiguousarray(q[np.arange(nq) % B])
         log(f"oracle: {nq} queries on {cores} cores")
         t0 = time.perf_counter()
@@ -170,6 +180,26 @@ def main():
         cpu["gpu_ids_match_oracle"] = bool(same)
         log(f"oracle done in {cpu_s:.1f}s, ids match: {same}")
 
+    precision = None
+    if args.recall and args.store != "f32":
+        import oracle as O
+        cores = len(os.sched_getaffinity(0))
+        nq = min(B, args.cpu_queries or cores)
+        qs = np.ascontiguousarray(q[:nq])
+        mo = O.L2SQ if metric == vrs.L2SQ else O.IP
+        t_r = O.Table.build(x, attr, O.F32, normalize=(metric == vrs.IP))
+        r2 = O.scan_topk(t_r, qs, pred, k, mo, nthreads=cores)
+        gi = idx.cpu().numpy()[:nq]
+        gd = dist.cpu().numpy()[:nq].astype(np.float64)
+        recall = float(np.mean([len(set(gi[i][gi[i] >= 0]) & set(r2[0][i][r2[0][i] >= 0])) /
+                                max(1, int((r2[0][i] >= 0).sum())) for i in range(nq)]))
+        fin = np.isfinite(r2[2]) & np.isfinite(gd)
+        maxerr = float(np.max(np.abs(gd[fin] - r2[2][fin]))) if fin.any() else 0.0
+        precision = {"queries": nq, "recall_at_k_vs_fp32_rows": round(recall, 4),
+                     "max_abs_dist_error_vs_fp32_rows": maxerr,
+                     "note": "ids are exact for the stored rows; this compares with the float32 rows"}
+        log(f"recall@{k} vs float32 rows: {recall:.4f}, max |dist err| {maxerr:.3g}")
+
     rec = {
         "metric": "filtered exact top-k queries/s (N=10M,d=128)",
         "value": round(qps, 2),
@@ -181,9 +211,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.store,
         "data": "synthetic",
-        "config": {"workload": f"clustered-gaussian N={args.n} d={args.d} top-{k} {args.metric}",
+        "config": {"workload": f"clustered-gaussian N={args.n} d={args.d} {args.store} top-{k} {args.metric}",
                    "batch": B, "selectivity_target": args.sel, "selectivity": round(realized, 6),
                    "strategy": "gather" if used_gather else "mask", "k": k},
         "roofline": roof,
@@ -191,6 +221,8 @@ def main():
         "stages_ms_per_step": {s: round(v[0] / max(1, args.steps), 4) for s, v in stages.items()},
         "certified_frac": certified,
     }
+    if precision is not None:
+        rec["precision"] = precision
     print(json.dumps(rec), flush=True)
 
 

@@ -48,9 +48,9 @@ hipError_t launch_select(const int32_t *attr, int64_t n, const PredDev &p, uint3
 
 // ---- query preparation (k_finish.hip)
 hipError_t launch_prep_queries(const float *q, int32_t B, int32_t d, int32_t dp, float *qp,
-                               double *qnorm, float *qn2, uint64_t *gthr, int32_t *fail_count,
-                               hipStream_t s);
-int screen_mfma_occupancy(int Kp, int CB);
+                               double *qnorm, float *qn2, uint16_t *qhl, uint64_t *gthr,
+                               int32_t *fail_count, hipStream_t s);
+int screen_mfma_occupancy(int Kp, int CB, int qm);
 hipError_t launch_prep_batched(const vrs_pred *preds, const int32_t *ks, int32_t B, int32_t kmax,
                                int32_t n_attr, int kmult, int f32_rule, PredDev *out,
                                int32_t *kc, int32_t *kps, hipStream_t s);
@@ -71,6 +71,7 @@ struct ScreenArgs {
     int gather;
     const float *qp;               // [B][dp]
     const float *qn2;              // [B] ||q||^2 (float32 of the FP64 sum)
+    const uint16_t *qhl;           // [B][2][dp] bfloat16 hi/lo split of the queries
     const float *norm2;            // [n] ||x_i||^2 of stored rows
     int32_t B;
     int metric;
@@ -82,8 +83,11 @@ struct ScreenArgs {
 };
 hipError_t launch_screen_stream(const ScreenArgs &a, int qt, hipStream_t s);
 size_t screen_stream_lds(int qt, int Kp, int CB, int dp);
-hipError_t launch_screen_mfma(const ScreenArgs &a, hipStream_t s);
-size_t screen_mfma_lds(int dp);
+hipError_t launch_screen_mfma(const ScreenArgs &a, int qm, hipStream_t s);
+size_t screen_mfma_lds(int dp, int qm);
+hipError_t launch_screen_mfma_bf16(const ScreenArgs &a, hipStream_t s);
+size_t screen_mfma_bf16_lds();
+bool screen_mfma_bf16_supported(int dp, vrs_dtype store, int metric, int Kp, int CB);
 bool screen_mfma_supported(int dp, vrs_dtype store, int Kp, int CB);
 
 // ---- merge, rerank, fallback (k_finish.hip)

@@ -19,6 +19,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, 
                                                    float *__restrict__ qp,
                                                    double *__restrict__ qnorm,
                                                    float *__restrict__ qn2,
+                                                   uint16_t *__restrict__ qhl,
                                                    uint64_t *__restrict__ gthr,
                                                    int32_t *__restrict__ fail_count) {
     const int b = blockIdx.x;
@@ -30,6 +31,15 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, 
         float v = j < d ? q[(int64_t)b * d + j] : 0.0f;
         qp[(int64_t)b * dp + j] = v;
         acc += (double)v * (double)v;
+        if (qhl) {  // bfloat16 hi/lo split (round to nearest-even both times)
+            const uint32_t u = __float_as_uint(v);
+            const uint32_t hi = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+            const float rest = v - __uint_as_float(hi << 16);  // exact
+            const uint32_t r = __float_as_uint(rest);
+            const uint32_t lo = (r + 0x7fffu + ((r >> 16) & 1u)) >> 16;
+            qhl[((int64_t)b * 2) * dp + j] = (uint16_t)hi;
+            qhl[((int64_t)b * 2 + 1) * dp + j] = (uint16_t)lo;
+        }
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -421,9 +431,9 @@ __global__ __launch_bounds__(256) void fallback_merge_kernel(FinishArgs a) {
 }  // namespace
 
 hipError_t launch_prep_queries(const float *q, int32_t B, int32_t d, int32_t dp, float *qp,
-                               double *qnorm, float *qn2, uint64_t *gthr, int32_t *fail_count,
-                               hipStream_t s) {
-    prep_kernel<<<B, 256, 0, s>>>(q, d, dp, qp, qnorm, qn2, gthr, fail_count);
+                               double *qnorm, float *qn2, uint16_t *qhl, uint64_t *gthr,
+                               int32_t *fail_count, hipStream_t s) {
+    prep_kernel<<<B, 256, 0, s>>>(q, d, dp, qp, qnorm, qn2, qhl, gthr, fail_count);
     return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@
 //     memory (L2-resident workspace) plus the sorted list, merged by the
 //     owning wave with a register bitonic sort when the buffer fills.
 #include "internal.h"
+#include "wave_topk.h"
 
 namespace vrs {
 
@@ -32,61 +33,15 @@ __device__ __forceinline__ float4 load_nt_f4(const float4 *p) {
                        __uint_as_float(v.w));
 }
 
-constexpr int QM = 64;  // queries per workgroup
 constexpr int BR = 64;  // rows per tile
 
-// Merge the append buffer of one query into its sorted list (one wave).
-template <int E>
-__device__ void flush_one(uint64_t *list, const uint64_t *buf, int n, int K, int Kp,
-                          uint64_t *thr_out, uint64_t *gthr) {
-    const int lane = threadIdx.x & 63;
-    uint64_t v[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = lane * E + e;
-        uint64_t x = KEY_INF;
-        if (i < Kp) {
-            if (i < K) x = list[i];
-        } else if (i - Kp < n) {
-            x = buf[i - Kp];
-        }
-        v[e] = x;
-    }
-    wave_sort_u64<E>(v);
-    uint64_t kth = KEY_INF;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = lane * E + e;
-        if (i < K) list[i] = v[e];
-        if (i == K - 1) kth = v[e];
-    }
-    // broadcast the K-th key from the lane that holds it, publish it as a
-    // bound for every chunk of this query and take the best bound known
-    const int src = (K - 1) / E;
-    kth = (uint64_t)__shfl((long long)kth, src);
-    if (lane == 0) {
-        uint64_t best = kth;
-        if (kth != KEY_INF) {
-            const uint64_t prev = atomicMin((unsigned long long *)gthr, (unsigned long long)kth);
-            best = prev < kth ? prev : kth;
-        }
-        *thr_out = best;
-    }
-}
-
-template <int E>
-__device__ void flush_query(uint64_t *list, const uint64_t *buf, int n, int K, int Kp,
-                            uint64_t *thr_out, uint64_t *gthr) {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    flush_one<E>(list, buf, n, K, Kp, thr_out, gthr);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-}
-
-// E = (Kp + CB) / 64 keys per lane in a flush (compile-time: sets the
-// register budget of the whole kernel).
-template <int DP, int METRIC, bool GATHER, bool BATCHED, int E>
-__global__ __launch_bounds__(256, E <= 8 ? 3 : 2) void screen_mfma_f32_kernel(ScreenArgs a) {
-    constexpr int NT4 = DP / 16;           // float4 A-fragments per lane
+// MB = 16-query blocks per wave (a workgroup holds QM = 64 * MB queries); a
+// B-operand read from LDS feeds MB MFMAs.
+template <int DP, int METRIC, bool GATHER, bool BATCHED, int E, int MB>
+__global__ __launch_bounds__(256, (E <= 8 && MB == 1) ? 3 : 2) void screen_mfma_f32_kernel(ScreenArgs a) {
+    constexpr int QM = 64 * MB;
+    constexpr int QW = 16 * MB;            // queries per wave
+    constexpr int NT4 = DP / 16;           // float4 A-fragments per lane per block
     constexpr int LDX = DP + 4;            // padded LDS row stride (floats)
     constexpr int NV4 = DP / 4;            // float4 per row
     constexpr int RP = 256 / NV4;          // rows staged per pass
@@ -107,25 +62,28 @@ __global__ __launch_bounds__(256, E <= 8 ? 3 : 2) void screen_mfma_f32_kernel(Sc
 
     const int K = a.K, Kp = a.Kp, CBq = a.CB;
 
-    // A fragments: lane (m = lane % 16, kq = lane / 16) of wave w holds
-    // query q0 + 16w + m, coordinates 16t + 4kq + c at (t, c).
-    const int mq = q0 + wave * 16 + (lane & 15);
-    float4 af[NT4];
+    // A fragments: lane (m = lane % 16, kq = lane / 16) of wave w holds, for
+    // block mb, query q0 + QW*w + 16*mb + m at coordinates 16t + 4kq + c.
+    float4 af[MB][NT4];
 #pragma unroll
-    for (int t = 0; t < NT4; ++t)
-        af[t] = mq < a.B ? *(const float4 *)(a.qp + (int64_t)mq * DP + 16 * t + 4 * (lane >> 4))
-                         : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int mb = 0; mb < MB; ++mb) {
+        const int mq = q0 + wave * QW + mb * 16 + (lane & 15);
+#pragma unroll
+        for (int t = 0; t < NT4; ++t)
+            af[mb][t] = mq < a.B ? *(const float4 *)(a.qp + (int64_t)mq * DP + 16 * t + 4 * (lane >> 4))
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     if (BATCHED && tid < QM) qpred[tid] = q0 + tid < a.B ? a.preds[q0 + tid] : PredDev{-1, {0}, {0}, {0}};
     // per-query state (wave-private) and list initialisation
-    for (int i = lane; i < 16; i += 64) {
-        const int q = wave * 16 + i;
+    for (int i = lane; i < QW; i += 64) {
+        const int q = wave * QW + i;
         cnt[q] = 0;
         thr[q] = KEY_INF;
         const int qa = q0 + q;
         qn2[q] = qa < a.B ? a.qn2[qa] : 0.0f;
     }
-    for (int i = lane; i < 16 * K; i += 64) {
-        const int qa = q0 + wave * 16 + i / K;
+    for (int i = lane; i < QW * K; i += 64) {
+        const int qa = q0 + wave * QW + i / K;
         if (qa < a.B) a.partials[((int64_t)qa * a.n_chunks + chunk) * K + (i % K)] = KEY_INF;
     }
     __syncthreads();
@@ -202,136 +160,152 @@ __global__ __launch_bounds__(256, E <= 8 ? 3 : 2) void screen_mfma_f32_kernel(Sc
         for (int p = 0; p < PASSES; ++p) *(float4 *)(xs + (p * RP + sr) * LDX + 4 * sc) = w[p];
         if (!__syncthreads_or(mine)) continue;
 
-        // ---- Q X^T for the wave's 16 queries x 64 rows
-        f4v acc[4];
+        // ---- Q X^T for the wave's QW queries x 64 rows
+        f4v acc[MB][4];
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) acc[nb] = (f4v){0.f, 0.f, 0.f, 0.f};
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = (f4v){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < NT4; ++t) {
             float4 bv[4];
 #pragma unroll
             for (int nb = 0; nb < 4; ++nb)
                 bv[nb] = *(const float4 *)(xs + (nb * 16 + (lane & 15)) * LDX + 16 * t + 4 * (lane >> 4));
+            // independent accumulators back to back: no MFMA waits on the
+            // result of the previous one
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb) {
-                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[t].x, bv[nb].x, acc[nb], 0, 0, 0);
-                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[t].y, bv[nb].y, acc[nb], 0, 0, 0);
-                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[t].z, bv[nb].z, acc[nb], 0, 0, 0);
-                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[t].w, bv[nb].w, acc[nb], 0, 0, 0);
-            }
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < 4; ++nb)
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb][t][c], bv[nb][c], acc[mb][nb], 0, 0, 0);
         }
 
-        // ---- epilogue: lane holds queries 16w + 4(lane/16) + i, rows 16nb + lane%16
-        if ((((t0 - c0) / BR) & 15) == 15 && lane < 16) {
-            const int qa = q0 + wave * 16 + lane;
-            if (qa < a.B) {
-                const uint64_t g = __atomic_load_n((const unsigned long long *)(a.gthr + qa), __ATOMIC_RELAXED);
-                if (g < thr[wave * 16 + lane]) thr[wave * 16 + lane] = g;
+        // ---- epilogue: lane holds queries QW*w + 16mb + 4(lane/16) + i, rows 16nb + lane%16
+        if ((((t0 - c0) / BR) & 15) == 15) {
+            for (int i = lane; i < QW; i += 64) {
+                const int qa = q0 + wave * QW + i;
+                if (qa < a.B) {
+                    const uint64_t g = __atomic_load_n((const unsigned long long *)(a.gthr + qa), __ATOMIC_RELAXED);
+                    if (g < thr[wave * QW + i]) thr[wave * QW + i] = g;
+                }
             }
         }
-        uint64_t th[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) th[i] = thr[wave * 16 + 4 * (lane >> 4) + i];
-        float qn[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) qn[i] = qn2[wave * 16 + 4 * (lane >> 4) + i];
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            const int r = nb * 16 + (lane & 15);
-            if (!rq[r]) continue;
-            const int row = rid[r];
+        for (int mb = 0; mb < MB; ++mb) {
+            const int qb = wave * QW + mb * 16 + 4 * (lane >> 4);
+            uint64_t th[4];
+            float qn[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int q = wave * 16 + 4 * (lane >> 4) + i;
-                const int qa = q0 + q;
-                if (qa >= a.B) continue;
-                if (BATCHED && !pred_eval(qpred[q], a.attr, a.n, row)) continue;
-                const float dist = METRIC == VRS_L2SQ ? fmaf(-2.0f, acc[nb][i], qn[i] + xn2[r]) : -acc[nb][i];
-                const uint64_t key = make_key(dist, (uint32_t)row);
-                if (key < th[i]) {
-                    const int slot = atomicAdd(&cnt[q], 1);
-                    a.cbuf[((int64_t)qa * a.n_chunks + chunk) * CBq + slot] = key;
+                th[i] = thr[qb + i];
+                qn[i] = qn2[qb + i];
+            }
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) {
+                const int r = nb * 16 + (lane & 15);
+                if (!rq[r]) continue;
+                const int row = rid[r];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int q = qb + i;
+                    const int qa = q0 + q;
+                    if (qa >= a.B) continue;
+                    if (BATCHED && !pred_eval(qpred[q], a.attr, a.n, row)) continue;
+                    const float dist = METRIC == VRS_L2SQ ? fmaf(-2.0f, acc[mb][nb][i], qn[i] + xn2[r]) : -acc[mb][nb][i];
+                    const uint64_t key = make_key(dist, (uint32_t)row);
+                    if (key < th[i]) {
+                        const int slot = atomicAdd(&cnt[q], 1);
+                        a.cbuf[((int64_t)qa * a.n_chunks + chunk) * CBq + slot] = key;
+                    }
                 }
             }
         }
         // ---- flush the wave's queries whose buffer could overflow next tile
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        const int myc = cnt[wave * 16 + (lane & 15)];
-        uint64_t full = __ballot(lane < 16 && myc > CBq - BR);
-        while (full) {
-            const int j = __ffsll((long long)full) - 1;
-            full &= full - 1;
-            const int q = wave * 16 + j, qa = q0 + q;
-            const int64_t base = (int64_t)qa * a.n_chunks + chunk;
-            flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, cnt[q], K, Kp, &thr[q],
-                           a.gthr + qa);
-            if (lane == 0) cnt[q] = 0;
+        {
+            const int myc = lane < QW ? cnt[wave * QW + lane] : 0;
+            uint64_t full = __ballot(lane < QW && myc > CBq - BR);
+            while (full) {
+                const int j = __ffsll((long long)full) - 1;
+                full &= full - 1;
+                const int q = wave * QW + j, qa = q0 + q;
+                const int64_t base = (int64_t)qa * a.n_chunks + chunk;
+                flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, cnt[q], K, Kp, &thr[q],
+                               a.gthr + qa);
+                if (lane == 0) cnt[q] = 0;
+            }
         }
         __syncthreads();  // the LDS tile is reused
     }
     // ---- final flush of every pending buffer
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    const int myc = cnt[wave * 16 + (lane & 15)];
-    uint64_t pend = __ballot(lane < 16 && myc > 0 && q0 + wave * 16 + lane < a.B);
+    const int myc = lane < QW ? cnt[wave * QW + lane] : 0;
+    uint64_t pend = __ballot(lane < QW && myc > 0 && q0 + wave * QW + lane < a.B);
     while (pend) {
         const int j = __ffsll((long long)pend) - 1;
         pend &= pend - 1;
-        const int q = wave * 16 + j, qa = q0 + q;
+        const int q = wave * QW + j, qa = q0 + q;
         const int64_t base = (int64_t)qa * a.n_chunks + chunk;
         flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, cnt[q], K, Kp, &thr[q],
                        a.gthr + qa);
     }
 }
 
-template <int DP, int METRIC, int E>
+template <int DP, int METRIC, int E, int MB>
 hipError_t launch_e(const ScreenArgs &a, hipStream_t s) {
+    constexpr int QM = 64 * MB;
     dim3 grid(a.n_chunks, (a.B + QM - 1) / QM), block(256);
-    const size_t lds = screen_mfma_lds(DP);
+    const size_t lds = screen_mfma_lds(DP, QM);
     if (a.preds) {
-        auto k = screen_mfma_f32_kernel<DP, METRIC, false, true, E>;
+        auto k = screen_mfma_f32_kernel<DP, METRIC, false, true, E, MB>;
         hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         k<<<grid, block, lds, s>>>(a);
     } else if (a.gather) {
-        auto k = screen_mfma_f32_kernel<DP, METRIC, true, false, E>;
+        auto k = screen_mfma_f32_kernel<DP, METRIC, true, false, E, MB>;
         hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         k<<<grid, block, lds, s>>>(a);
     } else {
-        auto k = screen_mfma_f32_kernel<DP, METRIC, false, false, E>;
+        auto k = screen_mfma_f32_kernel<DP, METRIC, false, false, E, MB>;
         hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         k<<<grid, block, lds, s>>>(a);
     }
     return hipGetLastError();
 }
 
-template <int DP, int METRIC>
+template <int DP, int METRIC, int MB>
 hipError_t launch_dp(const ScreenArgs &a, hipStream_t s) {
     switch ((a.Kp + a.CB) / 64) {
-    case 4: return launch_e<DP, METRIC, 4>(a, s);
-    case 8: return launch_e<DP, METRIC, 8>(a, s);
-    case 16: return launch_e<DP, METRIC, 16>(a, s);
-    default: return launch_e<DP, METRIC, 32>(a, s);
+    case 4: return launch_e<DP, METRIC, 4, MB>(a, s);
+    case 8: return launch_e<DP, METRIC, 8, MB>(a, s);
+    case 16: return launch_e<DP, METRIC, 16, MB>(a, s);
+    default: return launch_e<DP, METRIC, 32, MB>(a, s);
     }
 }
 
-template <int METRIC>
+template <int METRIC, int MB>
 hipError_t launch_m(const ScreenArgs &a, hipStream_t s) {
     switch (a.dp) {
-    case 32: return launch_dp<32, METRIC>(a, s);
-    case 64: return launch_dp<64, METRIC>(a, s);
-    case 128: return launch_dp<128, METRIC>(a, s);
-    case 256: return launch_dp<256, METRIC>(a, s);
+    case 32: return launch_dp<32, METRIC, MB>(a, s);
+    case 64: return launch_dp<64, METRIC, MB>(a, s);
+    case 128: return launch_dp<128, METRIC, MB>(a, s);
+    case 256: return launch_dp<256, METRIC, MB>(a, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-size_t screen_mfma_lds(int dp) {
-    return (size_t)BR * (dp + 4) * 4 + BR * 12 + QM * 8 + 8 + QM * 8 + QM * sizeof(PredDev) + 16;
+size_t screen_mfma_lds(int dp, int qm) {
+    return (size_t)BR * (dp + 4) * 4 + BR * 12 + qm * 8 + 8 + qm * 8 + qm * sizeof(PredDev) + 16;
 }
 
-// Resident workgroups per CU (register budget of the kernel, set by E).
-int screen_mfma_occupancy(int Kp, int CB) { return (Kp + CB) / 64 <= 8 ? 3 : 2; }
+// Resident workgroups per CU (register budget of the kernel, set by E and MB).
+int screen_mfma_occupancy(int Kp, int CB, int qm) {
+    return ((Kp + CB) / 64 <= 8 && qm == 64) ? 3 : 2;
+}
 
 bool screen_mfma_supported(int dp, vrs_dtype store, int Kp, int CB) {
     const int E = (Kp + CB) / 64;
@@ -339,8 +313,10 @@ bool screen_mfma_supported(int dp, vrs_dtype store, int Kp, int CB) {
            (E == 4 || E == 8 || E == 16 || E == 32) && (Kp + CB) == 64 * E;
 }
 
-hipError_t launch_screen_mfma(const ScreenArgs &a, hipStream_t s) {
-    return a.metric == VRS_L2SQ ? launch_m<VRS_L2SQ>(a, s) : launch_m<VRS_IP>(a, s);
+hipError_t launch_screen_mfma(const ScreenArgs &a, int qm, hipStream_t s) {
+    if (qm == 128)
+        return a.metric == VRS_L2SQ ? launch_m<VRS_L2SQ, 2>(a, s) : launch_m<VRS_IP, 2>(a, s);
+    return a.metric == VRS_L2SQ ? launch_m<VRS_L2SQ, 1>(a, s) : launch_m<VRS_IP, 1>(a, s);
 }
 
 }  // namespace vrs

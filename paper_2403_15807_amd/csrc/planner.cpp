@@ -17,7 +17,7 @@ namespace {
 // resident workgroups: 4 = one full round, 8 = two, 2 = half a round).
 const TileCfg kTiles[] = {
     {0, 1, 1024}, {0, 2, 1024}, {0, 4, 1024}, {0, 8, 1024},
-    {1, 64, 4}, {1, 64, 8}, {1, 64, 2}, {1, 64, 16},
+    {1, 64, 4}, {1, 128, 4}, {1, 64, 8}, {1, 128, 8},
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 constexpr size_t LDS_BUDGET = 64 * 1024;  // several workgroups per CU
@@ -51,11 +51,12 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
     P.mfma = cfg.kind == 1;
     if (P.mfma) {
         P.CB = mfma_cb(P.Kp);
-        P.qt = cfg.qt;
+        P.qt = t->store == VRS_F32 ? cfg.qt : 64;
         P.n_qtiles = (B + P.qt - 1) / P.qt;
-        const int64_t slots = (int64_t)256 * screen_mfma_occupancy(P.Kp, P.CB) * cfg.wg_target / 4;
+        const int occ = t->store == VRS_F32 ? screen_mfma_occupancy(P.Kp, P.CB, P.qt) : 2;
+        const int64_t slots = (int64_t)256 * occ * cfg.wg_target / 4;
         const int64_t rows = est_rows < 0 ? t->n : std::max<int64_t>(est_rows, 1);
-        int64_t max_chunks = std::max<int64_t>(1, rows / 4096);
+        int64_t max_chunks = std::max<int64_t>(1, rows / 1024);
         int64_t nc = std::max<int64_t>(1, std::min<int64_t>(max_chunks, slots / P.n_qtiles));
         if (nc >= 8) nc = nc / 8 * 8;  // whole XCD groups: a row chunk's query tiles share an L2
         P.n_chunks = (int)nc;
@@ -82,6 +83,7 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
     P.o_qp = take((size_t)B * t->dp * 4);
     P.o_qnorm = take((size_t)B * 8);
     P.o_qn2 = take((size_t)B * 4);
+    P.o_qhl = take(t->store == VRS_F32 ? 0 : (size_t)B * 2 * t->dp * 2);
     P.o_gthr = take((size_t)B * 8);
     P.o_cbuf = take(P.mfma ? (size_t)B * P.n_chunks * P.CB * 8 : 0);
     P.o_bitmap = take((size_t)(t->n + 31) / 32 * 4);
@@ -101,15 +103,18 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
     return P;
 }
 
-bool tile_ok(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int tile) {
+bool tile_ok(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int tile,
+             int metric = VRS_IP) {
     if (kTiles[tile].kind == 0) return true;
     const int kmult = opts ? opts->kprime_mult : 0;
     const int Kp = next_pow2(kprime_rule(kmax, t->store, kmult) + 1);
-    return screen_mfma_supported(t->dp, t->store, Kp, mfma_cb(Kp));
+    if (t->store == VRS_F32) return screen_mfma_supported(t->dp, t->store, Kp, mfma_cb(Kp));
+    return screen_mfma_bf16_supported(t->dp, t->store, metric, Kp, mfma_cb(Kp));
 }
 
-int default_tile(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts) {
-    if (B >= 8 && tile_ok(t, B, kmax, opts, 4)) return 4;
+int default_tile(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts,
+                 int metric = VRS_IP) {
+    if (B >= 8 && tile_ok(t, B, kmax, opts, 4, metric)) return 4;
     if (B <= 1) return 0;
     if (B <= 2) return 1;
     if (B <= 4) return 2;
@@ -214,8 +219,8 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
                     int64_t *out_idx, float *out_dist, void *ws, const vrs_opts *opts,
                     hipStream_t s) {
     const bool batched = preds != nullptr;
-    int tile = (opts && opts->tile >= 0) ? opts->tile : default_tile(t, B, k, opts);
-    if (!tile_ok(t, B, k, opts, tile)) tile = default_tile(t, B, k, opts);
+    int tile = (opts && opts->tile >= 0) ? opts->tile : default_tile(t, B, k, opts, metric);
+    if (!tile_ok(t, B, k, opts, tile, metric)) tile = default_tile(t, B, k, opts, metric);
     int strategy = opts ? opts->strategy : VRS_STRATEGY_AUTO;
     if (batched) strategy = VRS_STRATEGY_MASK;  // per-query predicates are checked per row
     const double est_sel = batched ? 1.0 : estimate_selectivity(t, p);
@@ -230,10 +235,11 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     float *qp = (float *)(w + P.o_qp);
     double *qnorm = (double *)(w + P.o_qnorm);
     float *qn2 = (float *)(w + P.o_qn2);
+    uint16_t *qhl = t->store == VRS_F32 ? nullptr : (uint16_t *)(w + P.o_qhl);
     uint64_t *gthr = (uint64_t *)(w + P.o_gthr);
     int32_t *fail_count = (int32_t *)(w + P.o_failcnt);
     prof_begin(0, s);
-    hipError_t e = launch_prep_queries(q, B, t->d, t->dp, qp, qnorm, qn2, gthr, fail_count, s);
+    hipError_t e = launch_prep_queries(q, B, t->d, t->dp, qp, qnorm, qn2, qhl, gthr, fail_count, s);
     if (e != hipSuccess) return e;
     PredDev *pdev = (PredDev *)(w + P.o_preds);
     int32_t *kc = (int32_t *)(w + P.o_kc), *kps = (int32_t *)(w + P.o_kps);
@@ -267,6 +273,7 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     sa.gather = gather;
     sa.qp = qp;
     sa.qn2 = qn2;
+    sa.qhl = qhl;
     sa.norm2 = t->norm2;
     sa.cbuf = (uint64_t *)(w + P.o_cbuf);
     sa.gthr = gthr;
@@ -278,7 +285,12 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     sa.n_chunks = P.n_chunks;
     sa.partials = (uint64_t *)(w + P.o_part);
     prof_begin(2, s);
-    e = P.mfma ? launch_screen_mfma(sa, s) : launch_screen_stream(sa, P.qt, s);
+    if (!P.mfma)
+        e = launch_screen_stream(sa, P.qt, s);
+    else if (t->store == VRS_F32)
+        e = launch_screen_mfma(sa, P.qt, s);
+    else
+        e = launch_screen_mfma_bf16(sa, s);
     if (e != hipSuccess) return e;
     prof_end(2, s);
 
@@ -315,9 +327,14 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     const double u32 = ldexp(1.0, -24), u64 = ldexp(1.0, -53);
     const double g = (gamma_n(t->dp + 3, u32) + gamma_n(t->dp + 3, u64)) * 1.001;
     const double g6 = (gamma_n(t->dp + 6, u32) + gamma_n(t->dp + 3, u64)) * 1.001;
+    //   bf16 MFMA IP (hi/lo query split, FP8 scale applied to the sum):
+    //              gamma_{dp+2} (1 + 2^-7) + 2^-16 + 3u, times |q| max|x|.
     fa.rel = (metric == VRS_L2SQ && !P.mfma) ? g : 0.0;
     fa.abs_ip = metric == VRS_IP ? g6 : 0.0;
     fa.abs_l2 = (metric == VRS_L2SQ && P.mfma) ? g6 : 0.0;
+    if (P.mfma && t->store != VRS_F32)
+        fa.abs_ip = (gamma_n(t->dp + 2, u32) * (1.0 + ldexp(1.0, -7)) + ldexp(1.0, -16) +
+                     3.0 * u32 + gamma_n(t->dp + 2, u64)) * 1.001;
     fa.max_norm = t->max_norm;
     fa.fail_list = (int32_t *)(w + P.o_fail);
     fa.fail_count = fail_count;

@@ -210,18 +210,24 @@ def test_planted_duplicates_and_queries():
 
 
 @pytest.mark.parametrize("store", [vrs.BF16, vrs.FP8E4M3, vrs.F32])
-def test_ip_quantised_storage(store):
-    x = inputs.table(2, 40000, 256, 200)
-    a = inputs.attributes(2, 40000, 2, 10 ** 6)
-    q = inputs.queries(2, 8, 256, 200)
+@pytest.mark.parametrize("d", [256, 200])
+def test_ip_quantised_storage(store, d):
+    # streaming (tile 3) and MFMA (tile 4) screening, ragged 64-query tiles
+    n, B = 40000, 70
+    x = inputs.table(2, n, d, 200)
+    a = inputs.attributes(2, n, 2, 10 ** 6)
+    q = inputs.queries(2, B, d, 200)
     T = vrs.Table(_dev(x), _dev(a), store=store, normalize=True)
     ot = O.Table.build(x, a, {vrs.F32: O.F32, vrs.BF16: O.BF16, vrs.FP8E4M3: O.FP8}[store], True)
-    w = inputs.two_term_width(0.3, 10 ** 6)
-    pred = [(0, 0, w), (1, 0, w)]
-    for k in (10, 100):
-        ref = O.scan_topk(ot, q, pred, k, O.IP)
-        r = T.scan_topk(_dev(q), pred, k, vrs.IP)
-        _check(r, ref, f"store {store} k {k}")
+    for sel in (0.3, 0.01):
+        w = inputs.two_term_width(sel, 10 ** 6)
+        pred = [(0, 0, w), (1, 0, w)]
+        for k in (10, 100):
+            ref = O.scan_topk(ot, q, pred, k, O.IP)
+            for tile in (3, 4):
+                for strategy in (vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER):
+                    r = T.scan_topk(_dev(q), pred, k, vrs.IP, tile=tile, strategy=strategy)
+                    _check(r, ref, f"store {store} d {d} sel {sel} k {k} tile {tile} strategy {strategy}")
 
 
 def test_forced_certificate_failure_uses_exact_fallback():
