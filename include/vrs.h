@@ -159,13 +159,65 @@ vrs_status vrs_scan_topk_batched(vrs_table t, const float *q, int32_t B, const v
                                  int64_t *out_idx, float *out_dist, void *ws, size_t ws_bytes,
                                  const vrs_opts *opts, void *stream);
 
-/* Number of kernel configurations ("tiles") the planner chooses from. */
+/* Number of kernel configurations ("tiles") the planner chooses from.  An
+ * access path ("arm") is strategy x tile: arm = (strategy - 1) * tiles + tile
+ * with strategy MASK = 1, GATHER = 2. */
 int32_t vrs_num_tiles(void);
 
-/* Load access-path chooser weights (host path).  On a missing or corrupt file
- * the chooser stays on the selectivity-threshold heuristic and the call
- * returns VRS_E_ARG. */
+/* ---- Learned access-path chooser (workload-driven access path selection,
+ * Sections 3.2 and 5: the best scan strategy depends on selectivity,
+ * dimensionality and the number of concurrent queries).
+ *
+ * A 6 -> 64 -> 64 -> 16 perceptron with ReLU (FP32) maps standardised
+ * features (ln n, ln d, ln B, ln estimated selectivity, ln k, storage dtype)
+ * to a predicted ln(milliseconds) per arm; the planner takes the arm with the
+ * smallest prediction among the valid ones.  It never changes results (every
+ * arm returns the same exact top-k).  Parameter block (floats, in order):
+ * W1[6][64], b1[64], W2[64][64], b2[64], W3[64][16], b3[16]; a layer computes
+ * out[j] = b[j] + sum_i in[i] * W[i][j]. */
+#define VRS_MLP_IN 6
+#define VRS_MLP_HIDDEN 64
+#define VRS_MLP_OUT 16
+#define VRS_MLP_PARAMS 5648
+
+/* Forward pass of nb samples: x [nb][6] -> y [nb][16]; act [nb][128] keeps the
+ * hidden activations for a backward pass (NULL when none follows). */
+vrs_status vrs_mlp_forward(const float *params, const float *x, int32_t nb, float *y, float *act,
+                           void *stream);
+
+/* Gradient of the masked mean squared error sum(mask (y - target)^2) / count,
+ * count = number of set mask entries (> 0): writes grad [VRS_MLP_PARAMS] and,
+ * if loss != NULL, loss [1].  Scratch: sig [nb][144], sqerr [nb] floats. */
+vrs_status vrs_mlp_backward(const float *params, const float *x, const float *y,
+                            const float *act, const float *target, const uint8_t *mask,
+                            int32_t nb, int32_t count, float *sig, float *sqerr, float *grad,
+                            float *loss, void *stream);
+
+/* One Adam step (Kingma & Ba) on all parameters; step counts from 1. */
+vrs_status vrs_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t step,
+                        float lr, float beta1, float beta2, float eps, void *stream);
+
+/* Install chooser weights from host memory: params [VRS_MLP_PARAMS], feature
+ * mean and standard deviation [6] each.  vrs_chooser_clear() returns the
+ * planner to the selectivity-threshold heuristic. */
+vrs_status vrs_chooser_set(const float *params, const float *feat_mean, const float *feat_std);
+vrs_status vrs_chooser_clear(void);
+
+/* Load chooser weights from a file written by the training tool (magic
+ * "VRSCHOOS", version 1, then the params, mean and std as little-endian
+ * float32).  On a missing or corrupt file the chooser stays on the heuristic
+ * and the call returns VRS_E_ARG. */
 vrs_status vrs_chooser_load(const char *path);
+
+/* The planner's decision for a call without running it (host only): raw
+ * features [6] (host, may be NULL), and the strategy / tile AUTO would use
+ * under opts->chooser. */
+vrs_status vrs_plan(vrs_table t, int32_t B, const vrs_pred *pred, int32_t k, vrs_metric metric,
+                    const vrs_opts *opts, float *features, int32_t *strategy, int32_t *tile);
+
+/* A non-owning view of the first n rows of a table (same storage; destroy
+ * the view before its parent).  Used to time scans at many table sizes. */
+vrs_status vrs_table_view(vrs_table t, int64_t n, vrs_table *out);
 
 /* Stage timing for measurement tools.  While enabled, every scan records a
  * pair of HIP events around each of its stages on the scan's own stream:

@@ -18,7 +18,8 @@ OUT = os.path.join(HERE, "libvrs.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.cpp", "planner.cpp", "k_build.hip", "k_select.hip", "k_stream.hip",
-           "k_mfma.hip", "k_mfma_bf16.hip", "k_finish.hip"]
+           "k_mfma.hip", "k_mfma_bf16.hip", "k_finish.hip",
+           "k_mlp.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = ["-x", "hip", "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",

@@ -149,6 +149,7 @@ vrs_status vrs_build_table(const float *vec, int64_t n, int32_t d, const int32_t
     t->d = d;
     t->dp = pad_dim(d, store);
     t->n_attr = n_attr;
+    t->attr_stride = n;
     t->store = store;
     HIP_TRY(hipGetDevice(&t->device));
     auto cleanup = [&]() { vrs_destroy_table(t); };
@@ -213,6 +214,10 @@ vrs_status vrs_build_table(const float *vec, int64_t n, int32_t d, const int32_t
 
 vrs_status vrs_destroy_table(vrs_table t) {
     if (!t) return fail(VRS_E_ARG, "table is NULL");
+    if (!t->owner) {
+        delete t;
+        return ok();
+    }
     if (t->rows) (void)hipFree(t->rows);
     if (t->scale) (void)hipFree(t->scale);
     if (t->norm2) (void)hipFree(t->norm2);
@@ -264,7 +269,8 @@ vrs_status vrs_select(vrs_table t, const vrs_pred *pred, int32_t *ids_out, int64
     if (st != VRS_OK) return st;
     uint32_t *bitmap = (uint32_t *)ws;
     uint32_t *blk = (uint32_t *)((char *)ws + align256((t->n + 31) / 32 * 4));
-    HIP_TRY(launch_select(t->attr, t->n, p, bitmap, blk, ids_out, count_out, (hipStream_t)stream));
+    HIP_TRY(launch_select(t->attr, t->n, t->attr_stride, p, bitmap, blk, ids_out, count_out,
+                          (hipStream_t)stream));
     return ok();
 }
 
@@ -285,6 +291,70 @@ vrs_status vrs_stage_times(double *ms, int64_t *calls) {
 vrs_status vrs_chooser_load(const char *path) {
     std::string err;
     if (!chooser_load(path, &err)) return fail(VRS_E_ARG, "%s", err.c_str());
+    return ok();
+}
+
+vrs_status vrs_chooser_set(const float *params, const float *feat_mean, const float *feat_std) {
+    if (!params || !feat_mean || !feat_std) return fail(VRS_E_ARG, "NULL argument");
+    if (!chooser_set(params, feat_mean, feat_std))
+        return fail(VRS_E_ARG, "chooser weights must be finite and std > 0");
+    return ok();
+}
+
+vrs_status vrs_chooser_clear(void) {
+    chooser_clear();
+    return ok();
+}
+
+vrs_status vrs_plan(vrs_table t, int32_t B, const vrs_pred *pred, int32_t k, vrs_metric metric,
+                    const vrs_opts *opts, float *features, int32_t *strategy, int32_t *tile) {
+    if (!t) return fail(VRS_E_ARG, "table is NULL");
+    if (B < 1 || k < 1 || k > 256) return fail(VRS_E_ARG, "bad B or k");
+    PredDev p;
+    vrs_status st = fold_pred(pred, t->n_attr, &p);
+    if (st != VRS_OK) return st;
+    float f[6];
+    int s_, t_;
+    plan_decide(t, B, p, false, k, metric, opts, f, &s_, &t_);
+    if (features)
+        for (int i = 0; i < 6; ++i) features[i] = f[i];
+    if (strategy) *strategy = s_;
+    if (tile) *tile = t_;
+    return ok();
+}
+
+vrs_status vrs_table_view(vrs_table t, int64_t n, vrs_table *out) {
+    if (!t || !out) return fail(VRS_E_ARG, "NULL argument");
+    if (n < 1 || n > t->n) return fail(VRS_E_ARG, "view rows %lld outside [1, %lld]", (long long)n, (long long)t->n);
+    auto *v = new vrs_table_s(*t);
+    v->n = n;
+    v->owner = false;
+    *out = v;
+    return ok();
+}
+
+vrs_status vrs_mlp_forward(const float *params, const float *x, int32_t nb, float *y, float *act,
+                           void *stream) {
+    if (!params || !x || !y || nb < 1) return fail(VRS_E_ARG, "bad MLP forward arguments");
+    HIP_TRY(launch_mlp_forward(params, x, nb, y, act, (hipStream_t)stream));
+    return ok();
+}
+
+vrs_status vrs_mlp_backward(const float *params, const float *x, const float *y,
+                            const float *act, const float *target, const uint8_t *mask,
+                            int32_t nb, int32_t count, float *sig, float *sqerr, float *grad,
+                            float *loss, void *stream) {
+    if (!params || !x || !y || !act || !target || !mask || !sig || !sqerr || !grad || nb < 1 || count < 1)
+        return fail(VRS_E_ARG, "bad MLP backward arguments");
+    HIP_TRY(launch_mlp_backward(params, x, y, act, target, mask, nb, 1.0f / (float)count, sig,
+                                sqerr, grad, loss, (hipStream_t)stream));
+    return ok();
+}
+
+vrs_status vrs_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t step,
+                        float lr, float beta1, float beta2, float eps, void *stream) {
+    if (!params || !grad || !m || !v || step < 1) return fail(VRS_E_ARG, "bad Adam arguments");
+    HIP_TRY(launch_mlp_adam(params, grad, m, v, step, lr, beta1, beta2, eps, (hipStream_t)stream));
     return ok();
 }
 

@@ -20,7 +20,9 @@ struct vrs_table_s {
     void *rows = nullptr;       // [n][dp] float / uint16 / uint8
     float *scale = nullptr;     // [n] FP8 row scales
     float *norm2 = nullptr;     // [n] ||x_i||^2 of the stored row (float32)
-    int32_t *attr = nullptr;    // [n_attr][n]
+    int32_t *attr = nullptr;    // [n_attr][attr_stride]
+    int64_t attr_stride = 0;    // column stride of attr (the parent's n for a view)
+    bool owner = true;          // false for a view (vrs_table_view)
     double max_norm = 0.0;      // max_i ||x_i|| of stored rows (rounded up)
     // per-column equi-width histograms for selectivity estimates
     std::vector<int32_t> amin, amax;
@@ -43,8 +45,9 @@ hipError_t launch_attr_stats(const int32_t *attr, int64_t n, int32_t n_attr, int
 
 // ---- predicate pass (k_select.hip)
 constexpr int SEL_BLOCK_ROWS = 8192;
-hipError_t launch_select(const int32_t *attr, int64_t n, const PredDev &p, uint32_t *bitmap,
-                         uint32_t *blkcnt, int32_t *ids, int64_t *count, hipStream_t s);
+hipError_t launch_select(const int32_t *attr, int64_t n, int64_t an, const PredDev &p,
+                         uint32_t *bitmap, uint32_t *blkcnt, int32_t *ids, int64_t *count,
+                         hipStream_t s);
 
 // ---- query preparation (k_finish.hip)
 hipError_t launch_prep_queries(const float *q, int32_t B, int32_t d, int32_t dp, float *qp,
@@ -64,6 +67,7 @@ struct ScreenArgs {
     int32_t dp;
     vrs_dtype store;
     const int32_t *attr;
+    int64_t an;                    // attribute column stride
     PredDev pred;                  // shared predicate (batch form: preds != null)
     const PredDev *preds;          // [B] per-query predicates or null
     const int32_t *sel_ids;        // gather: qualifying rows
@@ -98,6 +102,7 @@ struct FinishArgs {
     int32_t d, dp;
     vrs_dtype store;
     const int32_t *attr;
+    int64_t an;                    // attribute column stride
     PredDev pred;
     const PredDev *preds;
     const float *q;                // original queries [B][d]
@@ -128,5 +133,14 @@ struct FinishArgs {
 hipError_t launch_merge(const FinishArgs &a, hipStream_t s);
 hipError_t launch_rerank(const FinishArgs &a, hipStream_t s);
 hipError_t launch_fallback(const FinishArgs &a, hipStream_t s);
+
+// ---- chooser network (k_mlp.hip)
+hipError_t launch_mlp_forward(const float *p, const float *x, int nb, float *y, float *act,
+                              hipStream_t s);
+hipError_t launch_mlp_backward(const float *p, const float *x, const float *y, const float *act,
+                               const float *t, const uint8_t *mask, int nb, float inv_count,
+                               float *sig, float *sqerr, float *grad, float *loss, hipStream_t s);
+hipError_t launch_mlp_adam(float *p, const float *g, float *m, float *v, int step, float lr,
+                           float b1, float b2, float eps, hipStream_t s);
 
 }  // namespace vrs

@@ -360,7 +360,7 @@ __global__ __launch_bounds__(256) void fallback_scan_kernel(FinishArgs a) {
         const int64_t r1 = min(a.n, r0 + a.fb_rows_per_chunk);
         for (int64_t t0 = r0; t0 < r1; t0 += 256) {
             int64_t row = t0 + tid;
-            if (row < r1 && pred_eval(p, a.attr, a.n, row)) {
+            if (row < r1 && pred_eval(p, a.attr, a.an, row)) {
                 double dv = exact_dist<STORE, METRIC>(a.rows, a.scale, row, a.dp, qrow);
                 tk.push(0, Key128{ord64(dv), (uint64_t)row});
             }

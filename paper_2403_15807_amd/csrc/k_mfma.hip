@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256, (E <= 8 && MB == 1) ? 3 : 2) void screen_mfma_
 #pragma unroll
             for (int t = 0; t < 4; ++t)
                 ri_av[t] = (!GATHER && !BATCHED && ri_ok && t < a.pred.nterms)
-                               ? a.attr[(int64_t)a.pred.col[t] * a.n + ri_row]
+                               ? a.attr[(int64_t)a.pred.col[t] * a.an + ri_row]
                                : 0;
             ri_n2 = (METRIC == VRS_L2SQ && ri_ok) ? a.norm2[ri_row] : 0.0f;
         }
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256, (E <= 8 && MB == 1) ? 3 : 2) void screen_mfma_
                     const int q = qb + i;
                     const int qa = q0 + q;
                     if (qa >= a.B) continue;
-                    if (BATCHED && !pred_eval(qpred[q], a.attr, a.n, row)) continue;
+                    if (BATCHED && !pred_eval(qpred[q], a.attr, a.an, row)) continue;
                     const float dist = METRIC == VRS_L2SQ ? fmaf(-2.0f, acc[mb][nb][i], qn[i] + xn2[r]) : -acc[mb][nb][i];
                     const uint64_t key = make_key(dist, (uint32_t)row);
                     if (key < th[i]) {

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256, 2) void screen_mfma_bf16_kernel(ScreenArgs a) 
             const int64_t pos = t0 + tid;
             bool ok = pos < c1;
             int64_t row = ok ? (GATHER ? (int64_t)a.sel_ids[pos] : pos) : 0;
-            if (ok && !GATHER && !BATCHED) ok = pred_eval(a.pred, a.attr, a.n, row);
+            if (ok && !GATHER && !BATCHED) ok = pred_eval(a.pred, a.attr, a.an, row);
             rid[slot * BR + tid] = (int)row;
             rq[slot * BR + tid] = ok;
             rsc[slot * BR + tid] = (STORE == VRS_FP8E4M3 && ok) ? a.scale[row] : 1.0f;
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256, 2) void screen_mfma_bf16_kernel(ScreenArgs a) 
             for (int i = 0; i < 4; ++i) {
                 const int q = qb + i, qa = q0 + q;
                 if (qa >= a.B) continue;
-                if (BATCHED && !pred_eval(qpred[q], a.attr, a.n, row)) continue;
+                if (BATCHED && !pred_eval(qpred[q], a.attr, a.an, row)) continue;
                 const float dot = ah[nb][i] + al[nb][i];
                 const float dist = STORE == VRS_FP8E4M3 ? -(sc * dot) : -dot;
                 const uint64_t key = make_key(dist, (uint32_t)row);

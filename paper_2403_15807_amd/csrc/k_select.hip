@@ -12,7 +12,7 @@ namespace vrs {
 // One block = SEL_BLOCK_ROWS rows = 32 steps of 256 rows; every wave turns
 // 64 predicate results into one 64-bit ballot.
 __global__ __launch_bounds__(256) void select_bitmap_kernel(const int32_t *__restrict__ attr,
-                                                            int64_t n, PredDev p,
+                                                            int64_t n, int64_t an, PredDev p,
                                                             uint32_t *__restrict__ bitmap,
                                                             uint32_t *__restrict__ blkcnt) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -21,7 +21,7 @@ __global__ __launch_bounds__(256) void select_bitmap_kernel(const int32_t *__res
     for (int step = 0; step < SEL_BLOCK_ROWS / 256; ++step) {
         int64_t row0 = base + step * 256 + wave * 64;
         int64_t row = row0 + lane;
-        bool q = row < n && pred_eval(p, attr, n, row);
+        bool q = row < n && pred_eval(p, attr, an, row);
         uint64_t m = __ballot(q);
         if (lane == 0 && row0 < n) {
             int64_t w = row0 >> 5;  // row0 is a multiple of 64
@@ -72,10 +72,11 @@ __global__ __launch_bounds__(256) void select_ids_kernel(const uint32_t *__restr
     if (blockIdx.x == (unsigned)nblk - 1 && threadIdx.x == 0) *count = (int64_t)off;
 }
 
-hipError_t launch_select(const int32_t *attr, int64_t n, const PredDev &p, uint32_t *bitmap,
-                         uint32_t *blkcnt, int32_t *ids, int64_t *count, hipStream_t s) {
+hipError_t launch_select(const int32_t *attr, int64_t n, int64_t an, const PredDev &p,
+                         uint32_t *bitmap, uint32_t *blkcnt, int32_t *ids, int64_t *count,
+                         hipStream_t s) {
     int nblk = (int)((n + SEL_BLOCK_ROWS - 1) / SEL_BLOCK_ROWS);
-    select_bitmap_kernel<<<nblk, 256, 0, s>>>(attr, n, p, bitmap, blkcnt);
+    select_bitmap_kernel<<<nblk, 256, 0, s>>>(attr, n, an, p, bitmap, blkcnt);
     select_ids_kernel<<<nblk, 256, 0, s>>>(bitmap, blkcnt, n, nblk, ids, count);
     return hipGetLastError();
 }

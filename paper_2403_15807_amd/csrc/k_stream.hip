@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void screen_stream_kernel(ScreenArgs a) {
 #pragma unroll
             for (int t = 0; t < 4; ++t)
                 av[u][t] = (!GATHER && !BATCHED && vd[u] && t < a.pred.nterms)
-                               ? a.attr[(int64_t)a.pred.col[t] * a.n + rw[u]]
+                               ? a.attr[(int64_t)a.pred.col[t] * a.an + rw[u]]
                                : 0;
         }
     };
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256) void screen_stream_kernel(ScreenArgs a) {
                 if (BATCHED && ok) {
 #pragma unroll
                     for (int b = 0; b < QT; ++b)
-                        if (b == s) ok = pred_eval(qpred[b], a.attr, a.n, row[u]);
+                        if (b == s) ok = pred_eval(qpred[b], a.attr, a.an, row[u]);
                 }
                 if (ok) {
                     float dist;

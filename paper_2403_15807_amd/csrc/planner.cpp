@@ -3,6 +3,10 @@
 #include "planner.h"
 
 #include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
 
 #include <algorithm>
 #include <mutex>
@@ -214,20 +218,62 @@ bool planner_tile_ok(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts
     return tile_ok(t, B, kmax, opts, tile);
 }
 
+void plan_features(const vrs_table_s *t, int B, double sel, int k, float f[6]) {
+    f[0] = (float)log((double)t->n);
+    f[1] = (float)log((double)t->d);
+    f[2] = (float)log((double)B);
+    f[3] = (float)log(std::max(sel, 1e-6));
+    f[4] = (float)log((double)k);
+    f[5] = (float)t->store;
+}
+
+void plan_decide(const vrs_table_s *t, int B, const PredDev &p, bool batched, int k, int metric,
+                 const vrs_opts *opts, float feats[6], int *strategy_out, int *tile_out) {
+    const double est_sel = batched ? 1.0 : estimate_selectivity(t, p);
+    plan_features(t, B, est_sel, k, feats);
+    const int want_s = opts ? opts->strategy : VRS_STRATEGY_AUTO;
+    const int want_t = opts ? opts->tile : -1;
+    const bool learned = (!opts || opts->chooser == VRS_CHOOSER_LEARNED) && chooser_ready();
+    if (learned && (want_s == VRS_STRATEGY_AUTO || want_t < 0)) {
+        bool allowed[2 * kNumTiles];
+        for (int sidx = 0; sidx < 2; ++sidx)
+            for (int tile = 0; tile < kNumTiles; ++tile) {
+                const int st = sidx + 1;
+                bool ok = tile_ok(t, B, k, opts, tile, metric);
+                if (want_s != VRS_STRATEGY_AUTO && st != want_s) ok = false;
+                if (batched && st != VRS_STRATEGY_MASK) ok = false;
+                if (want_t >= 0 && tile != want_t) ok = false;
+                allowed[sidx * kNumTiles + tile] = ok;
+            }
+        const int arm = chooser_pick(feats, allowed, 2 * kNumTiles);
+        if (arm >= 0) {
+            *strategy_out = arm / kNumTiles + 1;
+            *tile_out = arm % kNumTiles;
+            return;
+        }
+    }
+    int tile = want_t >= 0 ? want_t : default_tile(t, B, k, opts, metric);
+    if (!tile_ok(t, B, k, opts, tile, metric)) tile = default_tile(t, B, k, opts, metric);
+    int strategy = want_s;
+    if (batched) strategy = VRS_STRATEGY_MASK;  // per-query predicates are checked per row
+    if (strategy == VRS_STRATEGY_AUTO) {
+        // selectivity-threshold heuristic
+        strategy = est_sel < 0.5 ? VRS_STRATEGY_GATHER : VRS_STRATEGY_MASK;
+        if (p.nterms == 0) strategy = VRS_STRATEGY_MASK;
+    }
+    *strategy_out = strategy;
+    *tile_out = tile;
+}
+
 hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &p,
                     const vrs_pred *preds, const int32_t *ks, int k, vrs_metric metric,
                     int64_t *out_idx, float *out_dist, void *ws, const vrs_opts *opts,
                     hipStream_t s) {
     const bool batched = preds != nullptr;
-    int tile = (opts && opts->tile >= 0) ? opts->tile : default_tile(t, B, k, opts, metric);
-    if (!tile_ok(t, B, k, opts, tile, metric)) tile = default_tile(t, B, k, opts, metric);
-    int strategy = opts ? opts->strategy : VRS_STRATEGY_AUTO;
-    if (batched) strategy = VRS_STRATEGY_MASK;  // per-query predicates are checked per row
+    float feats[6];
+    int strategy, tile;
+    plan_decide(t, B, p, batched, k, metric, opts, feats, &strategy, &tile);
     const double est_sel = batched ? 1.0 : estimate_selectivity(t, p);
-    if (strategy == VRS_STRATEGY_AUTO) {
-        strategy = est_sel < 0.5 ? VRS_STRATEGY_GATHER : VRS_STRATEGY_MASK;
-        if (p.nterms == 0) strategy = VRS_STRATEGY_MASK;
-    }
     const int64_t est_rows =
         strategy == VRS_STRATEGY_GATHER ? (int64_t)(est_sel * (double)t->n * 1.25) + 4096 : t->n;
     Plan P = make_plan(t, B, k, opts, tile, strategy, est_rows);
@@ -254,8 +300,8 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     int64_t *selcnt = (int64_t *)(w + P.o_selcnt);
     if (gather) {
         prof_begin(1, s);
-        e = launch_select(t->attr, t->n, p, (uint32_t *)(w + P.o_bitmap), (uint32_t *)(w + P.o_blk),
-                          sel, selcnt, s);
+        e = launch_select(t->attr, t->n, t->attr_stride, p, (uint32_t *)(w + P.o_bitmap),
+                          (uint32_t *)(w + P.o_blk), sel, selcnt, s);
         if (e != hipSuccess) return e;
         prof_end(1, s);
     }
@@ -266,6 +312,7 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     sa.dp = t->dp;
     sa.store = t->store;
     sa.attr = t->attr;
+    sa.an = t->attr_stride;
     sa.pred = p;
     sa.preds = batched ? pdev : nullptr;
     sa.sel_ids = sel;
@@ -302,6 +349,7 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     fa.dp = t->dp;
     fa.store = t->store;
     fa.attr = t->attr;
+    fa.an = t->attr_stride;
     fa.pred = p;
     fa.preds = batched ? pdev : nullptr;
     fa.q = q;
@@ -360,12 +408,93 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     return e;
 }
 
-// ------------------------------------------------------------- chooser stub
-bool chooser_load(const char *path, std::string *err) {
-    *err = std::string("chooser weights not supported yet: ") + (path ? path : "(null)");
-    return false;
+// ------------------------------------------------------------- chooser
+namespace {
+std::mutex g_ch_mu;
+bool g_ch_ready = false;
+std::vector<float> g_ch_p, g_ch_mean, g_ch_std;
+}  // namespace
+
+bool chooser_set(const float *params, const float *mean, const float *stdv) {
+    for (int i = 0; i < VRS_MLP_PARAMS; ++i)
+        if (!std::isfinite(params[i])) return false;
+    for (int i = 0; i < VRS_MLP_IN; ++i)
+        if (!std::isfinite(mean[i]) || !std::isfinite(stdv[i]) || !(stdv[i] > 0.0f)) return false;
+    std::lock_guard<std::mutex> g(g_ch_mu);
+    g_ch_p.assign(params, params + VRS_MLP_PARAMS);
+    g_ch_mean.assign(mean, mean + VRS_MLP_IN);
+    g_ch_std.assign(stdv, stdv + VRS_MLP_IN);
+    g_ch_ready = true;
+    return true;
 }
-bool chooser_ready() { return false; }
-int chooser_pick(const float *, const bool *, int) { return -1; }
+
+void chooser_clear() {
+    std::lock_guard<std::mutex> g(g_ch_mu);
+    g_ch_ready = false;
+}
+
+bool chooser_load(const char *path, std::string *err) {
+    if (!path) {
+        *err = "path is NULL";
+        return false;
+    }
+    FILE *f = fopen(path, "rb");
+    if (!f) {
+        *err = std::string("cannot open chooser weights: ") + path;
+        return false;
+    }
+    char magic[8];
+    int32_t ver = 0, np = 0;
+    std::vector<float> buf(VRS_MLP_PARAMS + 2 * VRS_MLP_IN);
+    bool good = fread(magic, 1, 8, f) == 8 && memcmp(magic, "VRSCHOOS", 8) == 0 &&
+                fread(&ver, 4, 1, f) == 1 && ver == 1 && fread(&np, 4, 1, f) == 1 &&
+                np == VRS_MLP_PARAMS && fread(buf.data(), 4, buf.size(), f) == buf.size();
+    fclose(f);
+    if (!good) {
+        *err = std::string("corrupt chooser weights file: ") + path;
+        return false;
+    }
+    if (!chooser_set(buf.data(), buf.data() + VRS_MLP_PARAMS, buf.data() + VRS_MLP_PARAMS + VRS_MLP_IN)) {
+        *err = std::string("chooser weights are not finite: ") + path;
+        return false;
+    }
+    return true;
+}
+
+bool chooser_ready() {
+    std::lock_guard<std::mutex> g(g_ch_mu);
+    return g_ch_ready;
+}
+
+// Host inference of the chooser network (same layer formula as the kernels).
+int chooser_pick(const float feats[6], const bool *allowed, int n_arms) {
+    std::lock_guard<std::mutex> g(g_ch_mu);
+    if (!g_ch_ready) return -1;
+    const int NI = VRS_MLP_IN, NH = VRS_MLP_HIDDEN, NO = VRS_MLP_OUT;
+    const float *p = g_ch_p.data();
+    const float *W1 = p, *b1 = W1 + NI * NH, *W2 = b1 + NH, *b2 = W2 + NH * NH, *W3 = b2 + NH,
+                *b3 = W3 + NH * NO;
+    float x[NI], h1[NH], h2[NH], y[NO];
+    for (int i = 0; i < NI; ++i) x[i] = (feats[i] - g_ch_mean[i]) / g_ch_std[i];
+    for (int j = 0; j < NH; ++j) {
+        float a = b1[j];
+        for (int i = 0; i < NI; ++i) a = fmaf(x[i], W1[i * NH + j], a);
+        h1[j] = a > 0.0f ? a : 0.0f;
+    }
+    for (int j = 0; j < NH; ++j) {
+        float a = b2[j];
+        for (int i = 0; i < NH; ++i) a = fmaf(h1[i], W2[i * NH + j], a);
+        h2[j] = a > 0.0f ? a : 0.0f;
+    }
+    for (int j = 0; j < NO; ++j) {
+        float a = b3[j];
+        for (int i = 0; i < NH; ++i) a = fmaf(h2[i], W3[i * NO + j], a);
+        y[j] = a;
+    }
+    int best = -1;
+    for (int j = 0; j < std::min(n_arms, NO); ++j)
+        if (allowed[j] && (best < 0 || y[j] < y[best])) best = j;
+    return best;
+}
 
 }  // namespace vrs

@@ -51,7 +51,13 @@ void prof_end(int stage, hipStream_t s);
 void prof_enable(bool on);
 hipError_t prof_collect(double *ms, int64_t *calls);
 
-// Learned chooser (host inference of the MLP; see chooser.cpp).
+// Planner decision (strategy, tile) for a call, with its raw chooser features.
+void plan_decide(const vrs_table_s *t, int B, const PredDev &p, bool batched, int k, int metric,
+                 const vrs_opts *opts, float feats[6], int *strategy_out, int *tile_out);
+
+// Learned chooser (host inference of the MLP).
+bool chooser_set(const float *params, const float *mean, const float *stdv);
+void chooser_clear();
 bool chooser_load(const char *path, std::string *err);
 bool chooser_ready();
 // Returns the arm index (strategy * num_tiles + tile) with the lowest

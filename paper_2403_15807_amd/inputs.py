@@ -53,11 +53,16 @@ def centers(cfg: int, n_clusters: int, d: int) -> np.ndarray:
     return _rng(cfg, _S_CENTERS).standard_normal((n_clusters, d))
 
 
+_SUB = 1 << 16  # rows per noise block inside a chunk (bounds temporary memory)
+
+
 def _rows_chunk(cfg, c, lo, hi, d, cent, sigma, out):
     g = _rng(cfg, _S_ROWS, c)
     lab = g.integers(0, cent.shape[0], size=hi - lo)
-    z = g.standard_normal((hi - lo, d))
-    out[lo:hi] = (cent[lab] + sigma * z).astype(np.float32)
+    for a in range(0, hi - lo, _SUB):
+        b = min(hi - lo, a + _SUB)
+        z = g.standard_normal((b - a, d))
+        out[lo + a:lo + b] = (cent[lab[a:b]] + sigma * z).astype(np.float32)
 
 
 def table(cfg: int, n: int, d: int, n_clusters: int, sigma: float = 0.1) -> np.ndarray:
@@ -132,3 +137,37 @@ def batched_predicates(cfg: int, b: int, attr_range: int, s_min: float = 1e-4,
     hi = lo + widths
     k = np.asarray(k_choices, dtype=np.int32)[g.integers(0, len(k_choices), size=b)]
     return BatchedPredicates(lo=lo, hi=hi, k=k, target_sel=s)
+
+
+@dataclass
+class ChooserWorkload:
+    """One scan configuration of the chooser's training or held-out set."""
+    n: int
+    d: int
+    b: int
+    sel: float
+    k: int
+    dtype: int      # 0 float32, 1 bfloat16, 2 FP8
+    seed: int       # query / predicate stream for this workload
+
+
+CHOOSER_DIMS = (64, 128, 768, 1536)
+CHOOSER_MAX_ROWS = {64: 10_000_000, 128: 10_000_000, 768: 2_000_000, 1536: 1_000_000}
+
+
+def chooser_workloads(cfg: int, count: int, n_min: int = 100_000, b_max: int = 4096):
+    """``count`` workloads: n ~ logU[n_min, max rows for d], d uniform over
+    CHOOSER_DIMS, B ~ logU-integer[1, b_max], selectivity ~ logU[1e-4, 1],
+    k uniform over {1, 10, 100}, storage dtype uniform over {f32, bf16, fp8}."""
+    g = _rng(cfg, _S_PRED, 7)
+    out = []
+    for i in range(count):
+        d = int(CHOOSER_DIMS[g.integers(0, len(CHOOSER_DIMS))])
+        n_max = CHOOSER_MAX_ROWS[d]
+        n = int(round(np.exp(g.uniform(np.log(n_min), np.log(n_max)))))
+        b = int(min(b_max, max(1, int(np.floor(np.exp(g.uniform(0.0, np.log(b_max + 1))))))))
+        sel = float(np.exp(g.uniform(np.log(1e-4), 0.0)))
+        k = int((1, 10, 100)[g.integers(0, 3)])
+        dtype = int(g.integers(0, 3))
+        out.append(ChooserWorkload(n=n, d=d, b=b, sel=sel, k=k, dtype=dtype, seed=int(g.integers(0, 2 ** 31))))
+    return out

@@ -16,6 +16,7 @@ import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvrs.so")
+CHOOSER_WEIGHTS = os.path.join(HERE, "chooser_weights.bin")
 
 VRS_OK, VRS_E_ARG, VRS_E_NONFINITE, VRS_E_NOMEM, VRS_E_UNSUPPORTED, VRS_E_HIP, VRS_E_WORKSPACE = range(7)
 L2SQ, IP = 0, 1
@@ -28,8 +29,10 @@ EXPORTS = [
     "vrs_build_table", "vrs_destroy_table", "vrs_table_info", "vrs_table_export",
     "vrs_scan_workspace_bytes", "vrs_select_workspace_bytes", "vrs_select", "vrs_scan_topk",
     "vrs_scan_topk_batched", "vrs_num_tiles", "vrs_chooser_load", "vrs_last_error",
-    "vrs_profile", "vrs_stage_times",
+    "vrs_profile", "vrs_stage_times", "vrs_mlp_forward", "vrs_mlp_backward", "vrs_mlp_adam",
+    "vrs_chooser_set", "vrs_chooser_clear", "vrs_plan", "vrs_table_view",
 ]
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 6, 64, 16, 5648
 NUM_STAGES = 6
 STAGES = ["prep", "select", "screen", "merge", "rerank", "fallback"]
 
@@ -79,6 +82,13 @@ def lib() -> C.CDLL:
             "vrs_last_error": [],
             "vrs_profile": [I32],
             "vrs_stage_times": [P, P],
+            "vrs_mlp_forward": [P, P, I32, P, P, P],
+            "vrs_mlp_backward": [P, P, P, P, P, P, I32, I32, P, P, P, P, P],
+            "vrs_mlp_adam": [P, P, P, P, I32, C.c_float, C.c_float, C.c_float, C.c_float, P],
+            "vrs_chooser_set": [P, P, P],
+            "vrs_chooser_clear": [],
+            "vrs_plan": [P, I32, P, I32, I32, P, P, P, P],
+            "vrs_table_view": [P, I64, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -86,6 +96,9 @@ def lib() -> C.CDLL:
             f.restype = C.c_int32
         L.vrs_last_error.restype = C.c_char_p
         _lib = L
+        # trained access-path chooser shipped with the package (see chooser.py)
+        if os.path.exists(CHOOSER_WEIGHTS):
+            L.vrs_chooser_load(CHOOSER_WEIGHTS.encode())
     return _lib
 
 
@@ -134,10 +147,13 @@ class ScanResult:
 
 
 class Table:
-    """A library-owned table (``vrs_build_table``)."""
+    """A library-owned table (``vrs_build_table``), or a row-prefix view of
+    one (``Table.view``)."""
 
-    def __init__(self, vec: torch.Tensor, attr: torch.Tensor | None = None, store: int = F32,
+    def __init__(self, vec: torch.Tensor | None, attr: torch.Tensor | None = None, store: int = F32,
                  normalize: bool = False, stream=None):
+        if vec is None:  # filled in by view()
+            return
         if not (vec.is_cuda and vec.dtype == torch.float32 and vec.dim() == 2):
             raise ValueError("vec must be a float32 [n, d] CUDA tensor")
         vec = vec.contiguous()
@@ -161,6 +177,26 @@ class Table:
     @property
     def handle(self):
         return self._h
+
+    def view(self, n: int) -> "Table":
+        """Non-owning view of the first n rows (keep the parent alive)."""
+        h = C.c_void_p()
+        _check(lib().vrs_table_view(self._h, int(n), C.byref(h)))
+        v = Table(None)
+        v._h, v._parent = h, self
+        v.n, v.d, v.n_attr, v.store, v.max_norm = int(n), self.d, self.n_attr, self.store, self.max_norm
+        return v
+
+    def plan(self, B: int, terms, k: int, metric: int = L2SQ, strategy: int = STRATEGY_AUTO,
+             tile: int = -1, chooser: int = CHOOSER_LEARNED):
+        """(features[6], strategy, tile) the planner picks for such a call."""
+        o = vrs_opts()
+        o.strategy, o.tile, o.chooser = strategy, tile, chooser
+        f = (C.c_float * 6)()
+        st, tl = C.c_int32(), C.c_int32()
+        p = make_pred(terms)
+        _check(lib().vrs_plan(self._h, B, C.byref(p), k, metric, C.byref(o), f, C.byref(st), C.byref(tl)))
+        return list(f), st.value, tl.value
 
     def close(self):
         if getattr(self, "_h", None):
@@ -263,6 +299,42 @@ def stage_times():
     calls = (C.c_int64 * NUM_STAGES)()
     _check(lib().vrs_stage_times(ms, calls))
     return {STAGES[i]: (ms[i], calls[i]) for i in range(NUM_STAGES)}
+
+
+def mlp_forward(params: torch.Tensor, x: torch.Tensor, act: torch.Tensor | None = None, stream=None):
+    y = torch.empty((x.shape[0], MLP_OUT), dtype=torch.float32, device=x.device)
+    _check(lib().vrs_mlp_forward(_ptr(params), _ptr(x), x.shape[0], _ptr(y), _ptr(act), _stream(stream)))
+    return y
+
+
+def mlp_backward(params, x, y, act, target, mask, stream=None):
+    """Returns (grad [MLP_PARAMS], loss [1]) of the masked mean squared error."""
+    nb = x.shape[0]
+    count = int(mask.sum().item())
+    sig = torch.empty((nb, MLP_OUT + 2 * MLP_HIDDEN), dtype=torch.float32, device=x.device)
+    sq = torch.empty(nb, dtype=torch.float32, device=x.device)
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    _check(lib().vrs_mlp_backward(_ptr(params), _ptr(x), _ptr(y), _ptr(act), _ptr(target), _ptr(mask),
+                                  nb, count, _ptr(sig), _ptr(sq), _ptr(grad), _ptr(loss), _stream(stream)))
+    return grad, loss
+
+
+def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().vrs_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr),
+                              float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def chooser_set(params, mean, std):
+    import numpy as np
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    mu = np.ascontiguousarray(mean, dtype=np.float32)
+    sd = np.ascontiguousarray(std, dtype=np.float32)
+    _check(lib().vrs_chooser_set(p.ctypes.data, mu.ctypes.data, sd.ctypes.data))
+
+
+def chooser_clear():
+    _check(lib().vrs_chooser_clear())
 
 
 def num_tiles() -> int:
