@@ -148,16 +148,67 @@ vrs_status vrs_scan_topk(vrs_table t, const float *q, int32_t B, const vrs_pred 
                          vrs_metric metric, int64_t *out_idx, float *out_dist, void *ws,
                          size_t ws_bytes, const vrs_opts *opts, void *stream);
 
-/* Filtered exact top-k for B queries, each with its own predicate and k.
- *   preds:    [B] vrs_pred (device).
- *   ks:       [B] int32 (device), each in [1, k_max]; 1 <= k_max <= 256.
+/* Filtered exact top-k for B queries, each with its own predicate and k:
+ * the selection of Section 3 (brute-force search with a relational
+ * predicate) per query.  The paper's batched (tensor) form stages one shared
+ * filter before the batch (Sections 3.1-3.2); here every query may differ.
+ *   preds:    [B] vrs_pred (device).  A malformed predicate (column outside
+ *             the table, more than VRS_MAX_TERMS terms, empty range) selects
+ *             no row; it is not an error, since it is only seen on the device.
+ *   ks:       [B] int32 (device), clamped into [1, k_max]; 1 <= k_max <= 256.
  *   out_idx/out_dist: [B][k_max]; row b holds k_b results then padding.
- * One launch sequence for the whole batch (no host synchronisation, so it can
- * be captured into a HIP graph). */
+ *   ws:       >= vrs_batched_workspace_bytes(t, B, k_max, metric, opts).
+ *   opts->tile: batched configuration in [0, vrs_batched_num_configs()), or
+ *             -1 for the one vrs_batched_tune() chose for this (table, B,
+ *             k_max, metric), else a default.  opts->strategy and
+ *             opts->chooser are ignored.
+ * Each query is screened either densely (MFMA kernel shared by 64 queries,
+ * predicate checked per pair) or, when it qualifies few rows, through its own
+ * selection vector (gather kernel); the split is made on the device.  One
+ * launch sequence, no host synchronisation and no memset, so it can be
+ * captured into a HIP graph (vrs_batched_graph_create). */
 vrs_status vrs_scan_topk_batched(vrs_table t, const float *q, int32_t B, const vrs_pred *preds,
                                  const int32_t *ks, int32_t k_max, vrs_metric metric,
                                  int64_t *out_idx, float *out_dist, void *ws, size_t ws_bytes,
                                  const vrs_opts *opts, void *stream);
+
+/* Workspace of vrs_scan_topk_batched (host pointers; opts may be NULL). */
+vrs_status vrs_batched_workspace_bytes(vrs_table t, int32_t B, int32_t k_max, vrs_metric metric,
+                                       const vrs_opts *opts, size_t *bytes);
+
+/* Number of batched configurations (sparse-query row cap, dense work per
+ * workgroup round, rows per sparse work item). */
+int32_t vrs_batched_num_configs(void);
+
+/* Autotuner: runs vrs_scan_topk_batched once per configuration on these
+ * inputs, times each (best of two runs, HIP events on `stream`; this call
+ * synchronizes), remembers the fastest for (t, B, k_max, metric, k' rule) and
+ * leaves its results in the outputs.  best: host int32; ms: host
+ * float[vrs_batched_num_configs()] or NULL.  Every configuration returns the
+ * same results. */
+vrs_status vrs_batched_tune(vrs_table t, const float *q, int32_t B, const vrs_pred *preds,
+                            const int32_t *ks, int32_t k_max, vrs_metric metric, int64_t *out_idx,
+                            float *out_dist, void *ws, size_t ws_bytes, const vrs_opts *opts,
+                            void *stream, int32_t *best, float *ms);
+
+/* HIP-graph form of vrs_scan_topk_batched: the whole launch sequence for
+ * these buffers (queries, predicates, ks, outputs, workspace, opts->n_valid
+ * and opts->certified pointers) captured once and replayed by
+ * vrs_graph_launch; the caller rewrites the buffers' contents between
+ * launches.  With opts->tile == -1 the configuration is autotuned first
+ * (as vrs_batched_tune) unless already known.  Creation runs the sequence
+ * once eagerly (its results land in the outputs) and synchronizes `stream`.
+ * The buffers must stay allocated while the graph exists. */
+typedef struct vrs_graph_s *vrs_graph;
+vrs_status vrs_batched_graph_create(vrs_table t, const float *q, int32_t B, const vrs_pred *preds,
+                                    const int32_t *ks, int32_t k_max, vrs_metric metric,
+                                    int64_t *out_idx, float *out_dist, void *ws, size_t ws_bytes,
+                                    const vrs_opts *opts, void *stream, vrs_graph *out);
+/* Enqueue one replay on `stream` (asynchronous). */
+vrs_status vrs_graph_launch(vrs_graph g, void *stream);
+/* The configuration a graph was captured with. */
+int32_t vrs_graph_config(vrs_graph g);
+vrs_status vrs_graph_destroy(vrs_graph g);
 
 /* Number of kernel configurations ("tiles") the planner chooses from.  An
  * access path ("arm") is strategy x tile: arm = (strategy - 1) * tiles + tile

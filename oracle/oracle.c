@@ -42,6 +42,7 @@
  */
 #include <math.h>
 #include <pthread.h>
+#include <unistd.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -151,22 +152,100 @@ uint8_t oracle_e4m3_from_f64(double v)
     return sign | (uint8_t)pick;
 }
 
-/* Bulk codecs (used by the tests on whole tables). */
+/* Bulk codecs (used by the tests on whole tables).  Rows are independent,
+ * so large tables are split into contiguous row ranges over a few threads;
+ * every row is computed exactly as in the serial loop. */
+typedef struct {
+    void (*fn)(void *ctx, int64_t i0, int64_t i1);
+    void *ctx;
+    int64_t n, per;
+    int t;
+} rows_job_t;
+
+static void *rows_worker(void *arg)
+{
+    rows_job_t *J = (rows_job_t *)arg;
+    int64_t i0 = (int64_t)J->t * J->per, i1 = i0 + J->per;
+    if (i1 > J->n)
+        i1 = J->n;
+    if (i0 < i1)
+        J->fn(J->ctx, i0, i1);
+    return NULL;
+}
+
+static void for_rows(int64_t n, void (*fn)(void *, int64_t, int64_t), void *ctx)
+{
+    long nt = sysconf(_SC_NPROCESSORS_ONLN);
+    if (nt < 1)
+        nt = 1;
+    if (nt > 32)
+        nt = 32;
+    if (n < 65536 || nt == 1) {
+        fn(ctx, 0, n);
+        return;
+    }
+    rows_job_t J[32];
+    pthread_t th[32];
+    int ok[32];
+    int64_t per = (n + nt - 1) / nt;
+    for (int t = 0; t < nt; t++) {
+        J[t] = (rows_job_t){fn, ctx, n, per, t};
+        ok[t] = pthread_create(&th[t], NULL, rows_worker, &J[t]) == 0;
+        if (!ok[t])
+            rows_worker(&J[t]);
+    }
+    for (int t = 0; t < nt; t++)
+        if (ok[t])
+            pthread_join(th[t], NULL);
+}
+
+typedef struct {
+    const float *x;
+    uint16_t *out;
+    int64_t overflow[32];
+    int64_t per;
+} bf16_ctx_t;
+
+static void bf16_rows(void *c, int64_t i0, int64_t i1)
+{
+    bf16_ctx_t *C = (bf16_ctx_t *)c;
+    int64_t ov = 0;
+    for (int64_t i = i0; i < i1; i++)
+        ov += oracle_bf16_from_f32(C->x[i], &C->out[i]);
+    C->overflow[i0 / C->per] = ov;
+}
+
 int64_t oracle_encode_bf16(const float *x, int64_t n, uint16_t *out)
 {
+    long nt = sysconf(_SC_NPROCESSORS_ONLN);
+    if (nt < 1)
+        nt = 1;
+    if (nt > 32)
+        nt = 32;
+    bf16_ctx_t C = {x, out, {0}, n < 65536 || nt == 1 ? (n > 0 ? n : 1) : (n + nt - 1) / nt};
+    for_rows(n, bf16_rows, &C);
     int64_t overflow = 0;
-    for (int64_t i = 0; i < n; i++)
-        overflow += oracle_bf16_from_f32(x[i], &out[i]);
+    for (int t = 0; t < 32; t++)
+        overflow += C.overflow[t];
     return overflow;
 }
 
 /* Row-wise FP8 quantisation: scale_i = max_j |x_ij| / 448 (one float32
  * division), 1 for an all-zero row; code_ij = e4m3(x_ij / scale_i) with the
  * quotient taken in FP64. */
-void oracle_encode_fp8_rows(const float *x, int64_t n, int32_t d, uint8_t *codes, float *scale)
+typedef struct {
+    const float *x;
+    int32_t d;
+    uint8_t *codes;
+    float *scale;
+} fp8_ctx_t;
+
+static void fp8_rows(void *c, int64_t i0, int64_t i1)
 {
-    for (int64_t i = 0; i < n; i++) {
-        const float *row = x + i * (int64_t)d;
+    fp8_ctx_t *C = (fp8_ctx_t *)c;
+    const int32_t d = C->d;
+    for (int64_t i = i0; i < i1; i++) {
+        const float *row = C->x + i * (int64_t)d;
         float m = 0.0f;
         for (int32_t j = 0; j < d; j++) {
             float a = fabsf(row[j]);
@@ -174,26 +253,46 @@ void oracle_encode_fp8_rows(const float *x, int64_t n, int32_t d, uint8_t *codes
                 m = a;
         }
         volatile float s = (m == 0.0f) ? 1.0f : m / 448.0f;
-        scale[i] = s;
+        C->scale[i] = s;
         for (int32_t j = 0; j < d; j++)
-            codes[i * (int64_t)d + j] = oracle_e4m3_from_f64((double)row[j] / (double)s);
+            C->codes[i * (int64_t)d + j] = oracle_e4m3_from_f64((double)row[j] / (double)s);
     }
+}
+
+void oracle_encode_fp8_rows(const float *x, int64_t n, int32_t d, uint8_t *codes, float *scale)
+{
+    fp8_ctx_t C = {x, d, codes, scale};
+    for_rows(n, fp8_rows, &C);
 }
 
 /* Row L2 normalisation for the cosine metric: ||x|| = sqrt(sum_j x_j^2) in
  * FP64 (j ascending, fma), then x_j / ||x|| in FP64 rounded to float32.  An
  * all-zero row is left as is. */
-void oracle_normalize_rows(const float *x, int64_t n, int32_t d, float *out)
+typedef struct {
+    const float *x;
+    int32_t d;
+    float *out;
+} norm_ctx_t;
+
+static void norm_rows(void *c, int64_t i0, int64_t i1)
 {
-    for (int64_t i = 0; i < n; i++) {
-        const float *row = x + i * (int64_t)d;
+    norm_ctx_t *C = (norm_ctx_t *)c;
+    const int32_t d = C->d;
+    for (int64_t i = i0; i < i1; i++) {
+        const float *row = C->x + i * (int64_t)d;
         double acc = 0.0;
         for (int32_t j = 0; j < d; j++)
             acc = fma((double)row[j], (double)row[j], acc);
         double nrm = sqrt(acc);
         for (int32_t j = 0; j < d; j++)
-            out[i * (int64_t)d + j] = (nrm == 0.0) ? row[j] : (float)((double)row[j] / nrm);
+            C->out[i * (int64_t)d + j] = (nrm == 0.0) ? row[j] : (float)((double)row[j] / nrm);
     }
+}
+
+void oracle_normalize_rows(const float *x, int64_t n, int32_t d, float *out)
+{
+    norm_ctx_t C = {x, d, out};
+    for_rows(n, norm_rows, &C);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -17,8 +17,8 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libvrs.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.cpp", "planner.cpp", "k_build.hip", "k_select.hip", "k_stream.hip",
-           "k_mfma.hip", "k_mfma_bf16.hip", "k_finish.hip",
+SOURCES = ["api.cpp", "planner.cpp", "batched.cpp", "k_build.hip", "k_select.hip",
+           "k_stream.hip", "k_mfma.hip", "k_mfma_bf16.hip", "k_finish.hip", "k_batched.hip",
            "k_mlp.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -190,8 +190,11 @@ vrs_status vrs_build_table(const float *vec, int64_t n, int32_t d, const int32_t
         if (e == hipSuccess) e = hipMemcpyAsync(hmax.data(), amax, 4 * n_attr, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipMemcpyAsync(hh.data(), hist, hist_words * 4, hipMemcpyDeviceToHost, s);
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the library's only host sync
-    (void)hipFree(scratch);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the build's one host sync
+    // the column statistics stay on the device for estimates made inside
+    // batched launches
+    t->stats_alloc = scratch;
+    t->dstats = (char *)scratch + 32;
     if (e != hipSuccess) {
         cleanup();
         return fail(VRS_E_HIP, "table build failed: %s", hipGetErrorString(e));
@@ -222,6 +225,7 @@ vrs_status vrs_destroy_table(vrs_table t) {
     if (t->scale) (void)hipFree(t->scale);
     if (t->norm2) (void)hipFree(t->norm2);
     if (t->attr) (void)hipFree(t->attr);
+    if (t->stats_alloc) (void)hipFree(t->stats_alloc);
     delete t;
     return ok();
 }
@@ -410,13 +414,171 @@ vrs_status vrs_scan_topk(vrs_table t, const float *q, int32_t B, const vrs_pred 
                        opts, stream);
 }
 
+static size_t batched_bytes(vrs_table t, int32_t B, int32_t k_max, vrs_metric metric,
+                            const vrs_opts *opts) {
+    if (batched_native(t, k_max, metric, opts)) return batched_workspace(t, B, k_max, metric, opts);
+    vrs_opts o = opts ? *opts : vrs_opts{};
+    o.tile = -1;
+    return plan_workspace(t, B, k_max, &o);
+}
+
+// Argument checks of the batched entry points (everything a launch needs).
+static vrs_status batched_check(vrs_table t, const float *q, int32_t B, const vrs_pred *preds,
+                                const int32_t *ks, int32_t k_max, vrs_metric metric,
+                                int64_t *out_idx, float *out_dist, void *ws, size_t ws_bytes,
+                                const vrs_opts *opts) {
+    if (!t) return fail(VRS_E_ARG, "table is NULL");
+    if (!q || !preds || !ks) return fail(VRS_E_ARG, "queries, preds or ks is NULL");
+    if (!out_idx || !out_dist) return fail(VRS_E_ARG, "outputs are NULL");
+    if (B < 1) return fail(VRS_E_ARG, "B=%d < 1", B);
+    if (k_max < 1 || k_max > 256) return fail(VRS_E_ARG, "k_max=%d outside [1, 256]", k_max);
+    if (metric != VRS_L2SQ && metric != VRS_IP) return fail(VRS_E_ARG, "unknown metric %d", (int)metric);
+    if (metric == VRS_L2SQ && t->store != VRS_F32)
+        return fail(VRS_E_UNSUPPORTED, "L2SQ needs a float32 table (bfloat16/FP8 tables support IP)");
+    if (opts && (opts->kprime_mult < 0 || opts->kprime_mult > 64))
+        return fail(VRS_E_ARG, "opts.kprime_mult=%d outside [0, 64]", opts->kprime_mult);
+    if (opts && (opts->tile < -1 || opts->tile >= batched_num_cfgs()))
+        return fail(VRS_E_ARG, "opts.tile=%d outside [-1, %d)", opts->tile, batched_num_cfgs());
+    const size_t need = batched_bytes(t, B, k_max, metric, opts);
+    if (!ws || ws_bytes < need) return fail(VRS_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    if (((uintptr_t)ws & 255) != 0) return fail(VRS_E_WORKSPACE, "workspace not 256-byte aligned");
+    return VRS_OK;
+}
+
+static hipError_t batched_run(vrs_table t, const float *q, int32_t B, const vrs_pred *preds,
+                              const int32_t *ks, int32_t k_max, vrs_metric metric, int64_t *out_idx,
+                              float *out_dist, void *ws, const vrs_opts *opts, int cfg,
+                              hipStream_t s) {
+    if (batched_native(t, k_max, metric, opts))
+        return run_batched(t, q, B, preds, ks, k_max, metric, out_idx, out_dist, ws, opts, cfg, s);
+    // no persistent dense kernel for this row width: the per-pair masked
+    // screening of the single-predicate path, with per-query predicates
+    vrs_opts o = opts ? *opts : vrs_opts{};
+    o.tile = -1;
+    o.strategy = VRS_STRATEGY_MASK;
+    PredDev p;
+    fold_pred(nullptr, t->n_attr, &p);
+    return run_scan(t, q, B, p, preds, ks, k_max, metric, out_idx, out_dist, ws, &o, s);
+}
+
 vrs_status vrs_scan_topk_batched(vrs_table t, const float *q, int32_t B, const vrs_pred *preds,
                                  const int32_t *ks, int32_t k_max, vrs_metric metric,
                                  int64_t *out_idx, float *out_dist, void *ws, size_t ws_bytes,
                                  const vrs_opts *opts, void *stream) {
-    if (!preds) return fail(VRS_E_ARG, "preds is NULL");
-    return scan_common(t, q, B, nullptr, preds, ks, k_max, metric, out_idx, out_dist, ws, ws_bytes,
-                       opts, stream);
+    vrs_status st = batched_check(t, q, B, preds, ks, k_max, metric, out_idx, out_dist, ws, ws_bytes, opts);
+    if (st != VRS_OK) return st;
+    const int cfg = batched_pick(t, B, k_max, metric, opts);
+    hipError_t e = batched_run(t, q, B, preds, ks, k_max, metric, out_idx, out_dist, ws, opts, cfg,
+                               (hipStream_t)stream);
+    if (e != hipSuccess) return fail(VRS_E_HIP, "batched scan launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+vrs_status vrs_batched_workspace_bytes(vrs_table t, int32_t B, int32_t k_max, vrs_metric metric,
+                                       const vrs_opts *opts, size_t *bytes) {
+    if (!t || !bytes) return fail(VRS_E_ARG, "NULL argument");
+    if (B < 1) return fail(VRS_E_ARG, "B=%d < 1", B);
+    if (k_max < 1 || k_max > 256) return fail(VRS_E_ARG, "k_max=%d outside [1, 256]", k_max);
+    if (metric != VRS_L2SQ && metric != VRS_IP) return fail(VRS_E_ARG, "unknown metric %d", (int)metric);
+    *bytes = batched_bytes(t, B, k_max, metric, opts);
+    return ok();
+}
+
+int32_t vrs_batched_num_configs(void) { return batched_num_cfgs(); }
+
+vrs_status vrs_batched_tune(vrs_table t, const float *q, int32_t B, const vrs_pred *preds,
+                            const int32_t *ks, int32_t k_max, vrs_metric metric, int64_t *out_idx,
+                            float *out_dist, void *ws, size_t ws_bytes, const vrs_opts *opts,
+                            void *stream, int32_t *best, float *ms) {
+    if (!best) return fail(VRS_E_ARG, "best is NULL");
+    vrs_status st = batched_check(t, q, B, preds, ks, k_max, metric, out_idx, out_dist, ws, ws_bytes, opts);
+    if (st != VRS_OK) return st;
+    if (!batched_native(t, k_max, metric, opts))
+        return fail(VRS_E_UNSUPPORTED, "no batched configurations for this table (float32 rows wider than 256)");
+    int b = -1;
+    hipError_t e = batched_tune(t, q, B, preds, ks, k_max, metric, out_idx, out_dist, ws, opts,
+                                (hipStream_t)stream, &b, ms);
+    if (e != hipSuccess) return fail(VRS_E_HIP, "batched autotuning failed: %s", hipGetErrorString(e));
+    *best = b;
+    return ok();
+}
+
+}  // extern "C"
+
+struct vrs_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int cfg = -1;
+    int device = 0;
+};
+
+extern "C" {
+
+vrs_status vrs_batched_graph_create(vrs_table t, const float *q, int32_t B, const vrs_pred *preds,
+                                    const int32_t *ks, int32_t k_max, vrs_metric metric,
+                                    int64_t *out_idx, float *out_dist, void *ws, size_t ws_bytes,
+                                    const vrs_opts *opts, void *stream, vrs_graph *out) {
+    if (!out) return fail(VRS_E_ARG, "out is NULL");
+    *out = nullptr;
+    vrs_status st = batched_check(t, q, B, preds, ks, k_max, metric, out_idx, out_dist, ws, ws_bytes, opts);
+    if (st != VRS_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const bool native = batched_native(t, k_max, metric, opts);
+    int cfg = batched_pick(t, B, k_max, metric, opts);
+    hipError_t e = hipSuccess;
+    if (native && !(opts && opts->tile >= 0) && batched_tuned(t, B, k_max, metric, opts) < 0) {
+        // autotune this shape first
+        int b = -1;
+        e = batched_tune(t, q, B, preds, ks, k_max, metric, out_idx, out_dist, ws, opts, s, &b, nullptr);
+        cfg = b;
+    } else {
+        // one eager run: kernel attributes are set outside the capture
+        e = batched_run(t, q, B, preds, ks, k_max, metric, out_idx, out_dist, ws, opts, cfg, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(VRS_E_HIP, "batched graph warm-up failed: %s", hipGetErrorString(e));
+    auto *g = new vrs_graph_s();
+    g->cfg = cfg;
+    HIP_TRY(hipGetDevice(&g->device));
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+        prof_quiet(true);
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t er = batched_run(t, q, B, preds, ks, k_max, metric, out_idx, out_dist, ws, opts, cfg, cs);
+            e = hipStreamEndCapture(cs, &g->graph);
+            if (er != hipSuccess) e = er;
+        }
+        prof_quiet(false);
+        (void)hipStreamDestroy(cs);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return fail(VRS_E_HIP, "batched graph capture failed: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return ok();
+}
+
+vrs_status vrs_graph_launch(vrs_graph g, void *stream) {
+    if (!g) return fail(VRS_E_ARG, "graph is NULL");
+    HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return ok();
+}
+
+int32_t vrs_graph_config(vrs_graph g) { return g ? g->cfg : -1; }
+
+vrs_status vrs_graph_destroy(vrs_graph g) {
+    if (!g) return fail(VRS_E_ARG, "graph is NULL");
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return ok();
 }
 
 }  // extern "C"

@@ -181,6 +181,44 @@ struct TopkLds {
     }
 };
 
+// ---------------------------------------- stored row element decoding
+// Elements of one 16-byte load of a stored row, widened exactly to float.
+template <int STORE>
+struct Elem;
+template <>
+struct Elem<VRS_F32> {
+    static constexpr int V = 4;      // elements per 16-byte load
+    __device__ static void decode(const uint4 &w, float *x) {
+        x[0] = __uint_as_float(w.x);
+        x[1] = __uint_as_float(w.y);
+        x[2] = __uint_as_float(w.z);
+        x[3] = __uint_as_float(w.w);
+    }
+};
+template <>
+struct Elem<VRS_BF16> {
+    static constexpr int V = 8;
+    __device__ static void decode(const uint4 &w, float *x) {
+        const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            x[2 * i] = __uint_as_float(v[i] << 16);
+            x[2 * i + 1] = __uint_as_float(v[i] & 0xffff0000u);
+        }
+    }
+};
+template <>
+struct Elem<VRS_FP8E4M3> {
+    static constexpr int V = 16;
+    __device__ static void decode(const uint4 &w, float *x) {
+        const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) x[4 * i + j] = e4m3_to_f32((v[i] >> (8 * j)) & 0xffu);
+    }
+};
+
 __host__ __device__ inline int next_pow2(int x) {
     int p = 1;
     while (p < x) p <<= 1;

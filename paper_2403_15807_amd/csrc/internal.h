@@ -24,14 +24,21 @@ struct vrs_table_s {
     int64_t attr_stride = 0;    // column stride of attr (the parent's n for a view)
     bool owner = true;          // false for a view (vrs_table_view)
     double max_norm = 0.0;      // max_i ||x_i|| of stored rows (rounded up)
-    // per-column equi-width histograms for selectivity estimates
+    // per-column equi-width histograms for selectivity estimates (host copy,
+    // and a device copy for estimates made inside a batched launch)
     std::vector<int32_t> amin, amax;
     std::vector<std::vector<uint32_t>> hist;
+    void *dstats = nullptr;     // device: amin[64] | amax[64] | hist[n_attr][HIST_BINS]
+    void *stats_alloc = nullptr;  // the allocation holding dstats (owner only)
 };
 
 namespace vrs {
 
 constexpr int HIST_BINS = 256;
+
+// Raise a kernel's dynamic LDS limit to `bytes` (once per kernel and size, so
+// launches made while a stream is being captured set nothing).
+void ensure_dyn_lds(const void *kernel, size_t bytes);
 
 int elem_bytes(vrs_dtype t);
 int pad_dim(int d, vrs_dtype t);
@@ -57,6 +64,13 @@ int screen_mfma_occupancy(int Kp, int CB, int qm);
 hipError_t launch_prep_batched(const vrs_pred *preds, const int32_t *ks, int32_t B, int32_t kmax,
                                int32_t n_attr, int kmult, int f32_rule, PredDev *out,
                                int32_t *kc, int32_t *kps, hipStream_t s);
+// Query preparation of the batched uneven form, by position: queries in the
+// order of `perm`, with their folded predicates and k, k' gathered alongside.
+hipError_t launch_prep_permuted(const float *q, const int32_t *perm, int32_t B, int32_t d,
+                                int32_t dp, const PredDev *pred_o, const int32_t *kc_o,
+                                const int32_t *kps_o, float *qp, double *qnorm, float *qn2,
+                                uint16_t *qhl, uint64_t *gthr, int32_t *fail_count,
+                                PredDev *pred_p, int32_t *kc_p, int32_t *kps_p, hipStream_t s);
 
 // ---- screening (k_stream.hip): per-(query, chunk) sorted lists of the K
 // smallest screening keys.
@@ -81,9 +95,29 @@ struct ScreenArgs {
     int metric;
     int32_t K, Kp, CB;
     int32_t n_chunks;
+    int32_t shared_rows;           // rows are read by several query tiles: keep them cacheable
     uint64_t *partials;            // [B][n_chunks][K]
     uint64_t *cbuf;                // [B][n_chunks][CB] candidate buffers (MFMA kernels)
     uint64_t *gthr;                // [B] smallest K-th key published by any chunk
+    // batched uneven form only (null otherwise): control words written on the
+    // device (dense query count, row chunks per dense query, work queues) and
+    // the sparse queries' id lists; see BatchCtl.
+    int32_t *bctl;
+    const int64_t *sp_off;         // [B] by position: first id of the query's list in sp_pool
+    const int32_t *sp_cnt;         // [B] by position: ids in the list
+    const int32_t *seg_pre;        // [B + 1] segments of the sparse positions, prefix sums
+    const int32_t *sp_pool;
+    const int32_t *kps;            // [B] by position: per-query k'
+};
+
+// Control words of a batched launch (int32, in the workspace).
+enum BatchCtl {
+    BC_NDENSE = 0,   // queries screened by the dense MFMA kernel (positions [0, n_dense))
+    BC_NSPARSE = 1,  // queries screened by the sparse gather kernel
+    BC_NC = 2,       // row chunks (lists) per dense query
+    BC_QDENSE = 3,   // 8 work-queue counters of the dense kernel, one per XCD
+    BC_QSPARSE = 11, // work-queue counter of the sparse kernel
+    BC_WORDS = 16
 };
 hipError_t launch_screen_stream(const ScreenArgs &a, int qt, hipStream_t s);
 size_t screen_stream_lds(int qt, int Kp, int CB, int dp);
@@ -93,6 +127,81 @@ hipError_t launch_screen_mfma_bf16(const ScreenArgs &a, hipStream_t s);
 size_t screen_mfma_bf16_lds();
 bool screen_mfma_bf16_supported(int dp, vrs_dtype store, int metric, int Kp, int CB);
 bool screen_mfma_supported(int dp, vrs_dtype store, int Kp, int CB);
+// persistent forms for the batched uneven launch (queue-driven, one grid)
+hipError_t launch_screen_mfma_persistent(const ScreenArgs &a, int qm, int grid, hipStream_t s);
+hipError_t launch_screen_mfma_bf16_persistent(const ScreenArgs &a, int grid, hipStream_t s);
+
+// Fold a caller's predicate (int64 half-open bounds) into inclusive int32
+// ranges: a term on a column outside [0, n_attr), a term count outside
+// [0, VRS_MAX_TERMS] or an empty range selects nothing (nterms = -1).
+__device__ inline PredDev fold_pred_dev(const vrs_pred &p, int n_attr) {
+    PredDev o;
+    o.nterms = 0;
+    for (int t = 0; t < 4; ++t) {
+        o.col[t] = 0;
+        o.lo[t] = 0;
+        o.hi[t] = -1;
+    }
+    bool empty = p.nterms < 0 || p.nterms > VRS_MAX_TERMS;
+    if (!empty) {
+        for (int t = 0; t < p.nterms; ++t) {
+            const vrs_range &r = p.term[t];
+            const int64_t lo = r.lo, hi = r.hi;
+            if (r.col < 0 || r.col >= n_attr || hi <= lo || hi <= (int64_t)INT32_MIN ||
+                lo > (int64_t)INT32_MAX) {
+                empty = true;
+                break;
+            }
+            o.col[t] = r.col;
+            o.lo[t] = (int32_t)(lo < (int64_t)INT32_MIN ? (int64_t)INT32_MIN : lo);
+            o.hi[t] = (int32_t)(hi - 1 > (int64_t)INT32_MAX ? (int64_t)INT32_MAX : hi - 1);
+        }
+        o.nterms = p.nterms;
+    }
+    if (empty) o.nterms = -1;
+    return o;
+}
+
+// k' of one query (the host rule of the planner).
+__device__ inline int kprime_dev(int k, int kmult, int f32_rule) {
+    int kp = kmult > 0 ? k * kmult : (f32_rule ? max(2 * k, k + 32) : 4 * k);
+    return min(max(kp, k), 1024);
+}
+
+// ---- batched uneven form (k_batched.hip)
+constexpr int BSUB_ROWS = 2048;    // rows per wave in the batched predicate passes
+struct BatchArgs {
+    const vrs_pred *preds;         // [B] caller's predicates
+    const int32_t *ks;             // [B] caller's k
+    int32_t B, kmax, n_attr, kmult, f32_rule;
+    const int32_t *attr;
+    int64_t n, an;
+    const void *dstats;            // device column statistics (table)
+    int64_t rows_cap;              // a query is sparse when it qualifies at most this many rows
+    int32_t seg_rows;              // target rows per sparse work item
+    int32_t seg_max;               // at most this many segments per sparse query
+    int32_t items_target;          // dense work items wanted (sets the row chunks per query)
+    int32_t nc_cap;                // most row chunks per dense query
+    int32_t qm;                    // queries per dense work item
+    int32_t nsub;                  // 2048-row sub-blocks
+    PredDev *pred_o;               // [B] folded predicates, by query
+    int32_t *kc_o, *kps_o;         // [B] clamped k and k', by query
+    uint8_t *cand;                 // [B] sparse candidate by the estimate
+    uint32_t *subcnt;              // [nsub][B] qualifying rows per sub-block, then prefix
+    int32_t *tot;                  // [B] qualifying rows (-1: not counted)
+    int32_t *perm;                 // [B] position -> query
+    int64_t *sp_off;               // [B] by position
+    int32_t *sp_cnt;               // [B] by position
+    int32_t *seg_pre;              // [B + 1]
+    int64_t *list_off;             // [B] by position: first list in the partials
+    int32_t *nlists;               // [B] by position: lists in the partials
+    int32_t *pool;                 // sparse id lists
+    int32_t *ctl;                  // BatchCtl words
+};
+hipError_t launch_batch_classify(const BatchArgs &b, hipStream_t s);
+hipError_t launch_batch_lists(const BatchArgs &b, hipStream_t s);
+hipError_t launch_screen_sparse(const ScreenArgs &a, int grid, hipStream_t s);
+size_t screen_sparse_lds(int K, int dp);
 
 // ---- merge, rerank, fallback (k_finish.hip)
 struct FinishArgs {
@@ -117,6 +226,9 @@ struct FinishArgs {
     int32_t K;                     // list length = max k' + 1
     int32_t n_chunks;
     const uint64_t *partials;
+    const int64_t *list_off;       // batched uneven form: [B] first list of each position
+    const int32_t *nlists;         // and its list count (null: n_chunks lists per query)
+    const int32_t *perm;           // position -> query index (null: identity)
     uint64_t *merge_mid;           // [B][ceil(n_chunks/2048)][K] (two-level merge)
     uint64_t *merged;              // [B][K]
     double rel, abs_ip, abs_l2, max_norm;  // screening error model

@@ -1,0 +1,431 @@
+// k_batched.hip -- the batched uneven form: thousands of concurrent queries,
+// each with its own conjunctive range predicate and its own k, in one
+// launch sequence that never returns to the host (so it can be captured
+// into a HIP graph and replayed).
+//
+// The paper's batched (tensor) form stages one shared filter before the
+// batch (Sections 3.1-3.2); with a predicate per query the two ways of
+// pushing the predicate down (Section 3.2: checked on the fly per pair, or
+// staged into a selection vector first) are chosen per query:
+//   * dense queries (many qualifying rows) run on the MFMA screening kernel,
+//     64 queries per work item sharing every row read, with the predicate
+//     checked per (query, row) pair (compute-then-mask);
+//   * sparse queries (few qualifying rows) get their own selection vector
+//     and a gather-then-compute VALU pass over exactly those rows.
+// The split is decided on the device: a histogram estimate proposes the
+// sparse candidates, an exact count confirms them (a query whose count
+// exceeds the cap goes dense), and the queries are permuted so that the
+// dense ones occupy positions [0, n_dense).
+//
+// Passes over the attribute columns are organised by 2048-row sub-blocks,
+// one wave each: the wave keeps its rows' values of the first two columns
+// in registers and walks the queries, so the columns are read once per
+// pass however many queries there are; qualifying rows are found 64 at a
+// time with one ballot per row group.
+#include "internal.h"
+
+namespace vrs {
+
+namespace {
+
+constexpr int GROUPS = BSUB_ROWS / 64;  // 64-row groups per sub-block
+
+__device__ __forceinline__ bool eval_cached(const PredDev &p, int32_t v0, int32_t v1,
+                                            const int32_t *__restrict__ attr, int64_t an,
+                                            int64_t row) {
+    bool ok = p.nterms >= 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (t < p.nterms) {
+            const int c = p.col[t];
+            const int32_t v = c == 0 ? v0 : (c == 1 ? v1 : attr[(int64_t)c * an + row]);
+            ok = ok && v >= p.lo[t] && v <= p.hi[t];
+        }
+    }
+    return ok;
+}
+
+// Estimated fraction of rows satisfying p: per term, the histogram mass of
+// the range (uniform within a bin), multiplied over terms (independence).
+__device__ double est_fraction(const void *dstats, int n_attr, const PredDev &p) {
+    if (p.nterms < 0) return 0.0;
+    const int32_t *amin = (const int32_t *)dstats, *amax = amin + 64;
+    const uint32_t *hist = (const uint32_t *)(amax + 64);
+    double sel = 1.0;
+    for (int t = 0; t < p.nterms; ++t) {
+        const int c = p.col[t];
+        const int64_t lo = amin[c], span = (int64_t)amax[c] - lo + 1;
+        double hit = 0.0, tot = 0.0;
+        for (int b = 0; b < HIST_BINS; ++b) {
+            const int64_t v0 = lo + ((int64_t)b * span + HIST_BINS - 1) / HIST_BINS;
+            const int64_t v1 = lo + ((int64_t)(b + 1) * span + HIST_BINS - 1) / HIST_BINS;
+            const double cb = (double)hist[(int64_t)c * HIST_BINS + b];
+            tot += cb;
+            if (v1 <= v0 || cb == 0.0) continue;
+            const int64_t a = max(v0, (int64_t)p.lo[t]), z = min(v1 - 1, (int64_t)p.hi[t]);
+            if (z >= a) hit += cb * (double)(z - a + 1) / (double)(v1 - v0);
+        }
+        sel *= tot > 0.0 ? hit / tot : 0.0;
+    }
+    return sel;
+}
+
+// Fold predicates and k, propose sparse candidates, reset the control words.
+__global__ __launch_bounds__(256) void batch_prepare_kernel(BatchArgs a) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b == 0)
+        for (int i = 0; i < BC_WORDS; ++i) a.ctl[i] = 0;
+    if (b >= a.B) return;
+    const PredDev o = fold_pred_dev(a.preds[b], a.n_attr);
+    a.pred_o[b] = o;
+    int k = a.ks[b];
+    k = k < 1 ? 1 : (k > a.kmax ? a.kmax : k);
+    a.kc_o[b] = k;
+    a.kps_o[b] = kprime_dev(k, a.kmult, a.f32_rule);
+    bool cand = false;
+    if (a.rows_cap > 0) {
+        if (o.nterms < 0)
+            cand = true;
+        else if (o.nterms > 0)
+            cand = est_fraction(a.dstats, a.n_attr, o) * (double)a.n <= 4.0 * (double)a.rows_cap + 1024.0;
+    }
+    a.cand[b] = cand;
+    a.tot[b] = -1;
+}
+
+// Load the first two attribute columns of a wave's sub-block (lane l holds
+// rows row0 + 64 g + l).
+__device__ __forceinline__ void load_sub(const BatchArgs &a, int64_t row0, int lane,
+                                         int32_t (&v0)[GROUPS], int32_t (&v1)[GROUPS]) {
+#pragma unroll
+    for (int g = 0; g < GROUPS; ++g) {
+        const int64_t row = row0 + g * 64 + lane;
+        const bool in = row < a.n;
+        v0[g] = (in && a.n_attr > 0) ? a.attr[row] : 0;
+        v1[g] = (in && a.n_attr > 1) ? a.attr[a.an + row] : 0;
+    }
+}
+
+// Qualifying rows of every sparse candidate in every sub-block.
+__global__ __launch_bounds__(256) void batch_count_kernel(BatchArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int sub = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (sub >= a.nsub) return;
+    const int64_t row0 = (int64_t)sub * BSUB_ROWS;
+    int32_t v0[GROUPS], v1[GROUPS];
+    load_sub(a, row0, lane, v0, v1);
+    for (int b = 0; b < a.B; ++b) {
+        if (!a.cand[b]) continue;
+        const PredDev p = a.pred_o[b];
+        uint32_t c = 0;
+        if (p.nterms >= 0) {
+#pragma unroll
+            for (int g = 0; g < GROUPS; ++g) {
+                const int64_t row = row0 + g * 64 + lane;
+                const bool q = row < a.n && eval_cached(p, v0[g], v1[g], a.attr, a.an, row);
+                c += (uint32_t)__popcll(__ballot(q));
+            }
+        }
+        if (lane == 0) a.subcnt[(int64_t)sub * a.B + b] = c;
+    }
+}
+
+// Per candidate: total count, and the sub-block counts turned into
+// exclusive prefix sums (each sub-block's first slot in the query's list).
+__global__ __launch_bounds__(256) void batch_total_kernel(BatchArgs a) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.B || !a.cand[b]) return;
+    uint32_t run = 0;
+    for (int sub = 0; sub < a.nsub; ++sub) {
+        uint32_t *p = a.subcnt + (int64_t)sub * a.B + b;
+        const uint32_t c = *p;
+        *p = run;
+        run += c;
+    }
+    a.tot[b] = (int32_t)run;
+}
+
+// Exclusive prefix sum over the 1024 threads of the block; returns the total.
+template <typename T>
+__device__ T block_scan_1024(T v, T &excl, T *wsum /* [16] LDS */) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    T before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+        const T s = wsum[w];
+        if (w < wave) before += s;
+        total += s;
+    }
+    __syncthreads();
+    excl = before + x - v;
+    return total;
+}
+
+// Final split and the permutation (dense queries first, each side in query
+// order), list layout, sparse list offsets and work-item prefix sums.
+__global__ __launch_bounds__(1024) void batch_order_kernel(BatchArgs a) {
+    __shared__ int32_t ws32[16];
+    __shared__ long long ws64[16];
+    const int tid = threadIdx.x;
+    auto is_sparse = [&](int b) { return a.cand[b] && a.tot[b] >= 0 && (int64_t)a.tot[b] <= a.rows_cap; };
+    int32_t ns = 0;
+    for (int c0 = 0; c0 < a.B; c0 += 1024) {
+        const int b = c0 + tid;
+        int32_t e;
+        ns += block_scan_1024<int32_t>(b < a.B && is_sparse(b) ? 1 : 0, e, ws32);
+    }
+    const int32_t nd = a.B - ns;
+    const int32_t ndt = (nd + a.qm - 1) / a.qm;
+    int32_t nc = ndt > 0 ? a.items_target / ndt : a.nc_cap;
+    nc = nc / 8 * 8;
+    nc = max(8, min(a.nc_cap, nc));
+    int32_t run_d = 0, run_s = 0, run_seg = 0;
+    long long run_off = 0;
+    for (int c0 = 0; c0 < a.B; c0 += 1024) {
+        const int b = c0 + tid;
+        const bool in = b < a.B;
+        const bool sp = in && is_sparse(b);
+        const int32_t cnt = sp ? a.tot[b] : 0;
+        const int32_t segs = cnt == 0 ? 0 : min(a.seg_max, (cnt + a.seg_rows - 1) / a.seg_rows);
+        int32_t rd, rs, rseg;
+        long long roff;
+        const int32_t td = block_scan_1024<int32_t>(in && !sp ? 1 : 0, rd, ws32);
+        const int32_t ts = block_scan_1024<int32_t>(sp ? 1 : 0, rs, ws32);
+        const int32_t tseg = block_scan_1024<int32_t>(segs, rseg, ws32);
+        const long long toff = block_scan_1024<long long>((long long)cnt, roff, ws64);
+        if (in) {
+            if (!sp) {
+                const int pos = run_d + rd;
+                a.perm[pos] = b;
+                a.list_off[pos] = (int64_t)pos * nc;
+                a.nlists[pos] = nc;
+                a.sp_off[pos] = 0;
+                a.sp_cnt[pos] = 0;
+            } else {
+                const int j = run_s + rs, pos = nd + j;
+                a.perm[pos] = b;
+                a.sp_off[pos] = run_off + roff;
+                a.sp_cnt[pos] = cnt;
+                a.seg_pre[j] = run_seg + rseg;
+                a.list_off[pos] = (int64_t)nd * nc + run_seg + rseg;
+                a.nlists[pos] = segs;
+            }
+        }
+        run_d += td;
+        run_s += ts;
+        run_seg += tseg;
+        run_off += toff;
+    }
+    if (tid == 0) {
+        a.seg_pre[ns] = run_seg;
+        a.ctl[BC_NDENSE] = nd;
+        a.ctl[BC_NSPARSE] = ns;
+        a.ctl[BC_NC] = nc;
+    }
+}
+
+// Selection vectors of the sparse queries: ascending row ids per query.
+__global__ __launch_bounds__(256) void batch_write_kernel(BatchArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int sub = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (sub >= a.nsub) return;
+    const int nd = a.ctl[BC_NDENSE];
+    const int64_t row0 = (int64_t)sub * BSUB_ROWS;
+    int32_t v0[GROUPS], v1[GROUPS];
+    load_sub(a, row0, lane, v0, v1);
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int pos = nd; pos < a.B; ++pos) {
+        if (a.sp_cnt[pos] == 0) continue;
+        const int b = a.perm[pos];
+        const PredDev p = a.pred_o[b];
+        int32_t *dst = a.pool + a.sp_off[pos] + a.subcnt[(int64_t)sub * a.B + b];
+#pragma unroll
+        for (int g = 0; g < GROUPS; ++g) {
+            const int64_t row = row0 + g * 64 + lane;
+            const bool q = row < a.n && eval_cached(p, v0[g], v1[g], a.attr, a.an, row);
+            const uint64_t m = __ballot(q);
+            if (q) dst[__popcll(m & below)] = (int32_t)row;
+            dst += __popcll(m);
+        }
+    }
+}
+
+// ------------------------------------------------- sparse gather screening
+// Persistent: every workgroup takes (query, segment) items from a queue
+// until none is left.  An item is a contiguous part of one query's
+// selection vector; its rows are read with 16-byte loads, 8 lanes per
+// 128-byte block as in the streaming kernel, and the FP32 distances go to
+// an LDS top-k list whose K smallest keys become one list of the merge.
+constexpr int SU = 2;                  // rows per lane-group per step
+constexpr int STILE = 4 * 8 * SU;      // rows per workgroup step
+constexpr int SNB = 4;                 // 128-byte blocks loaded together
+constexpr int SP_CB_MIN = 256;
+
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 load_nt(const uint4 *p) {
+    v4u32 v = __builtin_nontemporal_load((const v4u32 *)p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+__host__ __device__ inline int sparse_m(int K) { return next_pow2(next_pow2(K) + SP_CB_MIN); }
+
+template <int STORE, int METRIC>
+__global__ __launch_bounds__(256) void screen_sparse_kernel(ScreenArgs a) {
+    constexpr int V = Elem<STORE>::V;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane >> 3, s = lane & 7;
+    const int M = sparse_m(a.K);
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint64_t *keys = (uint64_t *)smem;
+    uint64_t *thr = keys + M;
+    int *cnt = (int *)(thr + 1);
+    float *qs = (float *)(((uintptr_t)(cnt + 4) + 15) & ~(uintptr_t)15);  // [dp]
+    __shared__ int item_s;
+
+    const int nd = a.bctl[BC_NDENSE], ns = a.bctl[BC_NSPARSE], nc = a.bctl[BC_NC];
+    const int n_items = a.seg_pre[ns];
+    const int eb = STORE == VRS_F32 ? 4 : (STORE == VRS_BF16 ? 2 : 1);
+    const int64_t row_bytes = (int64_t)a.dp * eb;
+    const int nblk = (int)(row_bytes / 128);
+    const char *base = (const char *)a.rows;
+
+    for (;;) {
+        if (tid == 0) item_s = atomicAdd(&a.bctl[BC_QSPARSE], 1);
+        __syncthreads();
+        const int it = item_s;
+        if (it >= n_items) break;
+        // the sparse query j owning item `it`: seg_pre[j] <= it < seg_pre[j + 1]
+        int lo = 0, hi = ns;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.seg_pre[mid] <= it) lo = mid;
+            else hi = mid;
+        }
+        const int j = lo, pos = nd + j;
+        const int seg = it - a.seg_pre[j], segs = a.seg_pre[j + 1] - a.seg_pre[j];
+        const int64_t cntq = a.sp_cnt[pos];
+        const int64_t r0 = cntq * seg / segs, r1 = cntq * (seg + 1) / segs;
+        const int32_t *ids = a.sp_pool + a.sp_off[pos];
+        const int Kq = a.kps[pos] + 1;
+        const int Kp = next_pow2(Kq);
+        TopkLds<uint64_t> tk{keys, cnt, thr, 1, Kq, Kp, M - Kp};
+        for (int i = tid; i < a.dp; i += 256) qs[i] = a.qp[(int64_t)pos * a.dp + i];
+        tk.init(tid, 256);  // barrier: item_s, qs and the list are ready
+
+        for (int64_t t0 = r0; t0 < r1; t0 += STILE) {
+            int64_t row[SU];
+            bool ok[SU];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int64_t p = t0 + u * 32 + wave * 8 + r;
+                ok[u] = p < r1;
+                row[u] = ok[u] ? (int64_t)ids[p] : 0;
+            }
+            float acc[SU] = {};
+            for (int cg = 0; cg < nblk; cg += SNB) {
+                uint4 w[SU][SNB];
+#pragma unroll
+                for (int c = 0; c < SNB; ++c)
+#pragma unroll
+                    for (int u = 0; u < SU; ++u)
+                        w[u][c] = (ok[u] && cg + c < nblk)
+                                      ? load_nt((const uint4 *)(base + row[u] * row_bytes + (cg + c) * 128 + s * 16))
+                                      : make_uint4(0, 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < SNB; ++c) {
+                    if (cg + c >= nblk) break;
+                    const float *qb = qs + ((cg + c) * 128 + s * 16) / eb;
+#pragma unroll
+                    for (int u = 0; u < SU; ++u) {
+                        float x[V];
+                        Elem<STORE>::decode(w[u][c], x);
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            if (METRIC == VRS_L2SQ) {
+                                const float t = qb[v] - x[v];
+                                acc[u] = fmaf(t, t, acc[u]);
+                            } else {
+                                acc[u] = fmaf(qb[v], x[v], acc[u]);
+                            }
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                float v = acc[u];
+                v += __shfl_xor(v, 1);
+                v += __shfl_xor(v, 2);
+                v += __shfl_xor(v, 4);
+                if (s == 0 && ok[u]) {
+                    float dist;
+                    if (METRIC == VRS_L2SQ)
+                        dist = v;
+                    else if (STORE == VRS_FP8E4M3)
+                        dist = -(a.scale[row[u]] * v);
+                    else
+                        dist = -v;
+                    tk.push(0, make_key(dist, (uint32_t)row[u]));
+                }
+            }
+            __syncthreads();
+            if (tk.need_flush(STILE)) {
+                tk.flush(tid, 256);
+                if (tid == 0 && thr[0] != KEY_INF) {
+                    const uint64_t prev = atomicMin((unsigned long long *)(a.gthr + pos),
+                                                    (unsigned long long)thr[0]);
+                    if (prev < thr[0]) thr[0] = prev;
+                }
+                __syncthreads();
+            }
+        }
+        if (tk.need_flush(M - Kp)) tk.flush(tid, 256);
+        uint64_t *dst = a.partials + ((int64_t)nd * nc + a.seg_pre[j] + seg) * a.K;
+        for (int i = tid; i < a.K; i += 256) dst[i] = i < Kq ? keys[i] : KEY_INF;
+        __syncthreads();  // LDS and item_s are reused by the next item
+    }
+}
+
+}  // namespace
+
+hipError_t launch_batch_classify(const BatchArgs &b, hipStream_t s) {
+    batch_prepare_kernel<<<(b.B + 255) / 256, 256, 0, s>>>(b);
+    if (b.rows_cap > 0) {
+        batch_count_kernel<<<(b.nsub + 3) / 4, 256, 0, s>>>(b);
+        batch_total_kernel<<<(b.B + 255) / 256, 256, 0, s>>>(b);
+    }
+    batch_order_kernel<<<1, 1024, 0, s>>>(b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_lists(const BatchArgs &b, hipStream_t s) {
+    if (b.rows_cap > 0) batch_write_kernel<<<(b.nsub + 3) / 4, 256, 0, s>>>(b);
+    return hipGetLastError();
+}
+
+size_t screen_sparse_lds(int K, int dp) { return (size_t)sparse_m(K) * 8 + 8 + 16 + 16 + (size_t)dp * 4; }
+
+hipError_t launch_screen_sparse(const ScreenArgs &a, int grid, hipStream_t s) {
+    const size_t lds = screen_sparse_lds(a.K, a.dp);
+    if (a.metric == VRS_L2SQ) {
+        if (a.store != VRS_F32) return hipErrorInvalidValue;
+        screen_sparse_kernel<VRS_F32, VRS_L2SQ><<<grid, 256, lds, s>>>(a);
+    } else if (a.store == VRS_F32) {
+        screen_sparse_kernel<VRS_F32, VRS_IP><<<grid, 256, lds, s>>>(a);
+    } else if (a.store == VRS_BF16) {
+        screen_sparse_kernel<VRS_BF16, VRS_IP><<<grid, 256, lds, s>>>(a);
+    } else {
+        screen_sparse_kernel<VRS_FP8E4M3, VRS_IP><<<grid, 256, lds, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace vrs

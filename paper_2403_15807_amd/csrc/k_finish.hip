@@ -21,14 +21,29 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, 
                                                    float *__restrict__ qn2,
                                                    uint16_t *__restrict__ qhl,
                                                    uint64_t *__restrict__ gthr,
-                                                   int32_t *__restrict__ fail_count) {
-    const int b = blockIdx.x;
-    if (threadIdx.x == 0) gthr[b] = KEY_INF;
+                                                   int32_t *__restrict__ fail_count,
+                                                   const int32_t *__restrict__ perm,
+                                                   const PredDev *__restrict__ pred_o,
+                                                   const int32_t *__restrict__ kc_o,
+                                                   const int32_t *__restrict__ kps_o,
+                                                   PredDev *__restrict__ pred_p,
+                                                   int32_t *__restrict__ kc_p,
+                                                   int32_t *__restrict__ kps_p) {
+    const int b = blockIdx.x;                 // position
+    const int src = perm ? perm[b] : b;       // query
+    if (threadIdx.x == 0) {
+        gthr[b] = KEY_INF;
+        if (perm) {
+            pred_p[b] = pred_o[src];
+            kc_p[b] = kc_o[src];
+            kps_p[b] = kps_o[src];
+        }
+    }
     if (b == 0 && threadIdx.x == 0) *fail_count = 0;
     __shared__ double red[256];
     double acc = 0.0;
     for (int j = threadIdx.x; j < dp; j += 256) {
-        float v = j < d ? q[(int64_t)b * d + j] : 0.0f;
+        float v = j < d ? q[(int64_t)src * d + j] : 0.0f;
         qp[(int64_t)b * dp + j] = v;
         acc += (double)v * (double)v;
         if (qhl) {  // bfloat16 hi/lo split (round to nearest-even both times)
@@ -135,12 +150,22 @@ constexpr int MERGE_HMAX = 4096;
 __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__restrict__ src,
                                                               int n_lists, int G, int K, int Kp,
                                                               int CB, uint64_t *__restrict__ dst,
-                                                              int n_out) {
+                                                              int n_out,
+                                                              const int64_t *__restrict__ list_off,
+                                                              const int32_t *__restrict__ nlists) {
     constexpr int T = MERGE_THREADS;
     const int g = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int l0 = g * G, l1 = min(n_lists, l0 + G), L = l1 - l0;
-    const uint64_t *lists = src + ((int64_t)b * n_lists + l0) * K;
+    // query b's lists: n_lists of them at b * n_lists, or (batched uneven
+    // form) nlists[b] of them at list_off[b]
+    const int nb = nlists ? nlists[b] : n_lists;
+    const int64_t first = nlists ? list_off[b] : (int64_t)b * n_lists;
+    const int l0 = g * G, l1 = min(nb, l0 + G), L = l1 - l0;
+    if (L <= 0) {  // no list: an empty result
+        for (int i = tid; i < K; i += T) dst[((int64_t)b * n_out + g) * K + i] = KEY_INF;
+        return;
+    }
+    const uint64_t *lists = src + (first + l0) * K;
     const int M = Kp + CB;
     uint64_t *keys = (uint64_t *)smem;                         // heads, then the top-k list
     const int region = max(M, MERGE_HMAX);
@@ -228,6 +253,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(FinishArgs a) {
     constexpr int V = STORE == VRS_F32 ? 4 : (STORE == VRS_BF16 ? 8 : 16);
     constexpr int EB = 16 / V;
     const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ob = a.perm ? a.perm[b] : b;  // the query at position b
     const int kb = k_of(a, b), kpb = kp_of(a, b);
     extern __shared__ __align__(16) unsigned char smem[];
     const int Mc = next_pow2(max(kpb, 2));
@@ -235,7 +261,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(FinishArgs a) {
     uint4 *stage = (uint4 *)(cand + Mc);                     // [4][64][RR_CHUNK + 1]
     float *qrow = (float *)(stage + 4 * 64 * (RR_CHUNK + 1)); // [dp], zero padded
     __shared__ int n_cand_s;
-    for (int j = tid; j < a.dp; j += 256) qrow[j] = j < a.d ? a.q[(int64_t)b * a.d + j] : 0.0f;
+    for (int j = tid; j < a.dp; j += 256) qrow[j] = j < a.d ? a.q[(int64_t)ob * a.d + j] : 0.0f;
     if (tid == 0) n_cand_s = 0;
     __syncthreads();
     const uint64_t *lst = a.merged + (int64_t)b * a.K;
@@ -311,7 +337,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(FinishArgs a) {
     if (ok) {
         const int m = min(kb, n_cand);
         for (int i = tid; i < a.kmax; i += 256) {
-            int64_t o = (int64_t)b * a.kmax + i;
+            int64_t o = (int64_t)ob * a.kmax + i;
             if (i < m) {
                 a.out_idx[o] = (int64_t)cand[i].lo;
                 a.out_dist[o] = (float)unord64(cand[i].hi);
@@ -321,11 +347,11 @@ __global__ __launch_bounds__(256) void rerank_kernel(FinishArgs a) {
             }
         }
         if (tid == 0) {
-            if (a.n_valid) a.n_valid[b] = m;
-            if (a.certified) a.certified[b] = 1;
+            if (a.n_valid) a.n_valid[ob] = m;
+            if (a.certified) a.certified[ob] = 1;
         }
     } else if (tid == 0) {
-        if (a.certified) a.certified[b] = 0;
+        if (a.certified) a.certified[ob] = 0;
         int slot = atomicAdd(a.fail_count, 1);
         a.fail_list[slot] = b;
     }
@@ -350,10 +376,11 @@ __global__ __launch_bounds__(256) void fallback_scan_kernel(FinishArgs a) {
     for (int64_t w = blockIdx.x; w < tasks; w += gridDim.x) {
         const int f = (int)(w / a.fb_chunks), c = (int)(w - (int64_t)f * a.fb_chunks);
         const int b = a.fail_list[f];
+        const int ob = a.perm ? a.perm[b] : b;
         const int kb = k_of(a, b);
         const PredDev p = a.preds ? a.preds[b] : a.pred;
         __syncthreads();  // previous task done with LDS
-        for (int j = tid; j < a.dp; j += 256) qrow[j] = j < a.d ? a.q[(int64_t)b * a.d + j] : 0.0f;
+        for (int j = tid; j < a.dp; j += 256) qrow[j] = j < a.d ? a.q[(int64_t)ob * a.d + j] : 0.0f;
         TopkLds<Key128> tk{keys, cnt, thr, 1, kb, Kp, CB};
         tk.init(tid, 256);
         const int64_t r0 = (int64_t)c * a.fb_rows_per_chunk;
@@ -390,6 +417,7 @@ __global__ __launch_bounds__(256) void fallback_merge_kernel(FinishArgs a) {
     int *cnt = (int *)(thr + 1);
     for (int f = blockIdx.x; f < nf; f += gridDim.x) {
         const int b = a.fail_list[f];
+        const int ob = a.perm ? a.perm[b] : b;
         const int kb = k_of(a, b);
         __syncthreads();
         TopkLds<Key128> tk{keys, cnt, thr, 1, kb, Kp, CB};
@@ -410,7 +438,7 @@ __global__ __launch_bounds__(256) void fallback_merge_kernel(FinishArgs a) {
         __syncthreads();
         int mine = 0;
         for (int i = tid; i < a.kmax; i += 256) {
-            int64_t o = (int64_t)b * a.kmax + i;
+            int64_t o = (int64_t)ob * a.kmax + i;
             Key128 k = keys[i];
             bool valid = i < kb && !(k.hi == KEY_INF && k.lo == KEY_INF);
             if (valid) {
@@ -424,7 +452,7 @@ __global__ __launch_bounds__(256) void fallback_merge_kernel(FinishArgs a) {
         }
         atomicAdd(&nvalid_s, mine);
         __syncthreads();
-        if (tid == 0 && a.n_valid) a.n_valid[b] = nvalid_s;
+        if (tid == 0 && a.n_valid) a.n_valid[ob] = nvalid_s;
     }
 }
 
@@ -433,7 +461,18 @@ __global__ __launch_bounds__(256) void fallback_merge_kernel(FinishArgs a) {
 hipError_t launch_prep_queries(const float *q, int32_t B, int32_t d, int32_t dp, float *qp,
                                double *qnorm, float *qn2, uint16_t *qhl, uint64_t *gthr,
                                int32_t *fail_count, hipStream_t s) {
-    prep_kernel<<<B, 256, 0, s>>>(q, d, dp, qp, qnorm, qn2, qhl, gthr, fail_count);
+    prep_kernel<<<B, 256, 0, s>>>(q, d, dp, qp, qnorm, qn2, qhl, gthr, fail_count, nullptr, nullptr,
+                                  nullptr, nullptr, nullptr, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_permuted(const float *q, const int32_t *perm, int32_t B, int32_t d,
+                                int32_t dp, const PredDev *pred_o, const int32_t *kc_o,
+                                const int32_t *kps_o, float *qp, double *qnorm, float *qn2,
+                                uint16_t *qhl, uint64_t *gthr, int32_t *fail_count,
+                                PredDev *pred_p, int32_t *kc_p, int32_t *kps_p, hipStream_t s) {
+    prep_kernel<<<B, 256, 0, s>>>(q, d, dp, qp, qnorm, qn2, qhl, gthr, fail_count, perm, pred_o, kc_o,
+                                  kps_o, pred_p, kc_p, kps_p);
     return hipGetLastError();
 }
 
@@ -447,40 +486,11 @@ __global__ void prep_batched_kernel(const vrs_pred *__restrict__ preds,
                                     int32_t *__restrict__ kc, int32_t *__restrict__ kps) {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
-    vrs_pred p = preds[b];
-    PredDev o;
-    o.nterms = 0;
-    bool empty = p.nterms < 0 || p.nterms > VRS_MAX_TERMS;
-    for (int t = 0; t < 4; ++t) {
-        o.col[t] = 0;
-        o.lo[t] = 0;
-        o.hi[t] = -1;
-    }
-    if (!empty) {
-        for (int t = 0; t < p.nterms; ++t) {
-            const vrs_range &r = p.term[t];
-            if (r.col < 0 || r.col >= n_attr) {
-                empty = true;
-                break;
-            }
-            int64_t lo = r.lo, hi = r.hi;
-            if (hi <= lo || hi <= (int64_t)INT32_MIN || lo > (int64_t)INT32_MAX) {
-                empty = true;
-                break;
-            }
-            o.col[t] = r.col;
-            o.lo[t] = (int32_t)(lo < (int64_t)INT32_MIN ? (int64_t)INT32_MIN : lo);
-            o.hi[t] = (int32_t)(hi - 1 > (int64_t)INT32_MAX ? (int64_t)INT32_MAX : hi - 1);
-        }
-        o.nterms = empty ? 0 : p.nterms;
-    }
-    if (empty) o.nterms = -1;
-    out[b] = o;
+    out[b] = fold_pred_dev(preds[b], n_attr);
     int k = ks[b];
     k = k < 1 ? 1 : (k > kmax ? kmax : k);
     kc[b] = k;
-    int kp = kmult > 0 ? k * kmult : (f32_rule ? max(2 * k, k + 32) : 4 * k);
-    kps[b] = min(max(kp, k), 1024);
+    kps[b] = kprime_dev(k, kmult, f32_rule);
 }
 
 hipError_t launch_prep_batched(const vrs_pred *preds, const int32_t *ks, int32_t B, int32_t kmax,
@@ -499,15 +509,16 @@ hipError_t launch_merge(const FinishArgs &a, hipStream_t s) {
     const int G = 2048;
     if (a.n_chunks <= G) {
         merge_kernel<<<dim3(1, a.B), MERGE_THREADS, lds, s>>>(a.partials, a.n_chunks, G, a.K, Kp,
-                                                             CB, a.merged, 1);
+                                                             CB, a.merged, 1, a.list_off, a.nlists);
         return hipGetLastError();
     }
     // two levels: groups of G lists, then the group results
     const int ng = (a.n_chunks + G - 1) / G;
     uint64_t *mid = a.merge_mid;
     merge_kernel<<<dim3(ng, a.B), MERGE_THREADS, lds, s>>>(a.partials, a.n_chunks, G, a.K, Kp, CB,
-                                                          mid, ng);
-    merge_kernel<<<dim3(1, a.B), MERGE_THREADS, lds, s>>>(mid, ng, ng, a.K, Kp, CB, a.merged, 1);
+                                                          mid, ng, a.list_off, a.nlists);
+    merge_kernel<<<dim3(1, a.B), MERGE_THREADS, lds, s>>>(mid, ng, ng, a.K, Kp, CB, a.merged, 1,
+                                                         nullptr, nullptr);
     return hipGetLastError();
 }
 

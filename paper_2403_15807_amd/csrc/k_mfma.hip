@@ -27,7 +27,10 @@ namespace {
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ float4 load_nt_f4(const float4 *p) {
+// Row loads: non-temporal when each row is read once (one query tile), plain
+// when the other query tiles of the same row chunk will read it again from L2.
+__device__ __forceinline__ float4 load_x(const float4 *p, int shared) {
+    if (shared) return *p;
     v4u32 v = __builtin_nontemporal_load((const v4u32 *)p);
     return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
                        __uint_as_float(v.w));
@@ -37,8 +40,11 @@ constexpr int BR = 64;  // rows per tile
 
 // MB = 16-query blocks per wave (a workgroup holds QM = 64 * MB queries); a
 // B-operand read from LDS feeds MB MFMAs.
+// One work item: queries [q0, q0 + QM) (of Bq) against row chunk `chunk` of
+// `nchunks`; its lists are (query, chunk) lists of the partials.
 template <int DP, int METRIC, bool GATHER, bool BATCHED, int E, int MB>
-__global__ __launch_bounds__(256, (E <= 8 && MB == 1) ? 3 : 2) void screen_mfma_f32_kernel(ScreenArgs a) {
+__device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, const int nchunks,
+                                         const int q0, const int Bq, unsigned char *smem) {
     constexpr int QM = 64 * MB;
     constexpr int QW = 16 * MB;            // queries per wave
     constexpr int NT4 = DP / 16;           // float4 A-fragments per lane per block
@@ -47,10 +53,7 @@ __global__ __launch_bounds__(256, (E <= 8 && MB == 1) ? 3 : 2) void screen_mfma_
     constexpr int RP = 256 / NV4;          // rows staged per pass
     constexpr int PASSES = BR / RP;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int q0 = blockIdx.y * QM;
-    const int chunk = blockIdx.x;
 
-    extern __shared__ __align__(16) unsigned char smem[];
     float *xs = (float *)smem;                                   // [BR][LDX]
     int *rid = (int *)(xs + BR * LDX);                           // [BR]
     int *rq = rid + BR;                                          // [BR] qualifies
@@ -70,26 +73,26 @@ __global__ __launch_bounds__(256, (E <= 8 && MB == 1) ? 3 : 2) void screen_mfma_
         const int mq = q0 + wave * QW + mb * 16 + (lane & 15);
 #pragma unroll
         for (int t = 0; t < NT4; ++t)
-            af[mb][t] = mq < a.B ? *(const float4 *)(a.qp + (int64_t)mq * DP + 16 * t + 4 * (lane >> 4))
+            af[mb][t] = mq < Bq ? *(const float4 *)(a.qp + (int64_t)mq * DP + 16 * t + 4 * (lane >> 4))
                                  : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    if (BATCHED && tid < QM) qpred[tid] = q0 + tid < a.B ? a.preds[q0 + tid] : PredDev{-1, {0}, {0}, {0}};
+    if (BATCHED && tid < QM) qpred[tid] = q0 + tid < Bq ? a.preds[q0 + tid] : PredDev{-1, {0}, {0}, {0}};
     // per-query state (wave-private) and list initialisation
     for (int i = lane; i < QW; i += 64) {
         const int q = wave * QW + i;
         cnt[q] = 0;
         thr[q] = KEY_INF;
         const int qa = q0 + q;
-        qn2[q] = qa < a.B ? a.qn2[qa] : 0.0f;
+        qn2[q] = qa < Bq ? a.qn2[qa] : 0.0f;
     }
     for (int i = lane; i < QW * K; i += 64) {
         const int qa = q0 + wave * QW + i / K;
-        if (qa < a.B) a.partials[((int64_t)qa * a.n_chunks + chunk) * K + (i % K)] = KEY_INF;
+        if (qa < Bq) a.partials[((int64_t)qa * nchunks + chunk) * K + (i % K)] = KEY_INF;
     }
     __syncthreads();
 
     const int64_t total = GATHER ? *a.sel_count : a.n;
-    int64_t per = (total + a.n_chunks - 1) / a.n_chunks;
+    int64_t per = (total + nchunks - 1) / nchunks;
     per = (per + BR - 1) / BR * BR;
     const int64_t c0 = (int64_t)chunk * per;
     const int64_t c1 = min(total, c0 + per);
@@ -137,7 +140,7 @@ __global__ __launch_bounds__(256, (E <= 8 && MB == 1) ? 3 : 2) void screen_mfma_
         for (int p = 0; p < PASSES; ++p) {
             const int64_t pos = t0 + p * RP + sr;
             const int64_t row = GATHER ? (int64_t)sid[p] : pos;
-            w[p] = pos < c1 ? load_nt_f4((const float4 *)(X + row * DP) + sc)
+            w[p] = pos < c1 ? load_x((const float4 *)(X + row * DP) + sc, a.shared_rows)
                             : make_float4(0.f, 0.f, 0.f, 0.f);
         }
         if (GATHER && t0 + BR < c1) issue_ids(t0 + BR);
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(256, (E <= 8 && MB == 1) ? 3 : 2) void screen_mfma_
         if ((((t0 - c0) / BR) & 15) == 15) {
             for (int i = lane; i < QW; i += 64) {
                 const int qa = q0 + wave * QW + i;
-                if (qa < a.B) {
+                if (qa < Bq) {
                     const uint64_t g = __atomic_load_n((const unsigned long long *)(a.gthr + qa), __ATOMIC_RELAXED);
                     if (g < thr[wave * QW + i]) thr[wave * QW + i] = g;
                 }
@@ -212,13 +215,13 @@ __global__ __launch_bounds__(256, (E <= 8 && MB == 1) ? 3 : 2) void screen_mfma_
                 for (int i = 0; i < 4; ++i) {
                     const int q = qb + i;
                     const int qa = q0 + q;
-                    if (qa >= a.B) continue;
+                    if (qa >= Bq) continue;
                     if (BATCHED && !pred_eval(qpred[q], a.attr, a.an, row)) continue;
                     const float dist = METRIC == VRS_L2SQ ? fmaf(-2.0f, acc[mb][nb][i], qn[i] + xn2[r]) : -acc[mb][nb][i];
                     const uint64_t key = make_key(dist, (uint32_t)row);
                     if (key < th[i]) {
                         const int slot = atomicAdd(&cnt[q], 1);
-                        a.cbuf[((int64_t)qa * a.n_chunks + chunk) * CBq + slot] = key;
+                        a.cbuf[((int64_t)qa * nchunks + chunk) * CBq + slot] = key;
                     }
                 }
             }
@@ -232,7 +235,7 @@ __global__ __launch_bounds__(256, (E <= 8 && MB == 1) ? 3 : 2) void screen_mfma_
                 const int j = __ffsll((long long)full) - 1;
                 full &= full - 1;
                 const int q = wave * QW + j, qa = q0 + q;
-                const int64_t base = (int64_t)qa * a.n_chunks + chunk;
+                const int64_t base = (int64_t)qa * nchunks + chunk;
                 flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, cnt[q], K, Kp, &thr[q],
                                a.gthr + qa);
                 if (lane == 0) cnt[q] = 0;
@@ -243,14 +246,59 @@ __global__ __launch_bounds__(256, (E <= 8 && MB == 1) ? 3 : 2) void screen_mfma_
     // ---- final flush of every pending buffer
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     const int myc = lane < QW ? cnt[wave * QW + lane] : 0;
-    uint64_t pend = __ballot(lane < QW && myc > 0 && q0 + wave * QW + lane < a.B);
+    uint64_t pend = __ballot(lane < QW && myc > 0 && q0 + wave * QW + lane < Bq);
     while (pend) {
         const int j = __ffsll((long long)pend) - 1;
         pend &= pend - 1;
         const int q = wave * QW + j, qa = q0 + q;
-        const int64_t base = (int64_t)qa * a.n_chunks + chunk;
+        const int64_t base = (int64_t)qa * nchunks + chunk;
         flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, cnt[q], K, Kp, &thr[q],
                        a.gthr + qa);
+    }
+}
+
+
+template <int DP, int METRIC, bool GATHER, bool BATCHED, int E, int MB>
+__global__ __launch_bounds__(256, (E <= 8 && MB == 1) ? 3 : 2) void screen_mfma_f32_kernel(ScreenArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    f32_tile<DP, METRIC, GATHER, BATCHED, E, MB>(a, blockIdx.x, a.n_chunks, blockIdx.y * (64 * MB), a.B,
+                                                 smem);
+}
+
+// Persistent form (batched uneven launch), queue per XCD: see the bfloat16
+// kernel's persistent form.
+template <int DP, int METRIC, int E, int MB>
+__global__ __launch_bounds__(256, (E <= 8 && MB == 1) ? 3 : 2) void screen_mfma_f32_persistent(ScreenArgs a) {
+    constexpr int QM = 64 * MB;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int item_s;
+    const int Bq = a.bctl[BC_NDENSE], nc = a.bctl[BC_NC];
+    const int ntiles = (Bq + QM - 1) / QM;
+    const int per = nc / 8 * ntiles;
+    const int x = blockIdx.x & 7;
+    int src = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int it = -1;
+            while (src < 8) {
+                const int qx = (x + src) & 7;
+                const int i = atomicAdd(&a.bctl[BC_QDENSE + qx], 1);
+                if (i < per) {
+                    it = qx * per + i;
+                    break;
+                }
+                ++src;
+            }
+            item_s = it;
+        }
+        __syncthreads();
+        const int it = item_s;
+        __syncthreads();
+        if (it < 0) break;
+        const int qx = it / per, i = it - qx * per;
+        const int chunk = qx + 8 * (i / ntiles), qt = i - (i / ntiles) * ntiles;
+        f32_tile<DP, METRIC, false, true, E, MB>(a, chunk, nc, qt * QM, Bq, smem);
+        __syncthreads();
     }
 }
 
@@ -261,15 +309,15 @@ hipError_t launch_e(const ScreenArgs &a, hipStream_t s) {
     const size_t lds = screen_mfma_lds(DP, QM);
     if (a.preds) {
         auto k = screen_mfma_f32_kernel<DP, METRIC, false, true, E, MB>;
-        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        ensure_dyn_lds((const void *)k, lds);
         k<<<grid, block, lds, s>>>(a);
     } else if (a.gather) {
         auto k = screen_mfma_f32_kernel<DP, METRIC, true, false, E, MB>;
-        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        ensure_dyn_lds((const void *)k, lds);
         k<<<grid, block, lds, s>>>(a);
     } else {
         auto k = screen_mfma_f32_kernel<DP, METRIC, false, false, E, MB>;
-        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        ensure_dyn_lds((const void *)k, lds);
         k<<<grid, block, lds, s>>>(a);
     }
     return hipGetLastError();
@@ -311,6 +359,43 @@ bool screen_mfma_supported(int dp, vrs_dtype store, int Kp, int CB) {
     const int E = (Kp + CB) / 64;
     return store == VRS_F32 && (dp == 32 || dp == 64 || dp == 128 || dp == 256) &&
            (E == 4 || E == 8 || E == 16 || E == 32) && (Kp + CB) == 64 * E;
+}
+
+template <int DP, int METRIC, int E, int MB>
+hipError_t launch_pe(const ScreenArgs &a, int grid, hipStream_t s) {
+    const size_t lds = screen_mfma_lds(DP, 64 * MB);
+    auto k = screen_mfma_f32_persistent<DP, METRIC, E, MB>;
+    ensure_dyn_lds((const void *)k, lds);
+    k<<<grid, 256, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int DP, int METRIC, int MB>
+hipError_t launch_pdp(const ScreenArgs &a, int grid, hipStream_t s) {
+    switch ((a.Kp + a.CB) / 64) {
+    case 4: return launch_pe<DP, METRIC, 4, MB>(a, grid, s);
+    case 8: return launch_pe<DP, METRIC, 8, MB>(a, grid, s);
+    case 16: return launch_pe<DP, METRIC, 16, MB>(a, grid, s);
+    default: return launch_pe<DP, METRIC, 32, MB>(a, grid, s);
+    }
+}
+
+template <int METRIC, int MB>
+hipError_t launch_pm(const ScreenArgs &a, int grid, hipStream_t s) {
+    switch (a.dp) {
+    case 32: return launch_pdp<32, METRIC, MB>(a, grid, s);
+    case 64: return launch_pdp<64, METRIC, MB>(a, grid, s);
+    case 128: return launch_pdp<128, METRIC, MB>(a, grid, s);
+    case 256: return launch_pdp<256, METRIC, MB>(a, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_screen_mfma_persistent(const ScreenArgs &a, int qm, int grid, hipStream_t s) {
+    if (!a.bctl || !a.preds) return hipErrorInvalidValue;
+    if (qm == 128)
+        return a.metric == VRS_L2SQ ? launch_pm<VRS_L2SQ, 2>(a, grid, s) : launch_pm<VRS_IP, 2>(a, grid, s);
+    return a.metric == VRS_L2SQ ? launch_pm<VRS_L2SQ, 1>(a, grid, s) : launch_pm<VRS_IP, 1>(a, grid, s);
 }
 
 hipError_t launch_screen_mfma(const ScreenArgs &a, int qm, hipStream_t s) {

@@ -9,6 +9,7 @@
 #include <cmath>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -31,7 +32,6 @@ size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 double gamma_n(double n, double u) { return n * u / (1.0 - n * u); }
 
 int screen_cb(int Kp) { return next_pow2(std::max(2 * Kp, Kp + 256)) - Kp; }
-int mfma_cb(int Kp) { return next_pow2(std::max(2 * Kp, Kp + 128)) - Kp; }
 
 // Largest tile-compatible query count per workgroup that fits the LDS budget.
 int fit_qt(int qt, int Kp, int CB, int dp) {
@@ -127,6 +127,20 @@ int default_tile(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts,
 
 }  // namespace
 
+int mfma_cb(int Kp) { return next_pow2(std::max(2 * Kp, Kp + 128)) - Kp; }
+
+void ensure_dyn_lds(const void *kernel, size_t bytes) {
+    static std::mutex mu;
+    static std::map<const void *, size_t> done;
+    std::lock_guard<std::mutex> g(mu);
+    size_t &d = done[kernel];
+    if (bytes <= d) return;
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess)
+        d = bytes;
+    else
+        (void)hipGetLastError();
+}
+
 // ------------------------------------------------------------ stage timing
 namespace {
 struct ProfRec {
@@ -135,6 +149,7 @@ struct ProfRec {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+thread_local bool g_prof_quiet = false;  // set while a launch sequence is captured
 std::vector<ProfRec> g_prof_recs;
 std::vector<hipEvent_t> g_prof_pool;
 hipEvent_t g_prof_open[VRS_NUM_STAGES];
@@ -153,18 +168,20 @@ hipEvent_t prof_event() {
 
 void prof_begin(int stage, hipStream_t s) {
     std::lock_guard<std::mutex> g(g_prof_mu);
-    if (!g_prof_on) return;
+    if (!g_prof_on || g_prof_quiet) return;
     hipEvent_t e = prof_event();
     if (e && hipEventRecord(e, s) == hipSuccess) g_prof_open[stage] = e;
 }
 
 void prof_end(int stage, hipStream_t s) {
     std::lock_guard<std::mutex> g(g_prof_mu);
-    if (!g_prof_on || !g_prof_open[stage]) return;
+    if (!g_prof_on || g_prof_quiet || !g_prof_open[stage]) return;
     hipEvent_t e = prof_event();
     if (e && hipEventRecord(e, s) == hipSuccess) g_prof_recs.push_back({stage, g_prof_open[stage], e});
     g_prof_open[stage] = nullptr;
 }
+
+void prof_quiet(bool on) { g_prof_quiet = on; }
 
 void prof_enable(bool on) {
     std::lock_guard<std::mutex> g(g_prof_mu);
@@ -330,6 +347,7 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     sa.Kp = P.Kp;
     sa.CB = P.CB;
     sa.n_chunks = P.n_chunks;
+    sa.shared_rows = P.n_qtiles > 1;
     sa.partials = (uint64_t *)(w + P.o_part);
     prof_begin(2, s);
     if (!P.mfma)

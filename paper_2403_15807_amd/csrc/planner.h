@@ -20,6 +20,8 @@ const TileCfg &planner_tile(int id);
 
 // k' = screening survivors per query.
 int kprime_rule(int k, vrs_dtype store, int kmult);
+// Candidate-buffer length of the MFMA screening kernels for a list of Kp.
+int mfma_cb(int Kp);
 
 struct Plan {
     int strategy;        // VRS_STRATEGY_MASK or VRS_STRATEGY_GATHER
@@ -49,6 +51,7 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
 void prof_begin(int stage, hipStream_t s);
 void prof_end(int stage, hipStream_t s);
 void prof_enable(bool on);
+void prof_quiet(bool on);  // this thread records no stage events (graph capture)
 hipError_t prof_collect(double *ms, int64_t *calls);
 
 // Planner decision (strategy, tile) for a call, with its raw chooser features.
@@ -63,5 +66,36 @@ bool chooser_ready();
 // Returns the arm index (strategy * num_tiles + tile) with the lowest
 // predicted time among the allowed arms, or -1.
 int chooser_pick(const float feats[6], const bool *allowed, int n_arms);
+
+// ---- batched uneven form (batched.cpp)
+// A configuration of the batched launch: queries qualifying at most
+// cap_frac * n rows go to the sparse gather kernel, the dense kernel aims at
+// `rounds` resident-workgroup rounds of work items, and sparse items hold
+// about seg_rows rows.
+struct BatchCfg {
+    double cap_frac;
+    int rounds;
+    int seg_rows;
+};
+int batched_num_cfgs();
+const BatchCfg &batched_cfg(int i);
+// The persistent dense kernel exists for this table, k_max and metric.
+bool batched_native(const vrs_table_s *t, int kmax, int metric, const vrs_opts *opts);
+// Workspace bytes covering every configuration.
+size_t batched_workspace(const vrs_table_s *t, int B, int kmax, int metric, const vrs_opts *opts);
+hipError_t run_batched(const vrs_table_s *t, const float *q, int B, const vrs_pred *preds,
+                       const int32_t *ks, int kmax, vrs_metric metric, int64_t *out_idx,
+                       float *out_dist, void *ws, const vrs_opts *opts, int cfg, hipStream_t s);
+// Configuration for a call: opts->tile if set, else the tuned one for this
+// (table, B, k_max, metric) if known, else the default.
+int batched_pick(const vrs_table_s *t, int B, int kmax, int metric, const vrs_opts *opts);
+// The tuned configuration for this shape, or -1.
+int batched_tuned(const vrs_table_s *t, int B, int kmax, int metric, const vrs_opts *opts);
+// Times every configuration on the given inputs (synchronizes), remembers
+// and returns the fastest; ms[i] = time of configuration i (or -1).
+hipError_t batched_tune(const vrs_table_s *t, const float *q, int B, const vrs_pred *preds,
+                        const int32_t *ks, int kmax, vrs_metric metric, int64_t *out_idx,
+                        float *out_dist, void *ws, const vrs_opts *opts, hipStream_t s, int *best,
+                        float *ms);
 
 }  // namespace vrs

@@ -31,6 +31,8 @@ EXPORTS = [
     "vrs_scan_topk_batched", "vrs_num_tiles", "vrs_chooser_load", "vrs_last_error",
     "vrs_profile", "vrs_stage_times", "vrs_mlp_forward", "vrs_mlp_backward", "vrs_mlp_adam",
     "vrs_chooser_set", "vrs_chooser_clear", "vrs_plan", "vrs_table_view",
+    "vrs_batched_workspace_bytes", "vrs_batched_num_configs", "vrs_batched_tune",
+    "vrs_batched_graph_create", "vrs_graph_launch", "vrs_graph_config", "vrs_graph_destroy",
 ]
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 6, 64, 16, 5648
 NUM_STAGES = 6
@@ -89,6 +91,13 @@ def lib() -> C.CDLL:
             "vrs_chooser_clear": [],
             "vrs_plan": [P, I32, P, I32, I32, P, P, P, P],
             "vrs_table_view": [P, I64, P],
+            "vrs_batched_workspace_bytes": [P, I32, I32, I32, P, P],
+            "vrs_batched_num_configs": [],
+            "vrs_batched_tune": [P, P, I32, P, P, I32, I32, P, P, P, S, P, P, P, P],
+            "vrs_batched_graph_create": [P, P, I32, P, P, I32, I32, P, P, P, S, P, P, P],
+            "vrs_graph_launch": [P, P],
+            "vrs_graph_config": [P],
+            "vrs_graph_destroy": [P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -266,27 +275,95 @@ class Table:
                                    _ptr(ws), ws.numel(), C.byref(o), _stream(stream)))
         return ScanResult(idx, dist, nv, cert)
 
+    def batched_workspace_bytes(self, B: int, k_max: int, metric: int = IP, opts: vrs_opts | None = None) -> int:
+        out = C.c_size_t()
+        _check(lib().vrs_batched_workspace_bytes(self._h, B, k_max, metric,
+                                                 None if opts is None else C.byref(opts), C.byref(out)))
+        return out.value
+
+    def _batched_args(self, q, k_max, metric, tile, kprime_mult, ws, out):
+        q = q.contiguous()
+        B = q.shape[0]
+        if out is None:
+            out = (torch.empty((B, k_max), dtype=torch.int64, device="cuda"),
+                   torch.empty((B, k_max), dtype=torch.float32, device="cuda"),
+                   torch.empty(B, dtype=torch.int32, device="cuda"),
+                   torch.empty(B, dtype=torch.uint8, device="cuda"))
+        idx, dist, nv, cert = out
+        o = self._opts(B, STRATEGY_MASK, tile, CHOOSER_HEURISTIC, kprime_mult, nv, cert)
+        if ws is None:
+            ws = torch.empty(max(self.batched_workspace_bytes(B, k_max, metric, o), 256), dtype=torch.uint8,
+                             device="cuda")
+        return q, B, o, ws, (idx, dist, nv, cert)
+
     def scan_topk_batched(self, q: torch.Tensor, preds: torch.Tensor, ks: torch.Tensor, k_max: int,
                           metric: int = IP, tile: int = -1, kprime_mult: int = 0,
                           ws: torch.Tensor | None = None, out: tuple | None = None,
                           stream=None) -> ScanResult:
-        """Per-query predicates (``preds_tensor``) and k (int32 device tensor)."""
-        q = q.contiguous()
-        B = q.shape[0]
-        if out is None:
-            idx = torch.empty((B, k_max), dtype=torch.int64, device="cuda")
-            dist = torch.empty((B, k_max), dtype=torch.float32, device="cuda")
-            nv = torch.empty(B, dtype=torch.int32, device="cuda")
-            cert = torch.empty(B, dtype=torch.uint8, device="cuda")
-        else:
-            idx, dist, nv, cert = out
-        o = self._opts(B, STRATEGY_MASK, tile, CHOOSER_HEURISTIC, kprime_mult, nv, cert)
-        if ws is None:
-            ws = self.workspace(B, k_max, o)
+        """Per-query predicates (``preds_tensor``) and k (int32 device tensor).
+        ``tile`` is a batched configuration index (-1: tuned or default)."""
+        q, B, o, ws, (idx, dist, nv, cert) = self._batched_args(q, k_max, metric, tile, kprime_mult, ws, out)
         _check(lib().vrs_scan_topk_batched(self._h, _ptr(q), B, _ptr(preds), _ptr(ks), k_max, metric,
                                            _ptr(idx), _ptr(dist), _ptr(ws), ws.numel(), C.byref(o),
                                            _stream(stream)))
         return ScanResult(idx, dist, nv, cert)
+
+    def batched_tune(self, q, preds, ks, k_max: int, metric: int = IP, kprime_mult: int = 0,
+                     ws=None, out=None, stream=None):
+        """Autotune the batched configuration on these inputs: (best, ms per
+        configuration, ScanResult of the best)."""
+        q, B, o, ws, (idx, dist, nv, cert) = self._batched_args(q, k_max, metric, -1, kprime_mult, ws, out)
+        n = batched_num_configs()
+        ms = (C.c_float * n)()
+        best = C.c_int32()
+        _check(lib().vrs_batched_tune(self._h, _ptr(q), B, _ptr(preds), _ptr(ks), k_max, metric, _ptr(idx),
+                                      _ptr(dist), _ptr(ws), ws.numel(), C.byref(o), _stream(stream),
+                                      C.byref(best), ms))
+        return best.value, list(ms), ScanResult(idx, dist, nv, cert)
+
+    def batched_graph(self, q, preds, ks, k_max: int, metric: int = IP, tile: int = -1,
+                      kprime_mult: int = 0, ws=None, out=None, stream=None) -> "BatchedGraph":
+        """Capture the batched launch for these buffers into a HIP graph."""
+        q, B, o, ws, res = self._batched_args(q, k_max, metric, tile, kprime_mult, ws, out)
+        h = C.c_void_p()
+        idx, dist, nv, cert = res
+        _check(lib().vrs_batched_graph_create(self._h, _ptr(q), B, _ptr(preds), _ptr(ks), k_max, metric,
+                                              _ptr(idx), _ptr(dist), _ptr(ws), ws.numel(), C.byref(o),
+                                              _stream(stream), C.byref(h)))
+        return BatchedGraph(h, (q, preds, ks, ws, self), ScanResult(idx, dist, nv, cert))
+
+
+class BatchedGraph:
+    """A captured batched launch; ``launch()`` replays it on a stream.  The
+    buffers it was captured with are kept alive here."""
+
+    def __init__(self, h, keep, result: ScanResult):
+        self._h = h
+        self._keep = keep
+        self.result = result
+
+    @property
+    def config(self) -> int:
+        return int(lib().vrs_graph_config(self._h))
+
+    def launch(self, stream=None):
+        _check(lib().vrs_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().vrs_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().vrs_graph_destroy(self._h)
+        except Exception:
+            pass
+
+
+def batched_num_configs() -> int:
+    return int(lib().vrs_batched_num_configs())
 
 
 def profile(enable: bool):

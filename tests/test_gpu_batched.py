@@ -1,0 +1,163 @@
+"""The batched uneven form (each query with its own predicate and k) against
+the FP64 oracle: every batched configuration (dense-only through mostly
+sparse splits), float32 / bfloat16 / FP8 tables, ragged shapes, degenerate
+predicates, HIP-graph replays checked against eager runs, and the
+autotuner."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2403_15807_amd import inputs, vrs
+
+pytestmark = pytest.mark.gpu
+
+ATTR = 10 ** 6
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _ready(oracle_lib):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return oracle_lib
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _check(res, ref, what):
+    gi, gd = res.idx.cpu().numpy(), res.dist.cpu().numpy()
+    bad = np.nonzero((gi != ref[0]).any(axis=1))[0]
+    assert bad.size == 0, f"{what}: id mismatch in queries {bad[:8]}: gpu {gi[bad[0]][:10]} oracle {ref[0][bad[0]][:10]}"
+    assert np.array_equal(gd, ref[1]), f"{what}: distances not bit-identical"
+    assert np.array_equal(res.n_valid.cpu().numpy(), ref[3]), f"{what}: n_valid"
+
+
+def _workload(cfg, n, d, B, s_min=1e-4, k_choices=(1, 10, 100)):
+    x = inputs.table(cfg, n, d, 100)
+    a = inputs.attributes(cfg, n, 2, ATTR)
+    q = inputs.queries(cfg, B, d, 100)
+    bp = inputs.batched_predicates(cfg, B, ATTR, s_min=s_min, k_choices=k_choices)
+    preds = [[(0, int(bp.lo[b, 0]), int(bp.hi[b, 0])), (1, int(bp.lo[b, 1]), int(bp.hi[b, 1]))]
+             for b in range(B)]
+    return x, a, q, preds, bp.k.copy()
+
+
+def _edge_cases(preds, ks):
+    preds[3] = []                          # every row
+    preds[4] = [(0, 10, 5)]                # empty range
+    preds[5] = [(1, 0, 3)]                 # about 3 rows (sparse, fewer than k)
+    preds[6] = [(0, 0, ATTR)]              # one term, every row
+    preds[7] = [(5, 0, 10)]                # column outside the table: no row
+    ks[5] = 100
+    ks[8] = 0                              # clamped to 1
+    ks[9] = 1000                           # clamped to k_max
+
+
+@pytest.mark.parametrize("store,metric,d", [(vrs.F32, vrs.L2SQ, 128), (vrs.F32, vrs.IP, 64),
+                                            (vrs.BF16, vrs.IP, 256), (vrs.FP8E4M3, vrs.IP, 128)])
+def test_batched_every_config_matches_oracle(store, metric, d):
+    n, B = 70_001, 203                   # ragged sub-blocks and query tiles
+    x, a, q, preds, ks = _workload(5, n, d, B)
+    _edge_cases(preds, ks)
+    kmax = 100
+    normalize = metric == vrs.IP
+    T = vrs.Table(_dev(x), _dev(a), store=store, normalize=normalize)
+    ot = O.Table.build(x, a, {vrs.F32: O.F32, vrs.BF16: O.BF16, vrs.FP8E4M3: O.FP8}[store], normalize)
+    kref = np.clip(ks, 1, kmax)
+    # a term on a column the table lacks selects no row (the library's
+    # reading for a malformed predicate seen on the device): an empty range
+    # states the same for the oracle
+    oracle_preds = [p if all(c < 2 for c, _, _ in p) else [(0, 10, 5)] for p in preds]
+    ref = O.scan_topk(ot, q, oracle_preds, kref, O.L2SQ if metric == vrs.L2SQ else O.IP, out_stride=kmax)
+    pd, kd, qd = vrs.preds_tensor(preds), _dev(ks), _dev(q)
+    for cfg in range(vrs.batched_num_configs()):
+        r = T.scan_topk_batched(qd, pd, kd, kmax, metric, tile=cfg)
+        _check(r, ref, f"store {store} metric {metric} config {cfg}")
+
+
+def test_batched_k_prime_one_forces_fallback_and_stays_exact():
+    # k' = k: many certificates fail and the exact FP64 pass decides
+    n, d, B = 40_000, 64, 70
+    x, a, q, preds, ks = _workload(6, n, d, B)
+    T = vrs.Table(_dev(x), _dev(a), normalize=True)
+    ot = O.Table.build(x, a, O.F32, True)
+    kmax = int(ks.max())
+    ref = O.scan_topk(ot, q, preds, ks, O.IP, out_stride=kmax)
+    for cfg in (0, 6):
+        r = T.scan_topk_batched(_dev(q), vrs.preds_tensor(preds), _dev(ks), kmax, vrs.IP, tile=cfg,
+                                kprime_mult=1)
+        _check(r, ref, f"k'=k config {cfg}")
+
+
+def test_batched_wide_float32_rows_use_the_masked_path():
+    # float32 rows wider than 256 have no persistent dense kernel
+    n, d, B = 20_000, 300, 19
+    x, a, q, preds, ks = _workload(7, n, d, B, k_choices=(1, 10))
+    T = vrs.Table(_dev(x), _dev(a))
+    ot = O.Table(O.F32, x, a)
+    kmax = int(ks.max())
+    ref = O.scan_topk(ot, q, preds, ks, O.L2SQ, out_stride=kmax)
+    r = T.scan_topk_batched(_dev(q), vrs.preds_tensor(preds), _dev(ks), kmax, vrs.L2SQ)
+    _check(r, ref, "wide rows")
+
+
+def test_batched_graph_replays_match_eager_runs():
+    n, d, B, kmax = 60_000, 128, 150, 100
+    x, a, _, _, _ = _workload(8, n, d, B)
+    T = vrs.Table(_dev(x), _dev(a), store=vrs.BF16, normalize=True)
+    ot = O.Table.build(x, a, O.BF16, True)
+    qd = torch.empty((B, d), dtype=torch.float32, device="cuda")
+    kd = torch.empty(B, dtype=torch.int32, device="cuda")
+    pd = torch.empty_like(vrs.preds_tensor([[]] * B))
+
+    def fill(seed):
+        q = inputs.queries(8, B, d, 100, stream_offset=seed)
+        bp = inputs.batched_predicates(100 + seed, B, ATTR)
+        preds = [[(0, int(bp.lo[b, 0]), int(bp.hi[b, 0])), (1, int(bp.lo[b, 1]), int(bp.hi[b, 1]))]
+                 for b in range(B)]
+        qd.copy_(_dev(q))
+        kd.copy_(_dev(bp.k))
+        pd.copy_(vrs.preds_tensor(preds))
+        return q, preds, bp.k
+
+    q, preds, ks = fill(0)
+    G = T.batched_graph(qd, pd, kd, kmax, vrs.IP, tile=3)
+    assert G.config == 3
+    for rep, seed in enumerate((1, 2, 3, 2)):
+        q, preds, ks = fill(seed)
+        torch.cuda.synchronize()
+        G.launch()
+        torch.cuda.synchronize()
+        got = (G.result.idx.clone(), G.result.dist.clone(), G.result.n_valid.clone())
+        # eager work between replays, then the eager result of the same inputs
+        e = T.scan_topk_batched(qd, pd, kd, kmax, vrs.IP, tile=3)
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], e.idx) and torch.equal(got[1], e.dist) and torch.equal(got[2], e.n_valid), rep
+        if rep == 0:
+            ref = O.scan_topk(ot, q, preds, ks, O.IP, out_stride=kmax)
+            _check(e, ref, "graph replay")
+    G.close()
+
+
+def test_batched_autotuner_picks_a_config_with_identical_results():
+    n, d, B, kmax = 80_000, 128, 300, 10
+    x, a, q, preds, ks = _workload(9, n, d, B, k_choices=(1, 10))
+    T = vrs.Table(_dev(x), _dev(a), store=vrs.FP8E4M3, normalize=True)
+    ot = O.Table.build(x, a, O.FP8, True)
+    pd, kd, qd = vrs.preds_tensor(preds), _dev(ks), _dev(q)
+    best, ms, r = T.batched_tune(qd, pd, kd, kmax, vrs.IP)
+    assert 0 <= best < vrs.batched_num_configs()
+    assert all(t > 0 for t in ms) and ms[best] == min(ms)
+    ref = O.scan_topk(ot, q, preds, ks, O.IP, out_stride=kmax)
+    _check(r, ref, "tuned")
+    # the tuned configuration is used by default afterwards, and by a graph
+    r2 = T.scan_topk_batched(qd, pd, kd, kmax, vrs.IP)
+    _check(r2, ref, "tuned default")
+    G = T.batched_graph(qd, pd, kd, kmax, vrs.IP)
+    assert G.config == best
+    G.launch()
+    torch.cuda.synchronize()
+    _check(G.result, ref, "tuned graph")
+    G.close()

@@ -1,0 +1,126 @@
+"""Parity at the benchmark sizes, in the launch configurations bench.py times:
+the whole batch runs on the GPU, and a sample of queries (one per host core,
+at most 16) is checked against the FP64 oracle, which scans the full table
+for each of them.  Ids must match exactly and distances bit for bit (within
+1e-5 relative is the stated bar)."""
+
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2403_15807_amd import inputs, vrs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+ATTR = 10 ** 6
+
+
+def _say(msg):
+    # long host steps (table generation, oracle scans): progress on stderr
+    print(f"[fullsize {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def _sample(B):
+    cores = len(os.sched_getaffinity(0))
+    m = min(16, max(4, cores), B)
+    return np.unique(np.linspace(0, B - 1, m).astype(int))
+
+
+def _check(res, ref, rows, what):
+    gi = res.idx.cpu().numpy()[rows]
+    gd = res.dist.cpu().numpy()[rows]
+    assert np.array_equal(res.n_valid.cpu().numpy()[rows], ref[3]), f"{what}: n_valid"
+    assert np.array_equal(gi, ref[0]), f"{what}: ids differ"
+    fin = np.isfinite(ref[1])
+    rel = np.abs(gd[fin].astype(np.float64) - ref[2][fin]) / np.maximum(np.abs(ref[2][fin]), 1e-30)
+    assert rel.max(initial=0.0) <= 1e-5, what
+    assert np.array_equal(gd, ref[1]), f"{what}: distances not bit-identical"
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    n, d = 10_000_000, 128
+    _say("generating 10M x 128")
+    x = inputs.table(1, n, d, 1000)
+    a = inputs.attributes(1, n, 2, ATTR)
+    T = vrs.Table(torch.from_numpy(x).cuda(), torch.from_numpy(a).cuda())
+    return x, a, T
+
+
+@pytest.mark.parametrize("B,sel", [(1, 1.0), (1, 0.01), (16, 0.1), (1024, 1.0), (1024, 0.1)])
+def test_10M_x_128_l2_top100(cfg1, B, sel):
+    x, a, T = cfg1
+    q = inputs.queries(1, B, 128, 1000)
+    w = inputs.two_term_width(sel, ATTR)
+    pred = [(0, 0, w), (1, 0, w)]
+    r = T.scan_topk(torch.from_numpy(q).cuda(), pred, 100, vrs.L2SQ)
+    torch.cuda.synchronize()
+    rows = _sample(B)
+    ot = O.Table(O.F32, x, a)
+    _say(f"oracle L2 B={B} sel={sel} on {len(rows)} queries")
+    ref = O.scan_topk(ot, q[rows], pred, 100, O.L2SQ)
+    _check(r, ref, rows, f"10M x 128 B={B} sel={sel}")
+
+
+@pytest.mark.parametrize("B,sel", [(1, 0.5), (1024, 0.01)])
+def test_10M_x_128_ip_normalised_top100(cfg1, B, sel):
+    x, a, _ = cfg1
+    T = vrs.Table(torch.from_numpy(x).cuda(), torch.from_numpy(a).cuda(), normalize=True)
+    q = inputs.queries(1, B, 128, 1000, stream_offset=1)
+    w = inputs.two_term_width(sel, ATTR)
+    pred = [(0, 0, w), (1, 0, w)]
+    r = T.scan_topk(torch.from_numpy(q).cuda(), pred, 100, vrs.IP)
+    torch.cuda.synchronize()
+    rows = _sample(B)
+    ot = O.Table.build(x, a, O.F32, normalize=True)
+    _say(f"oracle IP B={B} sel={sel} on {len(rows)} queries")
+    ref = O.scan_topk(ot, q[rows], pred, 100, O.IP)
+    _check(r, ref, rows, f"10M x 128 IP B={B} sel={sel}")
+
+
+@pytest.mark.parametrize("store", [vrs.BF16, vrs.FP8E4M3])
+def test_4M_x_768_precision_form(store):
+    n, d, B = 4_000_000, 768, 256
+    _say(f"generating 4M x 768 (store {store})")
+    x = inputs.table(2, n, d, 2000)
+    a = inputs.attributes(2, n, 2, ATTR)
+    q = inputs.queries(2, B, d, 2000)
+    T = vrs.Table(torch.from_numpy(x).cuda(), torch.from_numpy(a).cuda(), store=store, normalize=True)
+    _say("oracle table")
+    ot = O.Table.build(x, a, O.BF16 if store == vrs.BF16 else O.FP8, normalize=True)
+    del x
+    rows = _sample(B)
+    for sel, k in ((0.3, 100), (0.01, 10)):
+        w = inputs.two_term_width(sel, ATTR)
+        pred = [(0, 0, w), (1, 0, w)]
+        r = T.scan_topk(torch.from_numpy(q).cuda(), pred, k, vrs.IP)
+        torch.cuda.synchronize()
+        _say(f"oracle sel={sel} k={k}")
+        ref = O.scan_topk(ot, q[rows], pred, k, O.IP)
+        _check(r, ref, rows, f"4M x 768 store={store} sel={sel} k={k}")
+
+
+def test_2M_x_1536_batched_uneven():
+    n, d, B = 2_000_000, 1536, 4096
+    _say("generating 2M x 1536")
+    x = inputs.table(3, n, d, 1000)
+    a = inputs.attributes(3, n, 2, ATTR)
+    q = inputs.queries(3, B, d, 1000)
+    bp = inputs.batched_predicates(3, B, ATTR)
+    preds = [[(0, int(bp.lo[b, 0]), int(bp.hi[b, 0])), (1, int(bp.lo[b, 1]), int(bp.hi[b, 1]))]
+             for b in range(B)]
+    T = vrs.Table(torch.from_numpy(x).cuda(), torch.from_numpy(a).cuda(), store=vrs.BF16, normalize=True)
+    ot = O.Table.build(x, a, O.BF16, normalize=True)
+    del x
+    kmax = int(bp.k.max())
+    r = T.scan_topk_batched(torch.from_numpy(q).cuda(), vrs.preds_tensor(preds),
+                            torch.from_numpy(bp.k).cuda(), kmax, vrs.IP)
+    torch.cuda.synchronize()
+    rows = _sample(B)
+    _say("oracle batched")
+    ref = O.scan_topk(ot, q[rows], [preds[i] for i in rows], bp.k[rows], O.IP, out_stride=kmax)
+    _check(r, ref, rows, "2M x 1536 batched")

@@ -265,3 +265,25 @@ def test_batched_per_query_predicates_and_k():
     ref = O.scan_topk(ot, q, preds, bp.k, O.IP, out_stride=kmax)
     r = T.scan_topk_batched(_dev(q), vrs.preds_tensor(preds), _dev(bp.k), kmax, vrs.IP)
     _check(r, ref, "batched")
+
+
+@pytest.mark.parametrize("store", [vrs.BF16, vrs.FP8E4M3])
+def test_lowprec_mfma_one_coordinate_chunk_partial_query_tile(store):
+    # d = 64 is a single coordinate chunk per row, and B = 80 leaves the last
+    # 64-query tile with 16 queries (one busy wave, three idle ones): the
+    # idle waves run ahead into the next tile while the busy one is still
+    # reading the current tile's row records.
+    n, d, B = 300_000, 64, 80
+    x = inputs.table(4, n, d, 500)
+    a = inputs.attributes(4, n, 2, 10 ** 6)
+    q = inputs.queries(4, B, d, 500)
+    T = vrs.Table(_dev(x), _dev(a), store=store, normalize=True)
+    ot = O.Table.build(x, a, O.BF16 if store == vrs.BF16 else O.FP8, True)
+    for sel, k in ((0.04, 100), (1.0, 10)):
+        w = inputs.two_term_width(sel, 10 ** 6)
+        pred = [(0, 0, w), (1, 0, w)]
+        ref = O.scan_topk(ot, q, pred, k, O.IP)
+        for tile in (4, 6):
+            for strategy in (vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER):
+                r = T.scan_topk(_dev(q), pred, k, vrs.IP, tile=tile, strategy=strategy)
+                _check(r, ref, f"store {store} sel {sel} k {k} tile {tile} strategy {strategy}")
