@@ -88,7 +88,8 @@ enum { VRS_CHOOSER_LEARNED = 0, VRS_CHOOSER_HEURISTIC = 1 };
  *   tile:        kernel configuration id (vrs_num_tiles()), -1 = auto.
  *   chooser:     LEARNED (MLP, if weights are loaded) or HEURISTIC.
  *   kprime_mult: screening survivors per query k' = kprime_mult * k when > 0;
- *                0 = default (max(2k, k+32) for FP32 tables, 4k otherwise).
+ *                0 = default (max(2k, k+32) for FP32 tables, max(4k, k+32)
+ *                for bfloat16 / FP8 tables), at most 1024.
  *   n_valid:     [B] int32 out: min(k_b, |sigma_theta(R)|), or NULL.
  *   certified:   [B] uint8 out: 1 if the screened candidates provably held the
  *                exact top-k, 0 if the exact FP64 fallback pass ran; or NULL. */

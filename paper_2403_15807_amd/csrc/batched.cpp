@@ -27,7 +27,7 @@ const BatchCfg kCfgs[] = {
 };
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 constexpr int kDefaultCfg = 4;
-constexpr int QM = 64;            // queries per dense work item
+int dense_qm(const vrs_table_s *t) { return t->store == VRS_F32 ? 64 : screen_mfma_bf16_qm(); }
 constexpr int NC_CAP = 512;       // most row chunks per dense query
 constexpr int SEG_MAX = 32;       // most work items per sparse query
 constexpr int SPARSE_WG_PER_CU = 4;
@@ -43,7 +43,7 @@ struct BPlan {
     int nsub;
     int64_t dense_lists, lists;
     int fb_chunks, fb_rows_per_chunk;
-    size_t o_qp, o_qnorm, o_qn2, o_qhl, o_gthr, o_ctl, o_pred_o, o_pred_p, o_kc_o, o_kps_o, o_kc_p,
+    size_t o_qp, o_qnorm, o_qn2, o_qhl, o_gthr, o_ctl, o_pred_o, o_pred_p, o_qr, o_cands, o_sq, o_kc_o, o_kps_o, o_kc_p,
         o_kps_p, o_cand, o_subcnt, o_tot, o_perm, o_spoff, o_spcnt, o_segpre, o_listoff, o_nlists,
         o_pool, o_part, o_cbuf, o_merged, o_fail, o_failcnt, o_fb, total;
 };
@@ -56,15 +56,16 @@ BPlan make_bplan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, in
     P.K = P.kprime + 1;
     P.Kp = next_pow2(P.K);
     P.CB = mfma_cb(P.Kp);
-    P.occ = t->store == VRS_F32 ? screen_mfma_occupancy(P.Kp, P.CB, QM) : 2;
+    P.occ = t->store == VRS_F32 ? screen_mfma_occupancy(P.Kp, P.CB, 64) : 2;
     P.dense_grid = NUM_CU * P.occ;
     P.sparse_grid = NUM_CU * SPARSE_WG_PER_CU;
     P.items_target = c.rounds * P.dense_grid;
     P.rows_cap = (int64_t)floor(c.cap_frac * (double)t->n);
     P.nsub = (int)((t->n + BSUB_ROWS - 1) / BSUB_ROWS);
-    const int64_t ntiles = (B + QM - 1) / QM;
+    const int qm = dense_qm(t);
+    const int64_t ntiles = (B + qm - 1) / qm;
     P.dense_lists = std::min<int64_t>((int64_t)B * NC_CAP,
-                                      (int64_t)QM * std::max<int64_t>(P.items_target, 8 * ntiles));
+                                      (int64_t)qm * std::max<int64_t>(P.items_target, 8 * ntiles));
     P.lists = P.dense_lists + (P.rows_cap > 0 ? (int64_t)B * SEG_MAX : 0);
     const size_t fb_cap = (size_t)256 << 20;
     const int64_t want = std::max<int64_t>(1, (t->n + 65535) / 65536);
@@ -80,11 +81,14 @@ BPlan make_bplan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, in
     P.o_qp = take((size_t)B * t->dp * 4);
     P.o_qnorm = take((size_t)B * 8);
     P.o_qn2 = take((size_t)B * 4);
-    P.o_qhl = take(t->store == VRS_F32 ? 0 : (size_t)B * 2 * t->dp * 2);
+    P.o_qhl = take(t->store == VRS_F32 ? 0 : screen_mfma_bf16_qfrag_bytes(B, t->dp));
     P.o_gthr = take((size_t)B * 8);
     P.o_ctl = take(BC_WORDS * 4);
     P.o_pred_o = take((size_t)B * sizeof(PredDev));
     P.o_pred_p = take((size_t)B * sizeof(PredDev));
+    P.o_qr = take((size_t)B * sizeof(QRange));
+    P.o_cands = take((size_t)B * sizeof(QRange));
+    P.o_sq = take((size_t)B * sizeof(QRange));
     P.o_kc_o = take((size_t)B * 4);
     P.o_kps_o = take((size_t)B * 4);
     P.o_kc_p = take((size_t)B * 4);
@@ -170,9 +174,12 @@ hipError_t run_batched(const vrs_table_s *t, const float *q, int B, const vrs_pr
     ba.seg_max = SEG_MAX;
     ba.items_target = P.items_target;
     ba.nc_cap = NC_CAP;
-    ba.qm = QM;
+    ba.qm = dense_qm(t);
     ba.nsub = P.nsub;
     ba.pred_o = (PredDev *)(w + P.o_pred_o);
+    ba.qr = (QRange *)(w + P.o_qr);
+    ba.cands = (QRange *)(w + P.o_cands);
+    ba.sq = (QRange *)(w + P.o_sq);
     ba.kc_o = (int32_t *)(w + P.o_kc_o);
     ba.kps_o = (int32_t *)(w + P.o_kps_o);
     ba.cand = (uint8_t *)(w + P.o_cand);
@@ -219,6 +226,7 @@ hipError_t run_batched(const vrs_table_s *t, const float *q, int B, const vrs_pr
     sa.store = t->store;
     sa.attr = t->attr;
     sa.an = t->attr_stride;
+    sa.n_attr = t->n_attr;
     sa.preds = pred_p;
     sa.qp = qp;
     sa.qn2 = qn2;
@@ -241,7 +249,7 @@ hipError_t run_batched(const vrs_table_s *t, const float *q, int B, const vrs_pr
     sa.sp_pool = ba.pool;
     sa.kps = kps_p;
     prof_begin(2, s);
-    e = t->store == VRS_F32 ? launch_screen_mfma_persistent(sa, QM, P.dense_grid, s)
+    e = t->store == VRS_F32 ? launch_screen_mfma_persistent(sa, 64, P.dense_grid, s)
                             : launch_screen_mfma_bf16_persistent(sa, P.dense_grid, s);
     if (e != hipSuccess) return e;
     if (ba.rows_cap > 0) {

@@ -28,6 +28,12 @@ __device__ __forceinline__ float unord32(uint32_t o) {
 __device__ __forceinline__ uint64_t make_key(float d, uint32_t row) {
     return ((uint64_t)ord32(d) << 32) | row;
 }
+// Distance part of a key as a float bound: key(d, row) < th implies
+// d <= key_dist(th), so the float test can reject before the key is built.
+__device__ __forceinline__ float key_dist(uint64_t th) {
+    const uint32_t hi = (uint32_t)(th >> 32);
+    return hi == 0xffffffffu ? __int_as_float(0x7f800000) : unord32(hi);
+}
 __device__ __forceinline__ uint64_t ord64(double f) {
     f = (f == 0.0) ? 0.0 : f;
     uint64_t u = (uint64_t)__double_as_longlong(f);

@@ -82,6 +82,7 @@ struct ScreenArgs {
     vrs_dtype store;
     const int32_t *attr;
     int64_t an;                    // attribute column stride
+    int32_t n_attr;
     PredDev pred;                  // shared predicate (batch form: preds != null)
     const PredDev *preds;          // [B] per-query predicates or null
     const int32_t *sel_ids;        // gather: qualifying rows
@@ -117,7 +118,21 @@ enum BatchCtl {
     BC_NC = 2,       // row chunks (lists) per dense query
     BC_QDENSE = 3,   // 8 work-queue counters of the dense kernel, one per XCD
     BC_QSPARSE = 11, // work-queue counter of the sparse kernel
+    BC_NCAND = 12,   // sparse candidates (entries of BatchArgs::cands)
     BC_WORDS = 16
+};
+
+// A query's predicate as unsigned range tests on the first two attribute
+// columns (the batched predicate passes keep those columns in registers):
+// row i qualifies iff (uint32)(A[0][i] - lo0) <= span0 and likewise for
+// column 1.  kind 1 = a term on another column (evaluated from the folded
+// predicate), kind 2 = selects no row.
+struct QRange {
+    int32_t b;
+    int32_t kind;
+    int32_t lo0, lo1;
+    uint32_t span0, span1;
+    int64_t off;                   // write pass: first slot of the query's selection vector
 };
 hipError_t launch_screen_stream(const ScreenArgs &a, int qt, hipStream_t s);
 size_t screen_stream_lds(int qt, int Kp, int CB, int dp);
@@ -125,6 +140,8 @@ hipError_t launch_screen_mfma(const ScreenArgs &a, int qm, hipStream_t s);
 size_t screen_mfma_lds(int dp, int qm);
 hipError_t launch_screen_mfma_bf16(const ScreenArgs &a, hipStream_t s);
 size_t screen_mfma_bf16_lds();
+int screen_mfma_bf16_qm();                              // queries per workgroup
+size_t screen_mfma_bf16_qfrag_bytes(int B, int dp);     // fragment-ordered query copy
 bool screen_mfma_bf16_supported(int dp, vrs_dtype store, int metric, int Kp, int CB);
 bool screen_mfma_supported(int dp, vrs_dtype store, int Kp, int CB);
 // persistent forms for the batched uneven launch (queue-driven, one grid)
@@ -162,14 +179,41 @@ __device__ inline PredDev fold_pred_dev(const vrs_pred &p, int n_attr) {
     return o;
 }
 
+// Range form of a folded predicate (see QRange).
+__device__ inline QRange range_form(int b, const PredDev &o) {
+    QRange r;
+    r.b = b;
+    r.kind = 0;
+    r.off = 0;
+    int32_t lo[2] = {INT32_MIN, INT32_MIN}, hi[2] = {INT32_MAX, INT32_MAX};
+    bool none = o.nterms < 0;
+    for (int t = 0; t < 4; ++t) {
+        if (t >= o.nterms) break;
+        const int c = o.col[t];
+        if (c > 1) {
+            r.kind = 1;
+        } else {
+            lo[c] = max(lo[c], o.lo[t]);
+            hi[c] = min(hi[c], o.hi[t]);
+        }
+    }
+    if (lo[0] > hi[0] || lo[1] > hi[1]) none = true;
+    r.lo0 = lo[0];
+    r.lo1 = lo[1];
+    r.span0 = (uint32_t)hi[0] - (uint32_t)lo[0];
+    r.span1 = (uint32_t)hi[1] - (uint32_t)lo[1];
+    if (none) r.kind = 2;
+    return r;
+}
+
 // k' of one query (the host rule of the planner).
 __device__ inline int kprime_dev(int k, int kmult, int f32_rule) {
-    int kp = kmult > 0 ? k * kmult : (f32_rule ? max(2 * k, k + 32) : 4 * k);
+    int kp = kmult > 0 ? k * kmult : (f32_rule ? max(2 * k, k + 32) : max(4 * k, k + 32));
     return min(max(kp, k), 1024);
 }
 
 // ---- batched uneven form (k_batched.hip)
-constexpr int BSUB_ROWS = 2048;    // rows per wave in the batched predicate passes
+constexpr int BSUB_ROWS = 1024;    // rows per wave in the batched predicate passes
 struct BatchArgs {
     const vrs_pred *preds;         // [B] caller's predicates
     const int32_t *ks;             // [B] caller's k
@@ -183,8 +227,11 @@ struct BatchArgs {
     int32_t items_target;          // dense work items wanted (sets the row chunks per query)
     int32_t nc_cap;                // most row chunks per dense query
     int32_t qm;                    // queries per dense work item
-    int32_t nsub;                  // 2048-row sub-blocks
+    int32_t nsub;                  // 1024-row sub-blocks
     PredDev *pred_o;               // [B] folded predicates, by query
+    QRange *qr;                    // [B] range form, by query
+    QRange *cands;                 // [B] range form of the sparse candidates (any order)
+    QRange *sq;                    // [B] range form of the sparse queries, by sparse index
     int32_t *kc_o, *kps_o;         // [B] clamped k and k', by query
     uint8_t *cand;                 // [B] sparse candidate by the estimate
     uint32_t *subcnt;              // [nsub][B] qualifying rows per sub-block, then prefix

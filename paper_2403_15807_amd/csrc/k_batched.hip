@@ -17,11 +17,12 @@
 // exceeds the cap goes dense), and the queries are permuted so that the
 // dense ones occupy positions [0, n_dense).
 //
-// Passes over the attribute columns are organised by 2048-row sub-blocks,
-// one wave each: the wave keeps its rows' values of the first two columns
-// in registers and walks the queries, so the columns are read once per
-// pass however many queries there are; qualifying rows are found 64 at a
-// time with one ballot per row group.
+// Passes over the attribute columns are organised by 1024-row sub-blocks;
+// the queries of a sub-block are split over 8 waves, each of which keeps
+// its rows' values of the first two columns in registers and walks its
+// share of the queries, so the columns are read a few times per pass
+// however many queries there are; qualifying rows are found 64 at a time
+// with one ballot per row group.
 #include "internal.h"
 
 namespace vrs {
@@ -29,6 +30,7 @@ namespace vrs {
 namespace {
 
 constexpr int GROUPS = BSUB_ROWS / 64;  // 64-row groups per sub-block
+constexpr int QSPLIT = 8;               // waves sharing one sub-block's queries
 
 __device__ __forceinline__ bool eval_cached(const PredDev &p, int32_t v0, int32_t v1,
                                             const int32_t *__restrict__ attr, int64_t an,
@@ -70,11 +72,13 @@ __device__ double est_fraction(const void *dstats, int n_attr, const PredDev &p)
     return sel;
 }
 
-// Fold predicates and k, propose sparse candidates, reset the control words.
+__global__ void batch_reset_kernel(int32_t *ctl) {
+    if (threadIdx.x < BC_WORDS) ctl[threadIdx.x] = 0;
+}
+
+// Fold predicates and k, propose sparse candidates (appended to `cands`).
 __global__ __launch_bounds__(256) void batch_prepare_kernel(BatchArgs a) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b == 0)
-        for (int i = 0; i < BC_WORDS; ++i) a.ctl[i] = 0;
     if (b >= a.B) return;
     const PredDev o = fold_pred_dev(a.preds[b], a.n_attr);
     a.pred_o[b] = o;
@@ -82,6 +86,8 @@ __global__ __launch_bounds__(256) void batch_prepare_kernel(BatchArgs a) {
     k = k < 1 ? 1 : (k > a.kmax ? a.kmax : k);
     a.kc_o[b] = k;
     a.kps_o[b] = kprime_dev(k, a.kmult, a.f32_rule);
+    const QRange r = range_form(b, o);
+    a.qr[b] = r;
     bool cand = false;
     if (a.rows_cap > 0) {
         if (o.nterms < 0)
@@ -91,43 +97,85 @@ __global__ __launch_bounds__(256) void batch_prepare_kernel(BatchArgs a) {
     }
     a.cand[b] = cand;
     a.tot[b] = -1;
+    if (cand) a.cands[atomicAdd(&a.ctl[BC_NCAND], 1)] = r;
 }
 
 // Load the first two attribute columns of a wave's sub-block (lane l holds
-// rows row0 + 64 g + l).
+// rows row0 + 64 g + l); rows past the table read the last row (their
+// results are masked out by the caller).
 __device__ __forceinline__ void load_sub(const BatchArgs &a, int64_t row0, int lane,
                                          int32_t (&v0)[GROUPS], int32_t (&v1)[GROUPS]) {
+    const int32_t *c0 = a.attr;
+    const int32_t *c1 = a.attr + (a.n_attr > 1 ? a.an : 0);
 #pragma unroll
     for (int g = 0; g < GROUPS; ++g) {
-        const int64_t row = row0 + g * 64 + lane;
-        const bool in = row < a.n;
-        v0[g] = (in && a.n_attr > 0) ? a.attr[row] : 0;
-        v1[g] = (in && a.n_attr > 1) ? a.attr[a.an + row] : 0;
+        const int64_t row = min(row0 + g * 64 + lane, a.n - 1);
+        v0[g] = c0[row];
+        v1[g] = c1[row];
     }
 }
 
-// Qualifying rows of every sparse candidate in every sub-block.
-__global__ __launch_bounds__(256) void batch_count_kernel(BatchArgs a) {
+// Lane mask of the qualifying rows of 64-row group g; `valid` is the mask
+// of rows inside the table.
+__device__ __forceinline__ uint64_t range_mask(const QRange &r, int32_t v0, int32_t v1) {
+    const bool q0 = (uint32_t)(v0 - r.lo0) <= r.span0;
+    const bool q1 = (uint32_t)(v1 - r.lo1) <= r.span1;
+    return __ballot(q0 & q1);
+}
+
+__device__ __forceinline__ uint64_t general_mask(const BatchArgs &a, const QRange &r, int32_t v0,
+                                              int32_t v1, int64_t row) {
+    return __ballot(eval_cached(a.pred_o[r.b], v0, v1, a.attr, a.an, min(row, a.n - 1)));
+}
+
+// Qualifying rows of query r in 64-row group g (lane mask); FULL: the
+// whole sub-block lies inside the table.
+template <bool FULL>
+__device__ __forceinline__ uint64_t group_mask(const BatchArgs &a, const QRange &r, int32_t v0,
+                                               int32_t v1, int64_t row0, int g, int lane) {
+    uint64_t m = r.kind == 0 ? range_mask(r, v0, v1)
+                             : general_mask(a, r, v0, v1, row0 + g * 64 + lane);
+    if (!FULL) {
+        const int64_t in = a.n - row0 - g * 64;
+        if (in < 64) m &= in <= 0 ? 0ull : ((1ull << in) - 1ull);
+    }
+    return m;
+}
+
+template <bool FULL>
+__device__ __forceinline__ void count_sub(const BatchArgs &a, int sub, int part, int lane, int64_t row0,
+                                          const int32_t (&v0)[GROUPS], const int32_t (&v1)[GROUPS]) {
+    const int nc = a.ctl[BC_NCAND];
+    const int j0 = (int)((int64_t)nc * part / QSPLIT), j1 = (int)((int64_t)nc * (part + 1) / QSPLIT);
+    if (j0 >= j1) return;
+    QRange rn = a.cands[j0];
+    for (int j = j0; j < j1; ++j) {
+        const QRange r = rn;
+        if (j + 1 < j1) rn = a.cands[j + 1];  // in flight while this query is counted
+        uint32_t c = 0;
+        if (r.kind != 2) {
+#pragma unroll
+            for (int g = 0; g < GROUPS; ++g)
+                c += (uint32_t)__popcll(group_mask<FULL>(a, r, v0[g], v1[g], row0, g, lane));
+        }
+        if (lane == 0) a.subcnt[(int64_t)sub * a.B + r.b] = c;
+    }
+}
+
+// Qualifying rows of every sparse candidate in every sub-block: wave
+// (sub-block, part) counts part `part` of the candidate list.
+__global__ __launch_bounds__(256, 3) void batch_count_kernel(BatchArgs a) {
     const int lane = threadIdx.x & 63;
-    const int sub = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (sub >= a.nsub) return;
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int sub = w / QSPLIT, part = w % QSPLIT;
+    if (sub >= a.nsub || a.n_attr == 0 || a.ctl[BC_NCAND] == 0) return;
     const int64_t row0 = (int64_t)sub * BSUB_ROWS;
     int32_t v0[GROUPS], v1[GROUPS];
     load_sub(a, row0, lane, v0, v1);
-    for (int b = 0; b < a.B; ++b) {
-        if (!a.cand[b]) continue;
-        const PredDev p = a.pred_o[b];
-        uint32_t c = 0;
-        if (p.nterms >= 0) {
-#pragma unroll
-            for (int g = 0; g < GROUPS; ++g) {
-                const int64_t row = row0 + g * 64 + lane;
-                const bool q = row < a.n && eval_cached(p, v0[g], v1[g], a.attr, a.an, row);
-                c += (uint32_t)__popcll(__ballot(q));
-            }
-        }
-        if (lane == 0) a.subcnt[(int64_t)sub * a.B + b] = c;
-    }
+    if (row0 + BSUB_ROWS <= a.n)
+        count_sub<true>(a, sub, part, lane, row0, v0, v1);
+    else
+        count_sub<false>(a, sub, part, lane, row0, v0, v1);
 }
 
 // Per candidate: total count, and the sub-block counts turned into
@@ -213,6 +261,9 @@ __global__ __launch_bounds__(1024) void batch_order_kernel(BatchArgs a) {
                 const int j = run_s + rs, pos = nd + j;
                 a.perm[pos] = b;
                 a.sp_off[pos] = run_off + roff;
+                QRange r = a.qr[b];
+                r.off = run_off + roff;
+                a.sq[j] = r;
                 a.sp_cnt[pos] = cnt;
                 a.seg_pre[j] = run_seg + rseg;
                 a.list_off[pos] = (int64_t)nd * nc + run_seg + rseg;
@@ -232,30 +283,47 @@ __global__ __launch_bounds__(1024) void batch_order_kernel(BatchArgs a) {
     }
 }
 
-// Selection vectors of the sparse queries: ascending row ids per query.
-__global__ __launch_bounds__(256) void batch_write_kernel(BatchArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int sub = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (sub >= a.nsub) return;
-    const int nd = a.ctl[BC_NDENSE];
-    const int64_t row0 = (int64_t)sub * BSUB_ROWS;
-    int32_t v0[GROUPS], v1[GROUPS];
-    load_sub(a, row0, lane, v0, v1);
+template <bool FULL>
+__device__ __forceinline__ void write_sub(const BatchArgs &a, int sub, int part, int lane, int64_t row0,
+                                          const int32_t (&v0)[GROUPS], const int32_t (&v1)[GROUPS]) {
     const uint64_t below = (1ull << lane) - 1ull;
-    for (int pos = nd; pos < a.B; ++pos) {
-        if (a.sp_cnt[pos] == 0) continue;
-        const int b = a.perm[pos];
-        const PredDev p = a.pred_o[b];
-        int32_t *dst = a.pool + a.sp_off[pos] + a.subcnt[(int64_t)sub * a.B + b];
+    const int ns = a.ctl[BC_NSPARSE];
+    const int j0 = (int)((int64_t)ns * part / QSPLIT), j1 = (int)((int64_t)ns * (part + 1) / QSPLIT);
+    if (j0 >= j1) return;
+    QRange rn = a.sq[j0];
+    uint32_t pn = a.subcnt[(int64_t)sub * a.B + rn.b];
+    for (int j = j0; j < j1; ++j) {
+        const QRange r = rn;
+        const uint32_t pre = pn;
+        if (j + 1 < j1) {  // next query's range and slot, in flight meanwhile
+            rn = a.sq[j + 1];
+            pn = a.subcnt[(int64_t)sub * a.B + rn.b];
+        }
+        if (r.kind == 2) continue;
+        int32_t *dst = a.pool + r.off + pre;
 #pragma unroll
         for (int g = 0; g < GROUPS; ++g) {
-            const int64_t row = row0 + g * 64 + lane;
-            const bool q = row < a.n && eval_cached(p, v0[g], v1[g], a.attr, a.an, row);
-            const uint64_t m = __ballot(q);
-            if (q) dst[__popcll(m & below)] = (int32_t)row;
+            const uint64_t m = group_mask<FULL>(a, r, v0[g], v1[g], row0, g, lane);
+            if ((m >> lane) & 1ull) dst[__popcll(m & below)] = (int32_t)(row0 + g * 64 + lane);
             dst += __popcll(m);
         }
     }
+}
+
+// Selection vectors of the sparse queries: ascending row ids per query;
+// wave (sub-block, part) writes part `part` of the sparse queries.
+__global__ __launch_bounds__(256, 3) void batch_write_kernel(BatchArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int sub = w / QSPLIT, part = w % QSPLIT;
+    if (sub >= a.nsub || a.n_attr == 0 || a.ctl[BC_NSPARSE] == 0) return;
+    const int64_t row0 = (int64_t)sub * BSUB_ROWS;
+    int32_t v0[GROUPS], v1[GROUPS];
+    load_sub(a, row0, lane, v0, v1);
+    if (row0 + BSUB_ROWS <= a.n)
+        write_sub<true>(a, sub, part, lane, row0, v0, v1);
+    else
+        write_sub<false>(a, sub, part, lane, row0, v0, v1);
 }
 
 // ------------------------------------------------- sparse gather screening
@@ -397,9 +465,10 @@ __global__ __launch_bounds__(256) void screen_sparse_kernel(ScreenArgs a) {
 }  // namespace
 
 hipError_t launch_batch_classify(const BatchArgs &b, hipStream_t s) {
+    batch_reset_kernel<<<1, 64, 0, s>>>(b.ctl);
     batch_prepare_kernel<<<(b.B + 255) / 256, 256, 0, s>>>(b);
     if (b.rows_cap > 0) {
-        batch_count_kernel<<<(b.nsub + 3) / 4, 256, 0, s>>>(b);
+        batch_count_kernel<<<(b.nsub * QSPLIT + 3) / 4, 256, 0, s>>>(b);
         batch_total_kernel<<<(b.B + 255) / 256, 256, 0, s>>>(b);
     }
     batch_order_kernel<<<1, 1024, 0, s>>>(b);
@@ -407,7 +476,7 @@ hipError_t launch_batch_classify(const BatchArgs &b, hipStream_t s) {
 }
 
 hipError_t launch_batch_lists(const BatchArgs &b, hipStream_t s) {
-    if (b.rows_cap > 0) batch_write_kernel<<<(b.nsub + 3) / 4, 256, 0, s>>>(b);
+    if (b.rows_cap > 0) batch_write_kernel<<<(b.nsub * QSPLIT + 3) / 4, 256, 0, s>>>(b);
     return hipGetLastError();
 }
 

@@ -52,8 +52,13 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, 
             const float rest = v - __uint_as_float(hi << 16);  // exact
             const uint32_t r = __float_as_uint(rest);
             const uint32_t lo = (r + 0x7fffu + ((r >> 16) & 1u)) >> 16;
-            qhl[((int64_t)b * 2) * dp + j] = (uint16_t)hi;
-            qhl[((int64_t)b * 2 + 1) * dp + j] = (uint16_t)lo;
+            // in the A-operand order of v_mfma_f32_16x16x32_bf16: 16-byte unit
+            // ((b/16 * dp/32 + j/32) * 2 + part) * 64 + lane, lane = b%16 +
+            // 16 ((j%32)/8), element j%8
+            const int64_t unit = ((int64_t)(b >> 4) * (dp >> 5) + (j >> 5)) * 2;
+            const int ln = (b & 15) + 16 * ((j & 31) >> 3);
+            qhl[(unit * 64 + ln) * 8 + (j & 7)] = (uint16_t)hi;
+            qhl[((unit + 1) * 64 + ln) * 8 + (j & 7)] = (uint16_t)lo;
         }
     }
     red[threadIdx.x] = acc;

@@ -200,10 +200,11 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
         for (int mb = 0; mb < MB; ++mb) {
             const int qb = wave * QW + mb * 16 + 4 * (lane >> 4);
             uint64_t th[4];
-            float qn[4];
+            float qn[4], thf[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 th[i] = thr[qb + i];
+                thf[i] = key_dist(th[i]);
                 qn[i] = qn2[qb + i];
             }
 #pragma unroll
@@ -218,6 +219,7 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
                     if (qa >= Bq) continue;
                     if (BATCHED && !pred_eval(qpred[q], a.attr, a.an, row)) continue;
                     const float dist = METRIC == VRS_L2SQ ? fmaf(-2.0f, acc[mb][nb][i], qn[i] + xn2[r]) : -acc[mb][nb][i];
+                    if (!(dist <= thf[i])) continue;
                     const uint64_t key = make_key(dist, (uint32_t)row);
                     if (key < th[i]) {
                         const int slot = atomicAdd(&cnt[q], 1);

@@ -10,11 +10,15 @@
 // The screening distance therefore differs from the exact one by less than
 // (gamma_dp + 2^-16 + ...) |q| max|x|, which the rerank's certificate uses.
 //
-// Workgroup = 4 waves = 64 queries (16 per wave) x one chunk of rows, rows
-// in tiles of 128, coordinates in chunks of 64: the row chunk and the
-// queries' hi/lo chunk are staged through LDS, and the loads of the next
-// chunk (or of the next tile's first chunk) are in flight while the current
-// one is multiplied.  Top-k state is wave-private as in the float32 kernel.
+// Workgroup = 4 waves x 32 queries (two 16-query MFMA blocks per wave) = 128
+// queries against one chunk of rows, rows in tiles of 128, coordinates in
+// chunks of 64.  Only the rows go through LDS (double-buffered: the next
+// chunk's loads are in flight while the current one is multiplied, one
+// barrier per chunk); the query parts are read straight into registers
+// from a fragment-ordered copy made by the query preparation (one 1 KB
+// load per wave and operand), one k-step ahead.  Every 16-row B fragment
+// read from LDS feeds four MFMAs (two query blocks x hi/lo).  Top-k state is
+// wave-private as in the float32 kernel.
 #include "internal.h"
 #include "wave_topk.h"
 
@@ -26,10 +30,13 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
 
-constexpr int QM = 64;    // queries per workgroup
-constexpr int BR = 128;   // rows per tile
-constexpr int KC = 64;    // coordinates per chunk
-constexpr int LDK = 72;   // LDS row stride in bfloat16 elements (144 bytes)
+constexpr int QW = 32;          // queries per wave
+constexpr int QM = 4 * QW;      // queries per workgroup
+constexpr int BR = 128;         // rows per tile
+constexpr int NB = BR / 16;     // 16-row MFMA blocks per tile
+constexpr int KC = 64;          // coordinates per chunk (two k-steps of 32)
+constexpr int LDK = 72;         // LDS row stride in bfloat16 elements (144 bytes)
+constexpr int SLOTS = 3;        // rotating row-record slots
 
 // Row loads: non-temporal when each row is read once (one query tile), plain
 // when the other query tiles of the same row chunk will read it again from L2.
@@ -47,6 +54,36 @@ __device__ __forceinline__ uint2 e4m3x4_to_bf16x4(uint32_t w) {
     return make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
 }
 
+__device__ __forceinline__ bf8v as_bf8(const uint4 &u) {
+    bf8v v;
+    __builtin_memcpy(&v, &u, 16);
+    return v;
+}
+
+struct Lds {
+    uint16_t *xs;      // [2][BR][LDK]
+    int *rid;          // [SLOTS][BR]
+    int *rok;          // [SLOTS][BR] row exists (and, shared predicate, qualifies)
+    float *rsc;        // [SLOTS][BR] FP8 row scale
+    uint32_t *pm;      // [SLOTS][BR][QM/32] per-query predicates: query q qualifies row r
+    int *cnt;          // [QM]
+    uint64_t *thr;     // [QM]
+    QRange *qrg;       // [QM] per-query predicates (range form)
+};
+
+__device__ __forceinline__ Lds carve(unsigned char *smem) {
+    Lds L;
+    L.xs = (uint16_t *)smem;
+    L.rid = (int *)(L.xs + 2 * BR * LDK);
+    L.rok = L.rid + SLOTS * BR;
+    L.rsc = (float *)(L.rok + SLOTS * BR);
+    L.pm = (uint32_t *)(L.rsc + SLOTS * BR);
+    L.cnt = (int *)(L.pm + SLOTS * BR * (QM / 32));
+    L.thr = (uint64_t *)(L.cnt + QM);
+    L.qrg = (QRange *)(L.thr + QM);
+    return L;
+}
+
 // One work item: queries [q0, q0 + QM) (of Bq) against row chunk `chunk` of
 // `nchunks`; its lists are (query, chunk) lists of the partials.
 template <int STORE, bool GATHER, bool BATCHED, int E>
@@ -55,29 +92,21 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
     constexpr int XLD = STORE == VRS_BF16 ? 4 : 2;  // 16-byte row loads per thread per chunk
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int dp = a.dp;
-    const int nkc = dp / KC;
-
-    uint16_t *xs = (uint16_t *)smem;                      // [BR][LDK]
-    uint16_t *qs = xs + BR * LDK;                         // [QM][2][LDK]
-    // Per-row records in three rotating slots: tile t+1's record is written
-    // before tile t's first barrier, while waves that are still in the
-    // epilogue of tile t-1 read theirs (with one coordinate chunk per row
-    // there is no other barrier in between).
-    int *rid = (int *)(qs + QM * 2 * LDK);                // [3][BR]
-    int *rq = rid + 3 * BR;                               // [3][BR]
-    float *rsc = (float *)(rq + 3 * BR);                  // [3][BR]
-    int *cnt = (int *)(rsc + 3 * BR);                     // [QM]
-    uint64_t *thr = (uint64_t *)(((uintptr_t)(cnt + QM) + 7) & ~(uintptr_t)7);  // [QM]
-    PredDev *qpred = (PredDev *)(thr + QM);               // [QM]
+    const int nkc = dp / KC, nks = dp / 32;
+    const Lds L = carve(smem);
 
     const int K = a.K, Kp = a.Kp, CBq = a.CB;
     if (tid < QM) {
-        cnt[tid] = 0;
-        thr[tid] = KEY_INF;
-        if (BATCHED) qpred[tid] = q0 + tid < Bq ? a.preds[q0 + tid] : PredDev{-1, {0}, {0}, {0}};
+        L.cnt[tid] = 0;
+        L.thr[tid] = KEY_INF;
+        if (BATCHED) {
+            PredDev p{-1, {0}, {0}, {0}};
+            if (q0 + tid < Bq) p = a.preds[q0 + tid];
+            L.qrg[tid] = range_form(q0 + tid, p);
+        }
     }
-    for (int i = lane; i < 16 * K; i += 64) {
-        const int qa = q0 + wave * 16 + i / K;
+    for (int i = lane; i < QW * K; i += 64) {
+        const int qa = q0 + wave * QW + i / K;
         if (qa < Bq) a.partials[((int64_t)qa * nchunks + chunk) * K + (i % K)] = KEY_INF;
     }
 
@@ -86,158 +115,210 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
     per = (per + BR - 1) / BR * BR;
     const int64_t c0 = (int64_t)chunk * per;
     const int64_t c1 = min(total, c0 + per);
+    const int ntile = c1 > c0 ? (int)((c1 - c0 + BR - 1) / BR) : 0;
     const int EB = STORE == VRS_BF16 ? 2 : 1;
     const char *X = (const char *)a.rows;
     const int64_t row_bytes = (int64_t)dp * EB;
 
-    // per-row record of a tile, produced by thread r < BR
-    auto rowinfo = [&](int64_t t0, int slot) {
+    // query fragments of this wave: blocks qb0, qb0 + 1 (16 queries each)
+    const int qb0 = (q0 + wave * QW) >> 4;
+    const int nqb = (a.B + 15) >> 4;
+    const uint4 *QF = (const uint4 *)a.qhl;
+    auto loadA = [&](int ks, uint4 (&A)[2][2]) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int hl = 0; hl < 2; ++hl)
+                A[b][hl] = qb0 + b < nqb ? QF[((int64_t)((qb0 + b) * nks + ks) * 2 + hl) * 64 + lane]
+                                         : make_uint4(0, 0, 0, 0);
+    };
+
+    // per-row record of tile t: thread r < BR writes row r's id, validity
+    // and scale; with per-query predicates every thread also evaluates half
+    // of the workgroup's queries on row tid % BR (one bit per pair)
+    auto rowinfo = [&](int t) {
+        const int slot = t % SLOTS;
+        const int r = tid & (BR - 1);
+        const int64_t pos = c0 + (int64_t)t * BR + r;
+        bool ok = pos < c1;
+        const int64_t row = ok ? (GATHER ? (int64_t)a.sel_ids[pos] : pos) : 0;
         if (tid < BR) {
-            const int64_t pos = t0 + tid;
-            bool ok = pos < c1;
-            int64_t row = ok ? (GATHER ? (int64_t)a.sel_ids[pos] : pos) : 0;
-            if (ok && !GATHER && !BATCHED) ok = pred_eval(a.pred, a.attr, a.an, row);
-            rid[slot * BR + tid] = (int)row;
-            rq[slot * BR + tid] = ok;
-            rsc[slot * BR + tid] = (STORE == VRS_FP8E4M3 && ok) ? a.scale[row] : 1.0f;
+            bool okp = ok;
+            if (okp && !GATHER && !BATCHED) okp = pred_eval(a.pred, a.attr, a.an, row);
+            L.rid[slot * BR + r] = (int)row;
+            L.rok[slot * BR + r] = okp;
+            L.rsc[slot * BR + r] = (STORE == VRS_FP8E4M3 && okp) ? a.scale[row] : 1.0f;
+        }
+        if (BATCHED) {
+            const int h = tid / BR;  // queries [64 h, 64 h + 64)
+            const int32_t v0 = (ok && a.n_attr > 0) ? a.attr[row] : 0;
+            const int32_t v1 = (ok && a.n_attr > 1) ? a.attr[a.an + row] : 0;
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+                uint32_t bits = 0;
+                for (int j = 0; j < 32; ++j) {
+                    const int q = h * 64 + w * 32 + j;
+                    const QRange &g = L.qrg[q];
+                    bool in;
+                    if (g.kind == 0)
+                        in = ((uint32_t)(v0 - g.lo0) <= g.span0) & ((uint32_t)(v1 - g.lo1) <= g.span1);
+                    else if (g.kind == 1)
+                        in = ok && pred_eval(a.preds[q0 + q], a.attr, a.an, row);
+                    else
+                        in = false;
+                    bits |= (uint32_t)in << j;
+                }
+                L.pm[(slot * BR + r) * (QM / 32) + h * 2 + w] = ok ? bits : 0u;
+            }
         }
     };
-    uint4 xr[XLD], qr[4];
-    auto issue = [&](int slot, int kc) {
+    uint4 xr[XLD];
+    auto issue = [&](int c) {  // global loads of chunk c (tile c / nkc) into registers
+        const int t = c / nkc, kc = c - t * nkc, slot = t % SLOTS;
 #pragma unroll
         for (int i = 0; i < XLD; ++i) {
             const int idx = tid + 256 * i;
             const int r = STORE == VRS_BF16 ? idx >> 3 : idx >> 2;
-            const int c = STORE == VRS_BF16 ? idx & 7 : idx & 3;
-            xr[i] = rq[slot * BR + r]
-                        ? load_x(X + (int64_t)rid[slot * BR + r] * row_bytes + kc * KC * EB + c * 16, a.shared_rows)
+            const int cc = STORE == VRS_BF16 ? idx & 7 : idx & 3;
+            xr[i] = L.rok[slot * BR + r]
+                        ? load_x(X + (int64_t)L.rid[slot * BR + r] * row_bytes + kc * KC * EB + cc * 16,
+                                 a.shared_rows)
                         : make_uint4(0, 0, 0, 0);
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int idx = tid + 256 * i;
-            const int q = idx >> 4, hl = (idx >> 3) & 1, c = idx & 7;
-            qr[i] = q0 + q < Bq ? *(const uint4 *)(a.qhl + ((int64_t)(q0 + q) * 2 + hl) * dp + kc * KC + c * 8)
-                                 : make_uint4(0, 0, 0, 0);
-        }
     };
-    auto commit = [&]() {
+    auto commit = [&](int buf) {
+        uint16_t *xb = L.xs + buf * BR * LDK;
 #pragma unroll
         for (int i = 0; i < XLD; ++i) {
             const int idx = tid + 256 * i;
             if (STORE == VRS_BF16) {
-                *(uint4 *)(xs + (idx >> 3) * LDK + (idx & 7) * 8) = xr[i];
+                *(uint4 *)(xb + (idx >> 3) * LDK + (idx & 7) * 8) = xr[i];
             } else {
-                uint16_t *d = xs + (idx >> 2) * LDK + (idx & 3) * 16;
+                uint16_t *d = xb + (idx >> 2) * LDK + (idx & 3) * 16;
                 const uint2 p0 = e4m3x4_to_bf16x4(xr[i].x), p1 = e4m3x4_to_bf16x4(xr[i].y);
                 const uint2 p2 = e4m3x4_to_bf16x4(xr[i].z), p3 = e4m3x4_to_bf16x4(xr[i].w);
                 *(uint4 *)d = make_uint4(p0.x, p0.y, p1.x, p1.y);
                 *(uint4 *)(d + 8) = make_uint4(p2.x, p2.y, p3.x, p3.y);
             }
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int idx = tid + 256 * i;
-            *(uint4 *)(qs + ((idx >> 4) * 2 + ((idx >> 3) & 1)) * LDK + (idx & 7) * 8) = qr[i];
-        }
     };
 
-    rowinfo(c0, 0);
-    __syncthreads();
-    if (c0 < c1) issue(0, 0);
-    int slot = 0;
-    for (int64_t t0 = c0; t0 < c1; t0 += BR, slot = slot == 2 ? 0 : slot + 1) {
-        const int nslot = slot == 2 ? 0 : slot + 1;
-        const bool last_tile = t0 + BR >= c1;
-        f4v ah[8], al[8];
+    const int nch = ntile * nkc;
+    if (nch > 0) {
+        if (BATCHED) __syncthreads();  // query ranges are in LDS
+        rowinfo(0);
+        __syncthreads();
+        issue(0);
+    }
+    uint4 A[2][2];
+    if (nch > 0) loadA(0, A);
+    int c = 0;  // running chunk index (tile t, coordinate chunk kc)
+    for (int t = 0; t < ntile; ++t) {
+        f4v acc[2][2][NB];
 #pragma unroll
-        for (int nb = 0; nb < 8; ++nb) {
-            ah[nb] = (f4v){0.f, 0.f, 0.f, 0.f};
-            al[nb] = (f4v){0.f, 0.f, 0.f, 0.f};
-        }
-        for (int kc = 0; kc < nkc; ++kc) {
-            commit();
-            if (kc == nkc - 1 && !last_tile) rowinfo(t0 + BR, nslot);
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int hl = 0; hl < 2; ++hl)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[b][hl][nb] = (f4v){0.f, 0.f, 0.f, 0.f};
+        for (int kc = 0; kc < nkc; ++kc, ++c) {
+            const int buf = c & 1;
+            commit(buf);
+            if (kc == nkc - 1 && t + 1 < ntile) rowinfo(t + 1);
             __syncthreads();
-            if (kc + 1 < nkc)
-                issue(slot, kc + 1);
-            else if (!last_tile)
-                issue(nslot, 0);
+            if (c + 1 < nch) issue(c + 1);
+            const uint16_t *xb = L.xs + buf * BR * LDK;
 #pragma unroll
-            for (int ks = 0; ks < KC / 32; ++ks) {
-                const uint16_t *qa_p = qs + ((wave * 16 + (lane & 15)) * 2) * LDK + ks * 32 + (lane >> 4) * 8;
-                const bf8v A_hi = *(const bf8v *)qa_p;
-                const bf8v A_lo = *(const bf8v *)(qa_p + LDK);
+            for (int s = 0; s < KC / 32; ++s) {
+                const int ks = kc * 2 + s;
+                uint4 An[2][2];
+                loadA(ks + 1 < nks ? ks + 1 : 0, An);  // next k-step (the next tile starts at 0)
+                const bf8v a00 = as_bf8(A[0][0]), a01 = as_bf8(A[0][1]);
+                const bf8v a10 = as_bf8(A[1][0]), a11 = as_bf8(A[1][1]);
 #pragma unroll
-                for (int nb = 0; nb < 8; ++nb) {
-                    const bf8v Bv = *(const bf8v *)(xs + (nb * 16 + (lane & 15)) * LDK + ks * 32 + (lane >> 4) * 8);
-                    ah[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A_hi, Bv, ah[nb], 0, 0, 0);
-                    al[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A_lo, Bv, al[nb], 0, 0, 0);
+                for (int nb = 0; nb < NB; ++nb) {
+                    const bf8v Bv = *(const bf8v *)(xb + (nb * 16 + (lane & 15)) * LDK + s * 32 + (lane >> 4) * 8);
+                    acc[0][0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a00, Bv, acc[0][0][nb], 0, 0, 0);
+                    acc[0][1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a01, Bv, acc[0][1][nb], 0, 0, 0);
+                    acc[1][0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a10, Bv, acc[1][0][nb], 0, 0, 0);
+                    acc[1][1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a11, Bv, acc[1][1][nb], 0, 0, 0);
                 }
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int hl = 0; hl < 2; ++hl) A[b][hl] = An[b][hl];
             }
-            __syncthreads();
         }
 
-        // ---- epilogue: lane holds queries 16w + 4(lane/16) + i, rows 16nb + lane%16
-        if ((((t0 - c0) / BR) & 7) == 7 && lane < 16) {
-            const int qa = q0 + wave * 16 + lane;
+        // ---- epilogue of tile t: lane holds, per query block b, queries
+        // 32w + 16b + 4(lane/16) + i and rows 16nb + lane%16
+        const int slot = t % SLOTS;
+        if ((t & 7) == 7 && lane < QW) {
+            const int qa = q0 + wave * QW + lane;
             if (qa < Bq) {
                 const uint64_t g = __atomic_load_n((const unsigned long long *)(a.gthr + qa), __ATOMIC_RELAXED);
-                if (g < thr[wave * 16 + lane]) thr[wave * 16 + lane] = g;
+                if (g < L.thr[wave * QW + lane]) L.thr[wave * QW + lane] = g;
             }
         }
-        const int qb = wave * 16 + 4 * (lane >> 4);
-        uint64_t th[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) th[i] = thr[qb + i];
-#pragma unroll
-        for (int nb = 0; nb < 8; ++nb) {
-            const int r = slot * BR + nb * 16 + (lane & 15);
-            if (!rq[r]) continue;
-            const int row = rid[r];
-            const float sc = rsc[r];
+        for (int b = 0; b < 2; ++b) {
+            const int qb = wave * QW + 16 * b + 4 * (lane >> 4);
+            uint64_t th[4];
+            float thf[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int q = qb + i, qa = q0 + q;
-                if (qa >= Bq) continue;
-                if (BATCHED && !pred_eval(qpred[q], a.attr, a.an, row)) continue;
-                const float dot = ah[nb][i] + al[nb][i];
-                const float dist = STORE == VRS_FP8E4M3 ? -(sc * dot) : -dot;
-                const uint64_t key = make_key(dist, (uint32_t)row);
-                if (key < th[i]) {
-                    const int sl = atomicAdd(&cnt[q], 1);
-                    a.cbuf[((int64_t)qa * nchunks + chunk) * CBq + sl] = key;
+                th[i] = L.thr[qb + i];
+                thf[i] = key_dist(th[i]);
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int r = slot * BR + nb * 16 + (lane & 15);
+                if (!L.rok[r]) continue;
+                const int row = L.rid[r];
+                const float sc = L.rsc[r];
+                const uint32_t pmw = BATCHED ? L.pm[r * (QM / 32) + (qb >> 5)] >> (qb & 31) : 0xfu;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int q = qb + i, qa = q0 + q;
+                    if (qa >= Bq || !((pmw >> i) & 1u)) continue;
+                    const float dot = acc[b][0][nb][i] + acc[b][1][nb][i];
+                    const float dist = STORE == VRS_FP8E4M3 ? -(sc * dot) : -dot;
+                    if (!(dist <= thf[i])) continue;
+                    const uint64_t key = make_key(dist, (uint32_t)row);
+                    if (key < th[i]) {
+                        const int sl = atomicAdd(&L.cnt[q], 1);
+                        a.cbuf[((int64_t)qa * nchunks + chunk) * CBq + sl] = key;
+                    }
                 }
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         {
-            const int myc = lane < 16 ? cnt[wave * 16 + lane] : 0;
-            uint64_t full = __ballot(lane < 16 && myc > CBq - BR);
+            const int myc = lane < QW ? L.cnt[wave * QW + lane] : 0;
+            uint64_t full = __ballot(lane < QW && myc > CBq - BR);
             while (full) {
                 const int j = __ffsll((long long)full) - 1;
                 full &= full - 1;
-                const int q = wave * 16 + j, qa = q0 + q;
+                const int q = wave * QW + j, qa = q0 + q;
                 const int64_t base = (int64_t)qa * nchunks + chunk;
-                flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, cnt[q], K, Kp, &thr[q],
+                flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, L.cnt[q], K, Kp, &L.thr[q],
                                a.gthr + qa);
-                if (lane == 0) cnt[q] = 0;
+                if (lane == 0) L.cnt[q] = 0;
             }
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    const int myc = lane < 16 ? cnt[wave * 16 + lane] : 0;
-    uint64_t pend = __ballot(lane < 16 && myc > 0 && q0 + wave * 16 + lane < Bq);
+    const int myc = lane < QW ? L.cnt[wave * QW + lane] : 0;
+    uint64_t pend = __ballot(lane < QW && myc > 0 && q0 + wave * QW + lane < Bq);
     while (pend) {
         const int j = __ffsll((long long)pend) - 1;
         pend &= pend - 1;
-        const int q = wave * 16 + j, qa = q0 + q;
+        const int q = wave * QW + j, qa = q0 + q;
         const int64_t base = (int64_t)qa * nchunks + chunk;
-        flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, cnt[q], K, Kp, &thr[q],
+        flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, L.cnt[q], K, Kp, &L.thr[q],
                        a.gthr + qa);
     }
 }
-
 
 template <int STORE, bool GATHER, bool BATCHED, int E>
 __global__ __launch_bounds__(256, 2) void screen_mfma_bf16_kernel(ScreenArgs a) {
@@ -316,19 +397,6 @@ hipError_t launch_s(const ScreenArgs &a, hipStream_t s) {
     }
 }
 
-}  // namespace
-
-size_t screen_mfma_bf16_lds() {
-    return (size_t)BR * LDK * 2 + (size_t)QM * 2 * LDK * 2 + 3 * BR * 12 + QM * 4 + 8 + QM * 8 +
-           QM * sizeof(PredDev) + 16;
-}
-
-bool screen_mfma_bf16_supported(int dp, vrs_dtype store, int metric, int Kp, int CB) {
-    const int E = (Kp + CB) / 64;
-    return (store == VRS_BF16 || store == VRS_FP8E4M3) && metric == VRS_IP && dp % KC == 0 &&
-           (E == 4 || E == 8 || E == 16 || E == 32) && (Kp + CB) == 64 * E;
-}
-
 template <int STORE, int E>
 hipError_t launch_pe(const ScreenArgs &a, int grid, hipStream_t s) {
     const size_t lds = screen_mfma_bf16_lds();
@@ -348,14 +416,35 @@ hipError_t launch_p(const ScreenArgs &a, int grid, hipStream_t s) {
     }
 }
 
-hipError_t launch_screen_mfma_bf16_persistent(const ScreenArgs &a, int grid, hipStream_t s) {
-    if (a.metric != VRS_IP || !a.bctl || !a.preds) return hipErrorInvalidValue;
-    return a.store == VRS_BF16 ? launch_p<VRS_BF16>(a, grid, s) : launch_p<VRS_FP8E4M3>(a, grid, s);
+}  // namespace
+
+size_t screen_mfma_bf16_lds() {
+    return (size_t)2 * BR * LDK * 2 + (size_t)3 * SLOTS * BR * 4 + (size_t)SLOTS * BR * (QM / 32) * 4 +
+           QM * 4 + QM * 8 + QM * sizeof(QRange) + 16;
+}
+
+int screen_mfma_bf16_qm() { return QM; }
+
+// Fragment-ordered copy of the queries' bfloat16 hi/lo parts: 16-byte unit
+// ((qb * (dp / 32) + ks) * 2 + hl) * 64 + lane holds query 16 qb + lane % 16,
+// coordinates 32 ks + 8 (lane / 16) .. + 7 (the A operand of one
+// v_mfma_f32_16x16x32_bf16); bytes for queries rounded up to 16.
+size_t screen_mfma_bf16_qfrag_bytes(int B, int dp) { return (size_t)((B + 15) / 16) * 16 * dp * 2 * 2; }
+
+bool screen_mfma_bf16_supported(int dp, vrs_dtype store, int metric, int Kp, int CB) {
+    const int E = (Kp + CB) / 64;
+    return (store == VRS_BF16 || store == VRS_FP8E4M3) && metric == VRS_IP && dp % KC == 0 &&
+           (E == 4 || E == 8 || E == 16 || E == 32) && (Kp + CB) == 64 * E;
 }
 
 hipError_t launch_screen_mfma_bf16(const ScreenArgs &a, hipStream_t s) {
     if (a.metric != VRS_IP) return hipErrorInvalidValue;
     return a.store == VRS_BF16 ? launch_s<VRS_BF16>(a, s) : launch_s<VRS_FP8E4M3>(a, s);
+}
+
+hipError_t launch_screen_mfma_bf16_persistent(const ScreenArgs &a, int grid, hipStream_t s) {
+    if (a.metric != VRS_IP || !a.bctl || !a.preds) return hipErrorInvalidValue;
+    return a.store == VRS_BF16 ? launch_p<VRS_BF16>(a, grid, s) : launch_p<VRS_FP8E4M3>(a, grid, s);
 }
 
 }  // namespace vrs

@@ -55,7 +55,7 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
     P.mfma = cfg.kind == 1;
     if (P.mfma) {
         P.CB = mfma_cb(P.Kp);
-        P.qt = t->store == VRS_F32 ? cfg.qt : 64;
+        P.qt = t->store == VRS_F32 ? cfg.qt : screen_mfma_bf16_qm();
         P.n_qtiles = (B + P.qt - 1) / P.qt;
         const int occ = t->store == VRS_F32 ? screen_mfma_occupancy(P.Kp, P.CB, P.qt) : 2;
         const int64_t slots = (int64_t)256 * occ * cfg.wg_target / 4;
@@ -87,7 +87,7 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
     P.o_qp = take((size_t)B * t->dp * 4);
     P.o_qnorm = take((size_t)B * 8);
     P.o_qn2 = take((size_t)B * 4);
-    P.o_qhl = take(t->store == VRS_F32 ? 0 : (size_t)B * 2 * t->dp * 2);
+    P.o_qhl = take(t->store == VRS_F32 ? 0 : screen_mfma_bf16_qfrag_bytes(B, t->dp));
     P.o_gthr = take((size_t)B * 8);
     P.o_cbuf = take(P.mfma ? (size_t)B * P.n_chunks * P.CB * 8 : 0);
     P.o_bitmap = take((size_t)(t->n + 31) / 32 * 4);
@@ -219,7 +219,7 @@ int kprime_rule(int k, vrs_dtype store, int kmult) {
     else if (store == VRS_F32)
         kp = std::max(2 * k, k + 32);
     else
-        kp = 4 * k;
+        kp = std::max(4 * k, k + 32);
     return std::min(std::max(kp, k), 1024);
 }
 
@@ -252,6 +252,12 @@ void plan_decide(const vrs_table_s *t, int B, const PredDev &p, bool batched, in
     const int want_t = opts ? opts->tile : -1;
     const bool learned = (!opts || opts->chooser == VRS_CHOOSER_LEARNED) && chooser_ready();
     if (learned && (want_s == VRS_STRATEGY_AUTO || want_t < 0)) {
+        // A streaming tile re-reads the table once per query tile; when an
+        // MFMA tile exists, arms that would re-read it 8 or more times are
+        // not offered to the network (it has not seen every such shape).
+        bool any_mfma = false;
+        for (int tile = 0; tile < kNumTiles; ++tile)
+            if (kTiles[tile].kind == 1 && tile_ok(t, B, k, opts, tile, metric)) any_mfma = true;
         bool allowed[2 * kNumTiles];
         for (int sidx = 0; sidx < 2; ++sidx)
             for (int tile = 0; tile < kNumTiles; ++tile) {
@@ -260,6 +266,9 @@ void plan_decide(const vrs_table_s *t, int B, const PredDev &p, bool batched, in
                 if (want_s != VRS_STRATEGY_AUTO && st != want_s) ok = false;
                 if (batched && st != VRS_STRATEGY_MASK) ok = false;
                 if (want_t >= 0 && tile != want_t) ok = false;
+                if (want_t < 0 && any_mfma && kTiles[tile].kind == 0 &&
+                    (B + kTiles[tile].qt - 1) / kTiles[tile].qt >= 8)
+                    ok = false;
                 allowed[sidx * kNumTiles + tile] = ok;
             }
         const int arm = chooser_pick(feats, allowed, 2 * kNumTiles);
@@ -330,6 +339,7 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     sa.store = t->store;
     sa.attr = t->attr;
     sa.an = t->attr_stride;
+    sa.n_attr = t->n_attr;
     sa.pred = p;
     sa.preds = batched ? pdev : nullptr;
     sa.sel_ids = sel;
