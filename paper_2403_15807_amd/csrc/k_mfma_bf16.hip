@@ -38,14 +38,6 @@ constexpr int KC = 64;          // coordinates per chunk (two k-steps of 32)
 constexpr int LDK = 72;         // LDS row stride in bfloat16 elements (144 bytes)
 constexpr int SLOTS = 3;        // rotating row-record slots
 
-// Row loads: non-temporal when each row is read once (one query tile), plain
-// when the other query tiles of the same row chunk will read it again from L2.
-__device__ __forceinline__ uint4 load_x(const void *p, int shared) {
-    if (shared) return *(const uint4 *)p;
-    v4u32 v = __builtin_nontemporal_load((const v4u32 *)p);
-    return make_uint4(v.x, v.y, v.z, v.w);
-}
-
 // 4 e4m3fn codes -> 4 bfloat16 (exact), packed in two 32-bit words.
 __device__ __forceinline__ uint2 e4m3x4_to_bf16x4(uint32_t w) {
     uint32_t h[4];
@@ -124,13 +116,13 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
     const int qb0 = (q0 + wave * QW) >> 4;
     const int nqb = (a.B + 15) >> 4;
     const uint4 *QF = (const uint4 *)a.qhl;
+    // (a block past the batch reads the last one: its results are never used)
     auto loadA = [&](int ks, uint4 (&A)[2][2]) {
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int hl = 0; hl < 2; ++hl)
-                A[b][hl] = qb0 + b < nqb ? QF[((int64_t)((qb0 + b) * nks + ks) * 2 + hl) * 64 + lane]
-                                         : make_uint4(0, 0, 0, 0);
+                A[b][hl] = QF[((int64_t)(min(qb0 + b, nqb - 1) * nks + ks) * 2 + hl) * 64 + lane];
     };
 
     // per-row record of tile t: thread r < BR writes row r's id, validity
@@ -173,23 +165,29 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
         }
     };
     uint4 xr[XLD];
+    uint32_t xm[XLD];
     auto issue = [&](int c) {  // global loads of chunk c (tile c / nkc) into registers
         const int t = c / nkc, kc = c - t * nkc, slot = t % SLOTS;
+        int rr[XLD];
 #pragma unroll
         for (int i = 0; i < XLD; ++i) {
-            const int idx = tid + 256 * i;
-            const int r = STORE == VRS_BF16 ? idx >> 3 : idx >> 2;
-            const int cc = STORE == VRS_BF16 ? idx & 7 : idx & 3;
-            xr[i] = L.rok[slot * BR + r]
-                        ? load_x(X + (int64_t)L.rid[slot * BR + r] * row_bytes + kc * KC * EB + cc * 16,
-                                 a.shared_rows)
-                        : make_uint4(0, 0, 0, 0);
+            const int r = STORE == VRS_BF16 ? (tid + 256 * i) >> 3 : (tid + 256 * i) >> 2;
+            rr[i] = L.rid[slot * BR + r];
+            xm[i] = 0u - (uint32_t)(L.rok[slot * BR + r] != 0);
+        }
+        // every row id is a valid row (rows past the chunk read row 0), so
+        // the loads are unconditional; unwanted rows are zeroed at commit
+#pragma unroll
+        for (int i = 0; i < XLD; ++i) {
+            const int cc = STORE == VRS_BF16 ? (tid + 256 * i) & 7 : (tid + 256 * i) & 3;
+            xr[i] = *(const uint4 *)(X + (int64_t)rr[i] * row_bytes + kc * KC * EB + cc * 16);
         }
     };
     auto commit = [&](int buf) {
         uint16_t *xb = L.xs + buf * BR * LDK;
 #pragma unroll
         for (int i = 0; i < XLD; ++i) {
+            xr[i] = make_uint4(xr[i].x & xm[i], xr[i].y & xm[i], xr[i].z & xm[i], xr[i].w & xm[i]);
             const int idx = tid + 256 * i;
             if (STORE == VRS_BF16) {
                 *(uint4 *)(xb + (idx >> 3) * LDK + (idx & 7) * 8) = xr[i];
@@ -204,14 +202,17 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
     };
 
     const int nch = ntile * nkc;
+    // Loads are issued in the order they are consumed (they retire in
+    // order): this chunk's second k-step of query fragments, the next
+    // chunk's rows, then the next chunk's first k-step of query fragments.
+    uint4 A0[2][2], A1[2][2];
     if (nch > 0) {
         if (BATCHED) __syncthreads();  // query ranges are in LDS
         rowinfo(0);
         __syncthreads();
         issue(0);
+        loadA(0, A0);
     }
-    uint4 A[2][2];
-    if (nch > 0) loadA(0, A);
     int c = 0;  // running chunk index (tile t, coordinate chunk kc)
     for (int t = 0; t < ntile; ++t) {
         f4v acc[2][2][NB];
@@ -226,28 +227,37 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
             commit(buf);
             if (kc == nkc - 1 && t + 1 < ntile) rowinfo(t + 1);
             __syncthreads();
-            if (c + 1 < nch) issue(c + 1);
-            const uint16_t *xb = L.xs + buf * BR * LDK;
+            loadA(kc * 2 + 1, A1);
+            __builtin_amdgcn_sched_barrier(0);
+            issue(c + 1 < nch ? c + 1 : c);  // (the last chunk reloads itself, unused)
+            __builtin_amdgcn_sched_barrier(0);
+            uint4 An[2][2];
+            loadA(kc * 2 + 2 < nks ? kc * 2 + 2 : 0, An);  // the next tile starts at k-step 0
+            __builtin_amdgcn_sched_barrier(0);
+            const uint16_t *xb = L.xs + buf * BR * LDK + (lane & 15) * LDK + (lane >> 4) * 8;
 #pragma unroll
             for (int s = 0; s < KC / 32; ++s) {
-                const int ks = kc * 2 + s;
-                uint4 An[2][2];
-                loadA(ks + 1 < nks ? ks + 1 : 0, An);  // next k-step (the next tile starts at 0)
+                const uint4(&A)[2][2] = s == 0 ? A0 : A1;
                 const bf8v a00 = as_bf8(A[0][0]), a01 = as_bf8(A[0][1]);
                 const bf8v a10 = as_bf8(A[1][0]), a11 = as_bf8(A[1][1]);
+                bf8v Bc = *(const bf8v *)(xb + s * 32);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    const bf8v Bv = *(const bf8v *)(xb + (nb * 16 + (lane & 15)) * LDK + s * 32 + (lane >> 4) * 8);
-                    acc[0][0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a00, Bv, acc[0][0][nb], 0, 0, 0);
-                    acc[0][1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a01, Bv, acc[0][1][nb], 0, 0, 0);
-                    acc[1][0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a10, Bv, acc[1][0][nb], 0, 0, 0);
-                    acc[1][1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a11, Bv, acc[1][1][nb], 0, 0, 0);
+                    // the next 16-row fragment is read while these four run
+                    const bf8v Bn = *(const bf8v *)(xb + ((nb + 1) & (NB - 1)) * 16 * LDK + s * 32);
+                    __builtin_amdgcn_sched_barrier(0);
+                    acc[0][0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a00, Bc, acc[0][0][nb], 0, 0, 0);
+                    acc[0][1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a01, Bc, acc[0][1][nb], 0, 0, 0);
+                    acc[1][0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a10, Bc, acc[1][0][nb], 0, 0, 0);
+                    acc[1][1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a11, Bc, acc[1][1][nb], 0, 0, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    Bc = Bn;
                 }
-#pragma unroll
-                for (int b = 0; b < 2; ++b)
-#pragma unroll
-                    for (int hl = 0; hl < 2; ++hl) A[b][hl] = An[b][hl];
             }
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int hl = 0; hl < 2; ++hl) A0[b][hl] = An[b][hl];
         }
 
         // ---- epilogue of tile t: lane holds, per query block b, queries
