@@ -98,6 +98,7 @@ struct ScreenArgs {
     int32_t n_chunks;
     int32_t shared_rows;           // rows are read by several query tiles: keep them cacheable
     uint64_t *partials;            // [B][n_chunks][K]
+    uint64_t *heads;               // [B][n_chunks] first key of each list, or null
     uint64_t *cbuf;                // [B][n_chunks][CB] candidate buffers (MFMA kernels)
     uint64_t *gthr;                // [B] smallest K-th key published by any chunk
     // batched uneven form only (null otherwise): control words written on the
@@ -273,11 +274,14 @@ struct FinishArgs {
     int32_t K;                     // list length = max k' + 1
     int32_t n_chunks;
     const uint64_t *partials;
+    const uint64_t *heads;         // [B][n_chunks] first key of each list, or null
     const int64_t *list_off;       // batched uneven form: [B] first list of each position
     const int32_t *nlists;         // and its list count (null: n_chunks lists per query)
     const int32_t *perm;           // position -> query index (null: identity)
     uint64_t *merge_mid;           // [B][ceil(n_chunks/2048)][K] (two-level merge)
     uint64_t *merged;              // [B][K]
+    double *rr_dist;               // [B][K] exact distances of the candidates
+    int32_t *rr_count;             // [B] rerank arrival counters (zeroed by the merge)
     double rel, abs_ip, abs_l2, max_norm;  // screening error model
     int32_t *fail_list;            // [B]
     int32_t *fail_count;           // [1]

@@ -147,58 +147,133 @@ __device__ __forceinline__ int kp_of(const FinishArgs &a, int b) {
 //
 // Every list is sorted, so the K-th smallest of the lists' first m entries
 // ("heads") is an upper bound on the K-th smallest key overall: K keys at or
-// below it exist.  Only the list prefixes at or below that bound are read
-// and merged; with the chunk lists of a scan that is a few keys per list.
+// below it exist.  Only the list prefixes at or below that bound can hold
+// one of the K smallest; with the chunk lists of a scan that is a few keys
+// per list.  Those keys are collected and sorted once; if there are more
+// than fit, they go through an LDS top-k list instead.
 constexpr int MERGE_THREADS = 512;
 constexpr int MERGE_HMAX = 4096;
+constexpr int MERGE_RANK_MAX = 1024;  // collected keys sorted by ranking
+
+// The K-th smallest (1 <= K <= H) of H values spread over the T threads of
+// a workgroup (value i in thread i % T, slot i / T of v), by an 8-bit radix
+// select: each pass counts the values that share the digits fixed so far
+// by their next digit and keeps the digit whose bucket holds the K-th.
+// Every thread returns the same value.
+template <int S, int T>
+__device__ uint32_t block_kth_u32(const uint32_t (&v)[S], int H, int K, uint32_t *hist,
+                                  uint32_t *sel) {
+    const int tid = threadIdx.x;
+    uint32_t prefix = 0, mask = 0, kk = (uint32_t)K;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int i = tid; i < 256; i += T) hist[i] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < S; ++e)
+            if (e * T + tid < H && (v[e] & mask) == prefix) atomicAdd(&hist[(v[e] >> shift) & 255u], 1u);
+        __syncthreads();
+        if (tid < 64) {
+            uint32_t c[4], sum = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                c[e] = hist[tid * 4 + e];
+                sum += c[e];
+            }
+            uint32_t incl = sum;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(incl, o);
+                if (tid >= o) incl += t;
+            }
+            uint32_t run = incl - sum;
+            if (run < kk && kk <= incl) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (run < kk && kk <= run + c[e]) {
+                        sel[0] = prefix | ((uint32_t)(tid * 4 + e) << shift);
+                        sel[1] = kk - run;
+                    }
+                    run += c[e];
+                }
+            }
+        }
+        __syncthreads();
+        prefix = sel[0];
+        kk = sel[1];
+        mask |= 255u << shift;
+    }
+    return prefix;
+}
 
 __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__restrict__ src,
                                                               int n_lists, int G, int K, int Kp,
                                                               int CB, uint64_t *__restrict__ dst,
                                                               int n_out,
                                                               const int64_t *__restrict__ list_off,
-                                                              const int32_t *__restrict__ nlists) {
+                                                              const int32_t *__restrict__ nlists,
+                                                              const uint64_t *__restrict__ heads,
+                                                              int32_t *__restrict__ rr_count) {
     constexpr int T = MERGE_THREADS;
     const int g = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+    if (rr_count && tid == 0) rr_count[b] = 0;  // the rerank's arrival counter
     extern __shared__ __align__(16) unsigned char smem[];
     // query b's lists: n_lists of them at b * n_lists, or (batched uneven
     // form) nlists[b] of them at list_off[b]
     const int nb = nlists ? nlists[b] : n_lists;
     const int64_t first = nlists ? list_off[b] : (int64_t)b * n_lists;
     const int l0 = g * G, l1 = min(nb, l0 + G), L = l1 - l0;
+    uint64_t *out = dst + ((int64_t)b * n_out + g) * K;
     if (L <= 0) {  // no list: an empty result
-        for (int i = tid; i < K; i += T) dst[((int64_t)b * n_out + g) * K + i] = KEY_INF;
+        for (int i = tid; i < K; i += T) out[i] = KEY_INF;
         return;
     }
     const uint64_t *lists = src + (first + l0) * K;
     const int M = Kp + CB;
-    uint64_t *keys = (uint64_t *)smem;                         // heads, then the top-k list
+    uint64_t *keys = (uint64_t *)smem;  // heads, then the collected keys
     const int region = max(M, MERGE_HMAX);
     uint64_t *thr = keys + region;
     int *cnt = (int *)(thr + 1);
-    __shared__ uint64_t bound_s;
+    __shared__ uint32_t bound_s;
+    __shared__ int ncol_s;
 
-    // phase 1: bound from the heads
+    // phase 1: the K-th smallest head's distance bits bound every key of
+    // the result (keys with the same distance bits are all kept)
     int m = max(1, min(K, (2 * K + L - 1) / L));
     if (L * m > MERGE_HMAX) m = max(1, MERGE_HMAX / L);
     const int H = min(L * m, MERGE_HMAX);
-    const int HP = next_pow2(max(H, 2));
-    for (int i = tid; i < HP; i += T) keys[i] = i < H ? lists[(int64_t)(i / m) * K + (i % m)] : KEY_INF;
+    // with one head per list, a side array of the lists' first keys (when
+    // the screening kernel wrote one) is read instead of the lists
+    const uint64_t *hd = (heads && m == 1) ? heads + first + l0 : nullptr;
+    if (tid == 0) ncol_s = 0;
+    if (H < K) {
+        if (tid == 0) bound_s = 0xffffffffu;
+    } else {
+        constexpr int S = MERGE_HMAX / T;
+        uint32_t v[S];
+#pragma unroll
+        for (int e = 0; e < S; ++e) {
+            const int i = min(e * T + tid, H - 1);
+            const uint64_t key = hd ? hd[i] : lists[(int64_t)(i / m) * K + (i % m)];
+            v[e] = (uint32_t)(key >> 32);
+        }
+        uint32_t *hist = (uint32_t *)keys;  // the collection area is free until phase 2
+        const uint32_t bd = block_kth_u32<S, T>(v, H, K, hist, hist + 256);
+        if (tid == 0) bound_s = bd;
+    }
     __syncthreads();
-    lds_bitonic_sort<uint64_t>(keys, 1, HP, tid, T);
-    if (tid == 0) bound_s = (H >= K) ? keys[K - 1] : KEY_INF;
-    __syncthreads();
-    const uint64_t bound = bound_s;
+    const uint64_t bound = ((uint64_t)bound_s << 32) | 0xffffffffu;
 
-    // phase 2: merge every list prefix at or below the bound.  Thread tid owns
-    // lists tid + j*T (j < 4, since G <= 4T); each round it reads the next two
-    // entries of up to two of its lists, so most lists cost one round.
-    TopkLds<uint64_t> tk{keys, cnt, thr, 1, K, Kp, CB};
-    tk.init(tid, T);
+    // phase 2: collect every list prefix at or below the bound.  Thread tid
+    // owns lists tid + j*T (j < 4, since G <= 4T); each round it reads the
+    // next two entries of up to two of its lists, so most lists cost one
+    // round.
     int pos[4] = {0, 0, 0, 0};
     bool live[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) live[j] = tid + j * T < L;
+    for (int j = 0; j < 4; ++j) {
+        const int l = tid + j * T;
+        live[j] = l < L && (!hd || hd[min(l, L - 1)] <= bound);
+    }
     for (;;) {
         int sel0 = -1, sel1 = -1;
 #pragma unroll
@@ -223,10 +298,12 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 const uint64_t key = v[x][e];
-                if (keep && key != KEY_INF && key <= bound)
-                    tk.push(0, key);
-                else
+                if (keep && key != KEY_INF && key <= bound) {
+                    const int slot = atomicAdd(&ncol_s, 1);
+                    if (slot < region) keys[slot] = key;
+                } else {
                     keep = false;
+                }
             }
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj)
@@ -238,114 +315,307 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
         bool any = false;
 #pragma unroll
         for (int j = 0; j < 4; ++j) any = any || live[j];
+        if (!__syncthreads_or(any)) break;
+    }
+    const int C = ncol_s;
+    if (C <= MERGE_RANK_MAX) {
+        // keys are distinct (each row has one), so a key's rank among the
+        // collected ones is its place in the result
+        const int C8 = (C + 7) & ~7;
+        if (tid < C8 - C) keys[C + tid] = KEY_INF;
+        __syncthreads();
+        const uint64_t k0 = tid < C ? keys[tid] : KEY_INF;
+        const uint64_t k1 = tid + T < C ? keys[tid + T] : KEY_INF;
+        int r0 = 0, r1 = 0;
+        for (int j = 0; j < C8; j += 8) {
+            uint64_t a8[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) a8[e] = keys[j + e];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                r0 += a8[e] < k0;
+                r1 += a8[e] < k1;
+            }
+        }
+        if (tid < C && r0 < K) out[r0] = k0;
+        if (tid + T < C && r1 < K) out[r1] = k1;
+        for (int i = C + tid; i < K; i += T) out[i] = KEY_INF;
+        return;
+    }
+    if (C <= region) {
+        const int CP = next_pow2(C);
+        for (int i = C + tid; i < CP; i += T) keys[i] = KEY_INF;
+        __syncthreads();
+        lds_bitonic_sort<uint64_t>(keys, 1, CP, tid, T);
+        for (int i = tid; i < K; i += T) out[i] = i < C ? keys[i] : KEY_INF;
+        return;
+    }
+
+    // more candidates than fit: merge them through an LDS top-k list
+    __syncthreads();
+    TopkLds<uint64_t> tk{keys, cnt, thr, 1, K, Kp, CB};
+    tk.init(tid, T);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        pos[j] = 0;
+        live[j] = tid + j * T < L;
+    }
+    for (;;) {
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!live[j]) continue;
+            const uint64_t key = lists[(int64_t)(tid + j * T) * K + pos[j]];
+            if (key != KEY_INF && key <= bound) {
+                tk.push(0, key);
+                ++pos[j];
+                live[j] = pos[j] < K;
+            } else {
+                live[j] = false;
+            }
+            any = any || live[j];
+        }
         const bool more = __syncthreads_or(any);
         if (tk.need_flush(T * 4)) tk.flush(tid, T);
         if (!more) break;
     }
     if (tk.need_flush(CB)) tk.flush(tid, T);
-    for (int i = tid; i < K; i += T) dst[((int64_t)b * n_out + g) * K + i] = keys[i];
+    for (int i = tid; i < K; i += T) out[i] = keys[i];
 }
 
 // ----------------------------------------------------------------- rerank
-// One workgroup per query.  Each lane owns one candidate and runs the exact
-// FP64 formula over it in coordinate order; the rows themselves are loaded
-// cooperatively (8 lanes per 128-byte block of a row, 8 loads in flight per
-// lane) into LDS, one 128-byte column chunk of 64 rows per wave at a time.
-constexpr int RR_CHUNK = 8;  // 16-byte blocks per row per chunk
+// Workgroup (s, b) holds candidates [s*RR_ROWS, (s+1)*RR_ROWS) of query b's
+// first k' screening keys, RR_WROWS per wave.  A wave stages its rows through
+// LDS in column chunks of RR_CH 16-byte blocks (one coalesced load per row
+// per chunk, the next chunk in flight while the current one is summed), and
+// its lane r runs the exact FP64 formula over candidate r in coordinate
+// order.  Spreading one query's candidates over several workgroups puts
+// several CUs' load queues on the scattered rows.  The last workgroup of a
+// query to finish (an arrival counter, zeroed by the final merge level)
+// ranks the candidates by exact distance, checks the certificate and writes
+// the result.
+constexpr int RR_WROWS = 8;
+constexpr int RR_THREADS = 256;
+constexpr int RR_ROWS = RR_WROWS * (RR_THREADS / 64);
+constexpr int RR_CH = 64;
+typedef unsigned int rr_u32x4 __attribute__((ext_vector_type(4)));
 
-template <int STORE, int METRIC>
-__global__ __launch_bounds__(256) void rerank_kernel(FinishArgs a) {
-    constexpr int V = STORE == VRS_F32 ? 4 : (STORE == VRS_BF16 ? 8 : 16);
-    constexpr int EB = 16 / V;
-    const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int ob = a.perm ? a.perm[b] : b;  // the query at position b
-    const int kb = k_of(a, b), kpb = kp_of(a, b);
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int Mc = next_pow2(max(kpb, 2));
-    Key128 *cand = (Key128 *)smem;                           // [Mc]
-    uint4 *stage = (uint4 *)(cand + Mc);                     // [4][64][RR_CHUNK + 1]
-    float *qrow = (float *)(stage + 4 * 64 * (RR_CHUNK + 1)); // [dp], zero padded
-    __shared__ int n_cand_s;
-    for (int j = tid; j < a.dp; j += 256) qrow[j] = j < a.d ? a.q[(int64_t)ob * a.d + j] : 0.0f;
-    if (tid == 0) n_cand_s = 0;
-    __syncthreads();
-    const uint64_t *lst = a.merged + (int64_t)b * a.K;
-    const int nb16 = a.dp / V;                               // 16-byte blocks per row
-    const int64_t row_bytes = (int64_t)a.dp * EB;
-    uint4 *my_stage = stage + (wave * 64) * (RR_CHUNK + 1);
-    int mycnt = 0;
-    for (int g0 = 0; g0 < Mc; g0 += 256) {
-        const int ci = g0 + tid;
-        int64_t myrow = -1;
-        if (ci < kpb) {
-            uint64_t key = lst[ci];
-            if (key != KEY_INF) myrow = (int64_t)(uint32_t)key;
-        }
-        double acc = 0.0;
-        const double sc = (STORE == VRS_FP8E4M3 && myrow >= 0) ? (double)a.scale[myrow] : 1.0;
-        for (int c0 = 0; c0 < nb16; c0 += RR_CHUNK) {
-            uint4 w[8];
+__device__ __forceinline__ void rr_load(rr_u32x4 (&w)[RR_WROWS],
+                                        const char *const (&rp)[RR_WROWS], int c0, int nb16,
+                                        int lane) {
+    const int c = min(c0 + lane, nb16 - 1);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int src = (lane >> 3) + 8 * i;
-                const int64_t rr = __shfl(myrow, src);
-                w[i] = rr >= 0 ? *(const uint4 *)((const char *)a.rows + rr * row_bytes +
-                                                  (int64_t)(c0 + (lane & 7)) * 16)
-                               : make_uint4(0, 0, 0, 0);
-            }
+    for (int r = 0; r < RR_WROWS; ++r) w[r] = *(const rr_u32x4 *)(rp[r] + (int64_t)c * 16);
+}
+
+__device__ __forceinline__ bool k128_less(uint64_t ah, uint32_t al, uint64_t bh, uint32_t bl) {
+    return ah < bh || (ah == bh && al < bl);
+}
+
+// Ascending bitonic sort of the RR_THREADS*E keys (hi, lo) held E per
+// thread, element i in thread i % RR_THREADS, slot i / RR_THREADS.  Strides
+// below 64 exchange through lane shuffles, strides of a whole wave or more
+// but below RR_THREADS through LDS (xh, xl), larger ones inside a thread.
+template <int E>
+__device__ void rr_bitonic(uint64_t (&h)[E], uint32_t (&l)[E], uint64_t *xh, uint32_t *xl) {
+    constexpr int T = RR_THREADS;
+    const int tid = threadIdx.x;
+    for (int k = 2; k <= T * E; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= T) {
+                const int je = j / T;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) my_stage[((lane >> 3) + 8 * i) * (RR_CHUNK + 1) + (lane & 7)] = w[i];
-            __syncthreads();
-            if (myrow >= 0) {
-                for (int blk = 0; blk < RR_CHUNK; ++blk) {
-                    float x[V];
-                    decode16<STORE>(my_stage[lane * (RR_CHUNK + 1) + blk], x);
-                    const float *qj = qrow + (c0 + blk) * V;
-#pragma unroll
-                    for (int v = 0; v < V; ++v) {
-                        if (METRIC == VRS_L2SQ) {
-                            double t = (double)qj[v] - sc * (double)x[v];
-                            acc = fma(t, t, acc);
-                        } else {
-                            acc = fma((double)qj[v], (double)x[v], acc);
+                for (int e = 0; e < E; ++e) {
+                    const int p = e ^ je;
+                    if (p > e) {
+                        const bool up = ((e * T + tid) & k) == 0;
+                        if (k128_less(h[p], l[p], h[e], l[e]) == up) {
+                            const uint64_t th = h[e];
+                            const uint32_t tl = l[e];
+                            h[e] = h[p]; l[e] = l[p];
+                            h[p] = th; l[p] = tl;
                         }
                     }
                 }
+                continue;
             }
-            __syncthreads();
-        }
-        if (ci < Mc) {
-            Key128 c = KeyOps<Key128>::inf();
-            if (myrow >= 0) {
-                if (METRIC == VRS_IP) acc = -(sc * acc);
-                c.hi = ord64(acc == 0.0 ? 0.0 : acc);
-                c.lo = (uint64_t)myrow;
-                ++mycnt;
+            uint64_t ph[E];
+            uint32_t pl[E];
+            if (j >= 64) {
+                __syncthreads();
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    xh[e * T + tid] = h[e];
+                    xl[e * T + tid] = l[e];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    ph[e] = xh[e * T + (tid ^ j)];
+                    pl[e] = xl[e * T + (tid ^ j)];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    ph[e] = shfl_xor_u64(h[e], j);
+                    pl[e] = (uint32_t)__shfl_xor((int)l[e], j);
+                }
             }
-            cand[ci] = c;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int i = e * T + tid;
+                const bool take_min = ((i & j) == 0) == ((i & k) == 0);
+                const bool pless = k128_less(ph[e], pl[e], h[e], l[e]);
+                if (pless == take_min) {
+                    h[e] = ph[e];
+                    l[e] = pl[e];
+                }
+            }
         }
     }
-    atomicAdd(&n_cand_s, mycnt);
+}
+
+// Rank the first n candidates of cand by exact key and keep the first kb
+// (in order) in srt.
+template <int E>
+__device__ void rr_sort(const Key128 *cand, int n, int kb, Key128 *srt, uint64_t *xh, uint32_t *xl) {
+    constexpr int T = RR_THREADS;
+    const int tid = threadIdx.x;
+    uint64_t h[E];
+    uint32_t l[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = e * T + tid;
+        h[e] = i < n ? cand[i].hi : ~0ull;
+        l[e] = i < n ? (uint32_t)cand[i].lo : ~0u;
+    }
+    rr_bitonic<E>(h, l, xh, xl);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = e * T + tid;
+        if (i < kb && i < n) srt[i] = Key128{h[e], (uint64_t)l[e]};
+    }
+}
+
+template <int STORE, int METRIC>
+__global__ __launch_bounds__(RR_THREADS) void rerank_kernel(FinishArgs a) {
+    constexpr int V = STORE == VRS_F32 ? 4 : (STORE == VRS_BF16 ? 8 : 16);
+    constexpr int EB = 16 / V;
+    constexpr int T = RR_THREADS;
+    const int s = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int kpb = kp_of(a, b);
+    const int ns = (kpb + RR_ROWS - 1) / RR_ROWS;  // workgroups with candidates of query b
+    if (s >= ns) return;
+    const int ob = a.perm ? a.perm[b] : b;  // the query at position b
+    extern __shared__ __align__(16) unsigned char smem[];
+    rr_u32x4 *stage = (rr_u32x4 *)smem + wave * RR_WROWS * (RR_CH + 1);  // [RR_WROWS][RR_CH + 1]
+    float *qrow = (float *)((rr_u32x4 *)smem + (T / 64) * RR_WROWS * (RR_CH + 1));  // [dp]
+    Key128 *cand = (Key128 *)(qrow + ((a.dp + 3) & ~3));  // [round8(k')] (last workgroup)
+    Key128 *srt = cand + ((a.K + 7) & ~7);                 // [k] in exact order
+    __shared__ int last_s, n_cand_s;
+    for (int j = tid; j < a.dp; j += T) qrow[j] = j < a.d ? a.q[(int64_t)ob * a.d + j] : 0.0f;
+    if (tid == 0) n_cand_s = 0;
+    const uint64_t *lst = a.merged + (int64_t)b * a.K;
+    const int nb16 = a.dp / V;  // 16-byte blocks per row
+    const int64_t row_bytes = (int64_t)a.dp * EB;
+    const int ci0 = s * RR_ROWS + wave * RR_WROWS;
+    // candidate rows (a slot without a candidate reads row 0 and drops it)
+    const char *rp[RR_WROWS];
+    int64_t myrow = -1;
+#pragma unroll
+    for (int r = 0; r < RR_WROWS; ++r) {
+        const int ci = ci0 + r;
+        const uint64_t key = lst[min(ci, kpb - 1)];
+        const int64_t row = (ci < kpb && key != KEY_INF) ? (int64_t)(uint32_t)key : -1;
+        rp[r] = (const char *)a.rows + (row < 0 ? 0 : row) * row_bytes;
+        if (lane == r) myrow = row;
+    }
+    const double sc = (STORE == VRS_FP8E4M3 && myrow >= 0) ? (double)a.scale[myrow] : 1.0;
+    double acc = 0.0;
+    rr_u32x4 w[RR_WROWS];
+    rr_load(w, rp, 0, nb16, lane);
+    for (int c0 = 0; c0 < nb16; c0 += RR_CH) {
+        const int chn = min(RR_CH, nb16 - c0);
+        __syncthreads();  // previous chunk consumed (and, first time, qrow written)
+        if (lane < chn) {
+#pragma unroll
+            for (int r = 0; r < RR_WROWS; ++r) stage[r * (RR_CH + 1) + lane] = w[r];
+        }
+        __syncthreads();
+        rr_load(w, rp, c0 + RR_CH, nb16, lane);  // clamped: harmless past the end
+        if (lane < RR_WROWS) {
+            const rr_u32x4 *my = stage + lane * (RR_CH + 1);
+            for (int c = 0; c < chn; ++c) {
+                float x[V];
+                const rr_u32x4 u = my[c];
+                decode16<STORE>(make_uint4(u.x, u.y, u.z, u.w), x);
+                const float *qj = qrow + (c0 + c) * V;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    if (METRIC == VRS_L2SQ) {
+                        const double t = (double)qj[v] - sc * (double)x[v];
+                        acc = fma(t, t, acc);
+                    } else {
+                        acc = fma((double)qj[v], (double)x[v], acc);
+                    }
+                }
+            }
+        }
+    }
+    double *dist = a.rr_dist + (int64_t)b * a.K;
+    if (lane < RR_WROWS && myrow >= 0) {
+        if (METRIC == VRS_IP) acc = -(sc * acc);
+        dist[ci0 + lane] = acc;
+    }
+    // arrival: the last workgroup of query b finishes it
+    __threadfence();
     __syncthreads();
-    lds_bitonic_sort<Key128>(cand, 1, Mc, tid, 256);
+    if (tid == 0) last_s = atomicAdd(&a.rr_count[b], 1) == ns - 1;
+    __syncthreads();
+    if (!last_s) return;
+    __threadfence();
+
+    // the screening keys are sorted with empty slots last, so the candidates
+    // are the first n_cand of them
+    const int kb = k_of(a, b);
+    int valid = 0;
+    for (int ci = tid; ci < kpb; ci += T) {
+        const uint64_t key = lst[ci];
+        if (key != KEY_INF) {
+            const double dv = dist[ci];
+            cand[ci] = Key128{ord64(dv == 0.0 ? 0.0 : dv), (uint64_t)(uint32_t)key};
+            ++valid;
+        }
+    }
+    if (valid) atomicAdd(&n_cand_s, valid);
+    __syncthreads();
     const int n_cand = n_cand_s;
+    // exchange buffers of the sort: the row staging area, free by now
+    uint64_t *xh = (uint64_t *)smem;
+    uint32_t *xl = (uint32_t *)(xh + 4 * T);
+    if (n_cand <= T)
+        rr_sort<1>(cand, n_cand, kb, srt, xh, xl);
+    else if (n_cand <= 2 * T)
+        rr_sort<2>(cand, n_cand, kb, srt, xh, xl);
+    else
+        rr_sort<4>(cand, n_cand, kb, srt, xh, xl);
+    __syncthreads();
     bool ok = true;
     const uint64_t akey = lst[kpb];  // (k'+1)-th smallest screening key
     if (akey != KEY_INF && n_cand >= kb) {
-        double av = (double)unord32((uint32_t)(akey >> 32));
-        double qn = a.qnorm[b];
-        double E = a.rel * fabs(av) + a.abs_ip * qn * a.max_norm +
-                   a.abs_l2 * (qn + a.max_norm) * (qn + a.max_norm);
-        double ek = unord64(cand[kb - 1].hi);
-        ok = ek < av - E;
+        const double av = (double)unord32((uint32_t)(akey >> 32));
+        const double qn = a.qnorm[b];
+        const double E = a.rel * fabs(av) + a.abs_ip * qn * a.max_norm +
+                         a.abs_l2 * (qn + a.max_norm) * (qn + a.max_norm);
+        ok = unord64(srt[kb - 1].hi) < av - E;
     }
     if (ok) {
         const int m = min(kb, n_cand);
-        for (int i = tid; i < a.kmax; i += 256) {
-            int64_t o = (int64_t)ob * a.kmax + i;
+        for (int i = tid; i < a.kmax; i += T) {
+            const int64_t o = (int64_t)ob * a.kmax + i;
             if (i < m) {
-                a.out_idx[o] = (int64_t)cand[i].lo;
-                a.out_dist[o] = (float)unord64(cand[i].hi);
+                a.out_idx[o] = (int64_t)srt[i].lo;
+                a.out_dist[o] = (float)unord64(srt[i].hi);
             } else {
                 a.out_idx[o] = -1;
                 a.out_dist[o] = __int_as_float(0x7f800000);
@@ -357,7 +627,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(FinishArgs a) {
         }
     } else if (tid == 0) {
         if (a.certified) a.certified[ob] = 0;
-        int slot = atomicAdd(a.fail_count, 1);
+        const int slot = atomicAdd(a.fail_count, 1);
         a.fail_list[slot] = b;
     }
 }
@@ -514,24 +784,27 @@ hipError_t launch_merge(const FinishArgs &a, hipStream_t s) {
     const int G = 2048;
     if (a.n_chunks <= G) {
         merge_kernel<<<dim3(1, a.B), MERGE_THREADS, lds, s>>>(a.partials, a.n_chunks, G, a.K, Kp,
-                                                             CB, a.merged, 1, a.list_off, a.nlists);
+                                                             CB, a.merged, 1, a.list_off, a.nlists,
+                                                             a.heads, a.rr_count);
         return hipGetLastError();
     }
     // two levels: groups of G lists, then the group results
     const int ng = (a.n_chunks + G - 1) / G;
     uint64_t *mid = a.merge_mid;
     merge_kernel<<<dim3(ng, a.B), MERGE_THREADS, lds, s>>>(a.partials, a.n_chunks, G, a.K, Kp, CB,
-                                                          mid, ng, a.list_off, a.nlists);
+                                                          mid, ng, a.list_off, a.nlists, a.heads, nullptr);
     merge_kernel<<<dim3(1, a.B), MERGE_THREADS, lds, s>>>(mid, ng, ng, a.K, Kp, CB, a.merged, 1,
-                                                         nullptr, nullptr);
+                                                         nullptr, nullptr, nullptr, a.rr_count);
     return hipGetLastError();
 }
 
 template <int STORE, int METRIC>
 static hipError_t rerank_t(const FinishArgs &a, hipStream_t s, int kpmax) {
-    size_t lds = (size_t)next_pow2(std::max(kpmax, 2)) * sizeof(Key128) +
-                 (size_t)4 * 64 * (RR_CHUNK + 1) * 16 + (size_t)a.dp * 4 + 16;
-    rerank_kernel<STORE, METRIC><<<a.B, 256, lds, s>>>(a);
+    const size_t lds = (size_t)RR_ROWS * (RR_CH + 1) * 16 + (size_t)((a.dp + 3) & ~3) * 4 +
+                       (size_t)2 * ((a.K + 7) & ~7) * sizeof(Key128);
+    ensure_dyn_lds((const void *)rerank_kernel<STORE, METRIC>, lds);
+    const int ns = (kpmax + RR_ROWS - 1) / RR_ROWS;
+    rerank_kernel<STORE, METRIC><<<dim3(ns, a.B), RR_THREADS, lds, s>>>(a);
     return hipGetLastError();
 }
 

@@ -209,6 +209,9 @@ __global__ __launch_bounds__(256) void screen_stream_kernel(ScreenArgs a) {
         if (qt0 + b < a.B)
             a.partials[((int64_t)(qt0 + b) * a.n_chunks + chunk) * a.K + j] = keys[b * M + j];
     }
+    // the lists' first keys side by side, for the merge's bound
+    if (a.heads && tid < QT && qt0 + tid < a.B)
+        a.heads[(int64_t)(qt0 + tid) * a.n_chunks + chunk] = keys[tid * M];
 }
 
 template <int QT, int METRIC, int STORE>

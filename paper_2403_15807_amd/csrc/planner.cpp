@@ -95,8 +95,11 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
     P.o_sel = take((size_t)t->n * 4);
     P.o_selcnt = take(8);
     P.o_part = take((size_t)B * P.n_chunks * P.K * 8);
+    P.o_heads = take(P.mfma ? 0 : (size_t)B * P.n_chunks * 8);
     P.o_mid = take((size_t)B * ((P.n_chunks + 2047) / 2048) * P.K * 8);
     P.o_merged = take((size_t)B * P.K * 8);
+    P.o_rrdist = take((size_t)B * P.K * 8);
+    P.o_rrcnt = take((size_t)B * 4);
     P.o_fail = take((size_t)B * 4);
     P.o_failcnt = take(8);
     P.o_fb = take((size_t)B * P.fb_chunks * kmax * 16);
@@ -359,6 +362,7 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     sa.n_chunks = P.n_chunks;
     sa.shared_rows = P.n_qtiles > 1;
     sa.partials = (uint64_t *)(w + P.o_part);
+    sa.heads = P.mfma ? nullptr : (uint64_t *)(w + P.o_heads);
     prof_begin(2, s);
     if (!P.mfma)
         e = launch_screen_stream(sa, P.qt, s);
@@ -392,8 +396,11 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     fa.K = P.K;
     fa.n_chunks = P.n_chunks;
     fa.partials = sa.partials;
+    fa.heads = sa.heads;
     fa.merge_mid = (uint64_t *)(w + P.o_mid);
     fa.merged = (uint64_t *)(w + P.o_merged);
+    fa.rr_dist = (double *)(w + P.o_rrdist);
+    fa.rr_count = (int32_t *)(w + P.o_rrcnt);
     // Screening error bound, FP32 accumulation in any order (both sides of the
     // certificate also carry the FP64 sum's own error):
     //   VALU L2SQ: sum of dp non-negative rounded terms -> relative gamma_{dp+3};

@@ -31,7 +31,7 @@ struct Plan {
     int kprime, K, Kp, CB;
     int fb_chunks, fb_rows_per_chunk;
     // workspace offsets (bytes)
-    size_t o_qp, o_qnorm, o_qn2, o_qhl, o_gthr, o_cbuf, o_bitmap, o_blk, o_sel, o_selcnt, o_part, o_mid, o_merged, o_fail,
+    size_t o_qp, o_qnorm, o_qn2, o_qhl, o_gthr, o_cbuf, o_bitmap, o_blk, o_sel, o_selcnt, o_part, o_heads, o_mid, o_merged, o_rrdist, o_rrcnt, o_fail,
         o_failcnt, o_fb, o_preds, o_kc, o_kps, total;
 };
 

@@ -287,3 +287,20 @@ def test_lowprec_mfma_one_coordinate_chunk_partial_query_tile(store):
             for strategy in (vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER):
                 r = T.scan_topk(_dev(q), pred, k, vrs.IP, tile=tile, strategy=strategy)
                 _check(r, ref, f"store {store} sel {sel} k {k} tile {tile} strategy {strategy}")
+
+
+@pytest.mark.parametrize("B", [1, 9])
+def test_lowprec_largest_k_prime(B):
+    # bfloat16 rows at k = 256 take k' = 1024: the widest screening lists,
+    # merge bound over up to 4096 heads and the four-keys-per-thread sort
+    n, d, k = 30000, 96, 256
+    x = inputs.table(6, n, d, 40)
+    a = inputs.attributes(6, n, 2, 1000)
+    q = inputs.queries(6, B, d, 40)
+    T = vrs.Table(_dev(x), _dev(a), store=vrs.BF16, normalize=True)
+    ot = O.Table.build(x, a, O.BF16, True)
+    pred = [(0, 0, 900)]
+    ref = O.scan_topk(ot, q, pred, k, O.IP)
+    for strategy in (vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER):
+        r = T.scan_topk(_dev(q), pred, k, vrs.IP, strategy=strategy)
+        _check(r, ref, f"B {B} strategy {strategy}")
