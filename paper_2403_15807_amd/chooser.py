@@ -249,9 +249,10 @@ def main():
               "heldout_timed_arms": int(np.isfinite(Yh).sum()), "final_train_mse_ln_ms": loss,
               "collect_train_s": round(t_collect, 1), "train_s": round(t_train, 2),
               "collect_heldout_s": round(t_held, 1), "regret": ev, "arms": vrs.num_tiles() * 2,
-              "workload_ranges": {"n": "logU[1e5, 1e7] (d<=128), [1e5, 2e6] (768), [1e5, 1e6] (1536)",
+              "workload_ranges": {"n": "logU[1e5, 1e7] (d<=128), [1e5, 4e6] (768), [1e5, 2e6] (1536)",
                                   "d": list(inputs.CHOOSER_DIMS), "B": "logU-int[1, 4096]",
-                                  "selectivity": "logU[1e-4, 1]", "k": [1, 10, 100],
+                                  "selectivity": "logU[1e-4, 1] (3/4), U[0.3, 1] (1/4)",
+                                  "k": [1, 10, 100],
                                   "dtype": ["f32", "bf16", "fp8"], "metric": "IP (normalised rows)"}}
     with open(args.report, "w") as f:
         json.dump(report, f, indent=1)

@@ -152,13 +152,15 @@ class ChooserWorkload:
 
 
 CHOOSER_DIMS = (64, 128, 768, 1536)
-CHOOSER_MAX_ROWS = {64: 10_000_000, 128: 10_000_000, 768: 2_000_000, 1536: 1_000_000}
+CHOOSER_MAX_ROWS = {64: 10_000_000, 128: 10_000_000, 768: 4_000_000, 1536: 2_000_000}
 
 
 def chooser_workloads(cfg: int, count: int, n_min: int = 100_000, b_max: int = 4096):
     """``count`` workloads: n ~ logU[n_min, max rows for d], d uniform over
-    CHOOSER_DIMS, B ~ logU-integer[1, b_max], selectivity ~ logU[1e-4, 1],
-    k uniform over {1, 10, 100}, storage dtype uniform over {f32, bf16, fp8}."""
+    CHOOSER_DIMS, B ~ logU-integer[1, b_max], selectivity ~ logU[1e-4, 1]
+    with probability 3/4 and U[0.3, 1] otherwise (the dense end, where the
+    masked and gathered scans trade places), k uniform over {1, 10, 100},
+    storage dtype uniform over {f32, bf16, fp8}."""
     g = _rng(cfg, _S_PRED, 7)
     out = []
     for i in range(count):
@@ -167,6 +169,8 @@ def chooser_workloads(cfg: int, count: int, n_min: int = 100_000, b_max: int = 4
         n = int(round(np.exp(g.uniform(np.log(n_min), np.log(n_max)))))
         b = int(min(b_max, max(1, int(np.floor(np.exp(g.uniform(0.0, np.log(b_max + 1))))))))
         sel = float(np.exp(g.uniform(np.log(1e-4), 0.0)))
+        if g.uniform() < 0.25:
+            sel = float(g.uniform(0.3, 1.0))
         k = int((1, 10, 100)[g.integers(0, 3)])
         dtype = int(g.integers(0, 3))
         out.append(ChooserWorkload(n=n, d=d, b=b, sel=sel, k=k, dtype=dtype, seed=int(g.integers(0, 2 ** 31))))
