@@ -87,10 +87,14 @@ def screen_kernel_name(store, used_mfma):
     return "screen_mfma_f32" if store == "f32" else "screen_mfma_bf16"
 
 
-def roofline(n_sel, n, d, B, store, gather, n_terms, screen_ms):
+def roofline(n_sel, n, d, B, store, gather, n_terms, screen_ms, launches=1):
+    """Roofline of the screening kernel.  ``screen_ms`` is its average
+    launch duration; a scan that screens in ``launches`` passes splits one
+    step's algorithmic work over them, so the work per launch is the step's
+    divided by ``launches`` (achieved = step work / step screening time)."""
     row_bytes = d * {"f32": 4, "bf16": 2, "fp8": 1}[store] + (4 if store == "fp8" else 0)
-    bytes_alg = n_sel * row_bytes + (n_sel * 4 if gather else n * 4 * n_terms) + B * d * 4
-    flops_alg = 2.0 * B * n_sel * d
+    bytes_alg = (n_sel * row_bytes + (n_sel * 4 if gather else n * 4 * n_terms) + B * d * 4) / launches
+    flops_alg = 2.0 * B * n_sel * d / launches
     hbm_gbs = bytes_alg / (screen_ms * 1e-3) / 1e9
     tflops = flops_alg / (screen_ms * 1e-3) / 1e12
     mfma_peak = MFMA_F32_PEAK_TFLOPS if store == "f32" else MFMA_BF16_PEAK_TFLOPS
@@ -159,7 +163,7 @@ def bench_scan(args):
     out = (idx, dist, nv, cert)
 
     def step():
-        T.scan_topk(qd, pred, k, metric, strategy=strategy, tile=args.tile, ws=ws, out=out)
+        T.scan_topk(qd, pred, k, metric, strategy=strategy, tile=args.tile, ws=ws, out=out, passes=args.passes)
 
     for _ in range(args.warmup):
         step()
@@ -183,7 +187,9 @@ def bench_scan(args):
     used_gather = stages["select"][1] > 0
     used_mfma = mfma_used(T, vrs, B, pred, k, metric, strategy, args.tile)
     screen_ms = stages["screen"][0] / max(1, stages["screen"][1])
-    roof = roofline(n_sel, n, d, B, args.store, used_gather, len(pred), screen_ms)
+    launches = max(1, round(stages["screen"][1] / args.steps))
+    roof = roofline(n_sel, n, d, B, args.store, used_gather, len(pred), screen_ms, launches)
+    roof["launches_per_step"] = launches
     kname = screen_kernel_name(args.store, used_mfma)
     wkey = f"scan-{n}x{d}-{args.store}-{args.metric}-b{B}-s{args.sel:g}-k{k}-{'gather' if used_gather else 'mask'}"
     tb = traffic_from_profiles(kname, wkey)
@@ -281,11 +287,13 @@ def run_sweep(args, T, T_other, n, d, metric, vrs, torch, dev):
                     stg = vrs.stage_times()
                     gather = stg["select"][1] > 0
                     sms = stg["screen"][0] / max(1, stg["screen"][1])
-                    r = roofline(n_sel, n, d, B, args.store, gather, 2, sms)
+                    nl = max(1, round(stg["screen"][1] / reps))
+                    r = roofline(n_sel, n, d, B, args.store, gather, 2, sms, nl)
                     points.append({"metric": mname, "batch": B, "sel": s, "strategy": sname,
                                    "used": "gather" if gather else "mask",
                                    "qps": round(B * reps / el, 1), "ms": round(el * 1e3 / reps, 4),
-                                   "screen_ms": round(sms, 4), "bound": r["bound"], "frac": r["frac"]})
+                                   "screen_ms": round(sms * nl, 4), "passes": nl,
+                                   "bound": r["bound"], "frac": r["frac"]})
     log(f"sweep: {len(points)} points in {time.time() - t_start:.1f}s")
     return points
 
@@ -464,6 +472,8 @@ def main():
                          "result against the FP64 oracle on the float32 rows (sampled queries)")
     ap.add_argument("--strategy", choices=["auto", "mask", "gather"], default="auto")
     ap.add_argument("--tile", type=int, default=-1)
+    ap.add_argument("--passes", type=int, default=0, choices=[0, 1, 2],
+                    help="MFMA screening passes (0 = planner's choice)")
     ap.add_argument("--cpu-queries", type=int, default=0, help="oracle sample size (0 = #cores, at most 16)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", dest="sweep", action="store_false",

@@ -92,7 +92,12 @@ enum { VRS_CHOOSER_LEARNED = 0, VRS_CHOOSER_HEURISTIC = 1 };
  *                for bfloat16 / FP8 tables), at most 1024.
  *   n_valid:     [B] int32 out: min(k_b, |sigma_theta(R)|), or NULL.
  *   certified:   [B] uint8 out: 1 if the screened candidates provably held the
- *                exact top-k, 0 if the exact FP64 fallback pass ran; or NULL. */
+ *                exact top-k, 0 if the exact FP64 fallback pass ran; or NULL.
+ *   passes:      MFMA screening in one pass (1) or in two (2: a prefix of
+ *                every row chunk, a merge whose K-th key then bounds every
+ *                chunk, the rest of every chunk); 0 = two when a chunk holds
+ *                at least 8192 rows.  Results do not depend on it; streaming
+ *                tiles always use one pass. */
 typedef struct {
     int32_t strategy;
     int32_t tile;
@@ -100,6 +105,7 @@ typedef struct {
     int32_t kprime_mult;
     int32_t *n_valid;
     uint8_t *certified;
+    int32_t passes;
 } vrs_opts;
 
 /* Build a table (the column store of Section 3) from float32 rows.

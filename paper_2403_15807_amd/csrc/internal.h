@@ -101,6 +101,10 @@ struct ScreenArgs {
     uint64_t *heads;               // [B][n_chunks] first key of each list, or null
     uint64_t *cbuf;                // [B][n_chunks][CB] candidate buffers (MFMA kernels)
     uint64_t *gthr;                // [B] smallest K-th key published by any chunk
+    // Two-pass screening (MFMA kernels): pass 1 covers the first
+    // ceil(tiles / 2^prefix_shift) row tiles of every chunk, pass 2 the rest,
+    // continuing pass 1's lists; pass 0 = one pass over everything.
+    int32_t pass, prefix_shift;
     // batched uneven form only (null otherwise): control words written on the
     // device (dense query count, row chunks per dense query, work queues) and
     // the sparse queries' id lists; see BatchCtl.
@@ -111,6 +115,18 @@ struct ScreenArgs {
     const int32_t *sp_pool;
     const int32_t *kps;            // [B] by position: per-query k'
 };
+
+// Rows [c0, c1) of a chunk that this screening pass covers (tiles of br rows).
+__device__ __forceinline__ void pass_range(const ScreenArgs &a, int64_t &c0, int64_t &c1, int br) {
+    if (a.pass == 0) return;
+    const int64_t nt = (c1 - c0 + br - 1) / br;
+    const int64_t tp = (nt + ((int64_t)1 << a.prefix_shift) - 1) >> a.prefix_shift;
+    const int64_t cs = c1 < c0 + tp * br ? c1 : c0 + tp * br;
+    if (a.pass == 1)
+        c1 = cs;
+    else
+        c0 = cs;
+}
 
 // Control words of a batched launch (int32, in the workspace).
 enum BatchCtl {
@@ -294,6 +310,9 @@ struct FinishArgs {
     uint64_t *fb_partials;         // [fb_slots][fb_chunks][kmax][2]
 };
 hipError_t launch_merge(const FinishArgs &a, hipStream_t s);
+// gthr[b] = min(gthr[b], merged[b][K-1]): the K-th smallest key of the merged
+// lists bounds the K-th key of every superset of their rows.
+hipError_t launch_set_bound(const FinishArgs &a, uint64_t *gthr, hipStream_t s);
 hipError_t launch_rerank(const FinishArgs &a, hipStream_t s);
 hipError_t launch_fallback(const FinishArgs &a, hipStream_t s);
 

@@ -504,7 +504,10 @@ __global__ __launch_bounds__(RR_THREADS) void rerank_kernel(FinishArgs a) {
     constexpr int T = RR_THREADS;
     const int s = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int kpb = kp_of(a, b);
-    const int ns = (kpb + RR_ROWS - 1) / RR_ROWS;  // workgroups with candidates of query b
+    // workgroup s takes candidate groups s, s + S, ... (S = gridDim.x); ns of
+    // them have work for query b
+    const int S = gridDim.x;
+    const int ns = min(S, (kpb + RR_ROWS - 1) / RR_ROWS);
     if (s >= ns) return;
     const int ob = a.perm ? a.perm[b] : b;  // the query at position b
     extern __shared__ __align__(16) unsigned char smem[];
@@ -518,62 +521,69 @@ __global__ __launch_bounds__(RR_THREADS) void rerank_kernel(FinishArgs a) {
     const uint64_t *lst = a.merged + (int64_t)b * a.K;
     const int nb16 = a.dp / V;  // 16-byte blocks per row
     const int64_t row_bytes = (int64_t)a.dp * EB;
-    const int ci0 = s * RR_ROWS + wave * RR_WROWS;
-    // candidate rows (a slot without a candidate reads row 0 and drops it)
-    const char *rp[RR_WROWS];
-    int64_t myrow = -1;
+    double *dist = a.rr_dist + (int64_t)b * a.K;
+    for (int g = s; g * RR_ROWS < kpb; g += S) {
+        const int ci0 = g * RR_ROWS + wave * RR_WROWS;
+        // candidate rows (a slot without a candidate reads row 0 and drops it)
+        const char *rp[RR_WROWS];
+        int64_t myrow = -1;
 #pragma unroll
-    for (int r = 0; r < RR_WROWS; ++r) {
-        const int ci = ci0 + r;
-        const uint64_t key = lst[min(ci, kpb - 1)];
-        const int64_t row = (ci < kpb && key != KEY_INF) ? (int64_t)(uint32_t)key : -1;
-        rp[r] = (const char *)a.rows + (row < 0 ? 0 : row) * row_bytes;
-        if (lane == r) myrow = row;
-    }
-    const double sc = (STORE == VRS_FP8E4M3 && myrow >= 0) ? (double)a.scale[myrow] : 1.0;
-    double acc = 0.0;
-    rr_u32x4 w[RR_WROWS];
-    rr_load(w, rp, 0, nb16, lane);
-    for (int c0 = 0; c0 < nb16; c0 += RR_CH) {
-        const int chn = min(RR_CH, nb16 - c0);
-        __syncthreads();  // previous chunk consumed (and, first time, qrow written)
-        if (lane < chn) {
-#pragma unroll
-            for (int r = 0; r < RR_WROWS; ++r) stage[r * (RR_CH + 1) + lane] = w[r];
+        for (int r = 0; r < RR_WROWS; ++r) {
+            const int ci = ci0 + r;
+            const uint64_t key = lst[min(ci, kpb - 1)];
+            const int64_t row = (ci < kpb && key != KEY_INF) ? (int64_t)(uint32_t)key : -1;
+            rp[r] = (const char *)a.rows + (row < 0 ? 0 : row) * row_bytes;
+            if (lane == r) myrow = row;
         }
-        __syncthreads();
-        rr_load(w, rp, c0 + RR_CH, nb16, lane);  // clamped: harmless past the end
-        if (lane < RR_WROWS) {
-            const rr_u32x4 *my = stage + lane * (RR_CH + 1);
-            for (int c = 0; c < chn; ++c) {
-                float x[V];
-                const rr_u32x4 u = my[c];
-                decode16<STORE>(make_uint4(u.x, u.y, u.z, u.w), x);
-                const float *qj = qrow + (c0 + c) * V;
+        const double sc = (STORE == VRS_FP8E4M3 && myrow >= 0) ? (double)a.scale[myrow] : 1.0;
+        double acc = 0.0;
+        rr_u32x4 w[RR_WROWS];
+        rr_load(w, rp, 0, nb16, lane);
+        for (int c0 = 0; c0 < nb16; c0 += RR_CH) {
+            const int chn = min(RR_CH, nb16 - c0);
+            __syncthreads();  // previous chunk consumed (and, first time, qrow written)
+            if (lane < chn) {
 #pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    if (METRIC == VRS_L2SQ) {
-                        const double t = (double)qj[v] - sc * (double)x[v];
-                        acc = fma(t, t, acc);
-                    } else {
-                        acc = fma((double)qj[v], (double)x[v], acc);
+                for (int r = 0; r < RR_WROWS; ++r) stage[r * (RR_CH + 1) + lane] = w[r];
+            }
+            __syncthreads();
+            rr_load(w, rp, c0 + RR_CH, nb16, lane);  // clamped: harmless past the end
+            if (lane < RR_WROWS) {
+                const rr_u32x4 *my = stage + lane * (RR_CH + 1);
+                for (int c = 0; c < chn; ++c) {
+                    float x[V];
+                    const rr_u32x4 u = my[c];
+                    decode16<STORE>(make_uint4(u.x, u.y, u.z, u.w), x);
+                    const float *qj = qrow + (c0 + c) * V;
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        if (METRIC == VRS_L2SQ) {
+                            const double t = (double)qj[v] - sc * (double)x[v];
+                            acc = fma(t, t, acc);
+                        } else {
+                            acc = fma((double)qj[v], (double)x[v], acc);
+                        }
                     }
                 }
             }
         }
+        if (lane < RR_WROWS && myrow >= 0) {
+            if (METRIC == VRS_IP) acc = -(sc * acc);
+            dist[ci0 + lane] = acc;
+        }
     }
-    double *dist = a.rr_dist + (int64_t)b * a.K;
-    if (lane < RR_WROWS && myrow >= 0) {
-        if (METRIC == VRS_IP) acc = -(sc * acc);
-        dist[ci0 + lane] = acc;
+    // arrival: the last workgroup of query b finishes it (a single workgroup
+    // needs no counter and no device-scope fences)
+    if (ns > 1) {
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) last_s = atomicAdd(&a.rr_count[b], 1) == ns - 1;
+        __syncthreads();
+        if (!last_s) return;
+        __threadfence();
+    } else {
+        __syncthreads();  // every wave's distances written
     }
-    // arrival: the last workgroup of query b finishes it
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) last_s = atomicAdd(&a.rr_count[b], 1) == ns - 1;
-    __syncthreads();
-    if (!last_s) return;
-    __threadfence();
 
     // the screening keys are sorted with empty slots last, so the candidates
     // are the first n_cand of them
@@ -731,6 +741,14 @@ __global__ __launch_bounds__(256) void fallback_merge_kernel(FinishArgs a) {
     }
 }
 
+__global__ void set_bound_kernel(const uint64_t *__restrict__ merged, int K, int B,
+                                 uint64_t *__restrict__ gthr) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const uint64_t v = merged[(int64_t)b * K + K - 1];
+    if (v < gthr[b]) gthr[b] = v;
+}
+
 }  // namespace
 
 hipError_t launch_prep_queries(const float *q, int32_t B, int32_t d, int32_t dp, float *qp,
@@ -778,6 +796,11 @@ hipError_t launch_prep_batched(const vrs_pred *preds, const int32_t *ks, int32_t
 
 static int merge_cb(int Kp) { return next_pow2(Kp + MERGE_THREADS * 4) - Kp; }
 
+hipError_t launch_set_bound(const FinishArgs &a, uint64_t *gthr, hipStream_t s) {
+    set_bound_kernel<<<(a.B + 255) / 256, 256, 0, s>>>(a.merged, a.K, a.B, gthr);
+    return hipGetLastError();
+}
+
 hipError_t launch_merge(const FinishArgs &a, hipStream_t s) {
     const int Kp = next_pow2(a.K), CB = merge_cb(Kp);
     const size_t lds = (size_t)std::max(Kp + CB, MERGE_HMAX) * 8 + 8 + 16;
@@ -803,8 +826,12 @@ static hipError_t rerank_t(const FinishArgs &a, hipStream_t s, int kpmax) {
     const size_t lds = (size_t)RR_ROWS * (RR_CH + 1) * 16 + (size_t)((a.dp + 3) & ~3) * 4 +
                        (size_t)2 * ((a.K + 7) & ~7) * sizeof(Key128);
     ensure_dyn_lds((const void *)rerank_kernel<STORE, METRIC>, lds);
-    const int ns = (kpmax + RR_ROWS - 1) / RR_ROWS;
-    rerank_kernel<STORE, METRIC><<<dim3(ns, a.B), RR_THREADS, lds, s>>>(a);
+    // Several workgroups per query when the batch alone cannot fill the GPU
+    // (their rows come from many CUs at once); one per query, with no
+    // arrival counter or device-scope fence, from 256 queries on.
+    const int groups = (kpmax + RR_ROWS - 1) / RR_ROWS;
+    const int S = std::max(1, std::min(groups, (256 + a.B - 1) / a.B));
+    rerank_kernel<STORE, METRIC><<<dim3(S, a.B), RR_THREADS, lds, s>>>(a);
     return hipGetLastError();
 }
 

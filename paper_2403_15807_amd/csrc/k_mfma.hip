@@ -81,21 +81,26 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
     for (int i = lane; i < QW; i += 64) {
         const int q = wave * QW + i;
         cnt[q] = 0;
-        thr[q] = KEY_INF;
         const int qa = q0 + q;
+        // start from the best bound any chunk (or a first pass) has published
+        thr[q] = qa < Bq ? __atomic_load_n((const unsigned long long *)(a.gthr + qa), __ATOMIC_RELAXED)
+                         : KEY_INF;
         qn2[q] = qa < Bq ? a.qn2[qa] : 0.0f;
     }
-    for (int i = lane; i < QW * K; i += 64) {
-        const int qa = q0 + wave * QW + i / K;
-        if (qa < Bq) a.partials[((int64_t)qa * nchunks + chunk) * K + (i % K)] = KEY_INF;
+    if (a.pass != 2) {  // a second pass continues the first pass's lists
+        for (int i = lane; i < QW * K; i += 64) {
+            const int qa = q0 + wave * QW + i / K;
+            if (qa < Bq) a.partials[((int64_t)qa * nchunks + chunk) * K + (i % K)] = KEY_INF;
+        }
     }
     __syncthreads();
 
     const int64_t total = GATHER ? *a.sel_count : a.n;
     int64_t per = (total + nchunks - 1) / nchunks;
     per = (per + BR - 1) / BR * BR;
-    const int64_t c0 = (int64_t)chunk * per;
-    const int64_t c1 = min(total, c0 + per);
+    int64_t c0 = (int64_t)chunk * per;
+    int64_t c1 = min(total, c0 + per);
+    pass_range(a, c0, c1, BR);
     const float *X = (const float *)a.rows;
 
     // Tile pipeline: the row ids of tile t+1 (gather: sid) and the per-row

@@ -90,23 +90,29 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
     const int K = a.K, Kp = a.Kp, CBq = a.CB;
     if (tid < QM) {
         L.cnt[tid] = 0;
-        L.thr[tid] = KEY_INF;
+        // start from the best bound any chunk (or a first pass) has published
+        L.thr[tid] = q0 + tid < Bq
+                         ? __atomic_load_n((const unsigned long long *)(a.gthr + q0 + tid), __ATOMIC_RELAXED)
+                         : KEY_INF;
         if (BATCHED) {
             PredDev p{-1, {0}, {0}, {0}};
             if (q0 + tid < Bq) p = a.preds[q0 + tid];
             L.qrg[tid] = range_form(q0 + tid, p);
         }
     }
-    for (int i = lane; i < QW * K; i += 64) {
-        const int qa = q0 + wave * QW + i / K;
-        if (qa < Bq) a.partials[((int64_t)qa * nchunks + chunk) * K + (i % K)] = KEY_INF;
+    if (a.pass != 2) {  // a second pass continues the first pass's lists
+        for (int i = lane; i < QW * K; i += 64) {
+            const int qa = q0 + wave * QW + i / K;
+            if (qa < Bq) a.partials[((int64_t)qa * nchunks + chunk) * K + (i % K)] = KEY_INF;
+        }
     }
 
     const int64_t total = GATHER ? *a.sel_count : a.n;
     int64_t per = (total + nchunks - 1) / nchunks;
     per = (per + BR - 1) / BR * BR;
-    const int64_t c0 = (int64_t)chunk * per;
-    const int64_t c1 = min(total, c0 + per);
+    int64_t c0 = (int64_t)chunk * per;
+    int64_t c1 = min(total, c0 + per);
+    pass_range(a, c0, c1, BR);
     const int ntile = c1 > c0 ? (int)((c1 - c0 + BR - 1) / BR) : 0;
     const int EB = STORE == VRS_BF16 ? 2 : 1;
     const char *X = (const char *)a.rows;

@@ -64,6 +64,12 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
         int64_t nc = std::max<int64_t>(1, std::min<int64_t>(max_chunks, slots / P.n_qtiles));
         if (nc >= 8) nc = nc / 8 * 8;  // whole XCD groups: a row chunk's query tiles share an L2
         P.n_chunks = (int)nc;
+        // two passes once a chunk holds 8192 rows or more: the first pass
+        // (1/16 of every chunk) then still sees 16 x K rows per query and
+        // chunk for K <= 32 and, across all chunks, far more than K
+        P.prefix_shift = 4;
+        const int passes = opts ? opts->passes : 0;
+        P.two_pass = passes == 2 || (passes != 1 && rows / nc >= 8192);
     } else {
         P.CB = screen_cb(P.Kp);
         P.qt = fit_qt(std::min(cfg.qt, next_pow2(B)), P.Kp, P.CB, t->dp);
@@ -363,16 +369,6 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     sa.shared_rows = P.n_qtiles > 1;
     sa.partials = (uint64_t *)(w + P.o_part);
     sa.heads = P.mfma ? nullptr : (uint64_t *)(w + P.o_heads);
-    prof_begin(2, s);
-    if (!P.mfma)
-        e = launch_screen_stream(sa, P.qt, s);
-    else if (t->store == VRS_F32)
-        e = launch_screen_mfma(sa, P.qt, s);
-    else
-        e = launch_screen_mfma_bf16(sa, s);
-    if (e != hipSuccess) return e;
-    prof_end(2, s);
-
     FinishArgs fa{};
     fa.rows = t->rows;
     fa.scale = t->scale;
@@ -429,6 +425,35 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     fa.fb_chunks = P.fb_chunks;
     fa.fb_slots = B;
     fa.fb_partials = (uint64_t *)(w + P.o_fb);
+    // MFMA kernels keep one bound per query and row chunk, so every chunk
+    // pays for its own list fills.  With long chunks the scan runs in two
+    // passes: a prefix of every chunk, a merge of those lists whose K-th key
+    // bounds the result (K keys are at or below it), then the rest of every
+    // chunk with that bound, continuing the same lists.
+    auto screen = [&]() -> hipError_t {
+        prof_begin(2, s);
+        hipError_t r;
+        if (!P.mfma)
+            r = launch_screen_stream(sa, P.qt, s);
+        else if (t->store == VRS_F32)
+            r = launch_screen_mfma(sa, P.qt, s);
+        else
+            r = launch_screen_mfma_bf16(sa, s);
+        prof_end(2, s);
+        return r;
+    };
+    if (P.two_pass) {
+        sa.pass = 1;
+        sa.prefix_shift = P.prefix_shift;
+        if ((e = screen()) != hipSuccess) return e;
+        prof_begin(3, s);
+        if ((e = launch_merge(fa, s)) != hipSuccess) return e;
+        if ((e = launch_set_bound(fa, gthr, s)) != hipSuccess) return e;
+        prof_end(3, s);
+        sa.pass = 2;
+    }
+    if ((e = screen()) != hipSuccess) return e;
+
     prof_begin(3, s);
     e = launch_merge(fa, s);
     if (e != hipSuccess) return e;

@@ -55,7 +55,8 @@ class vrs_pred(C.Structure):
 
 class vrs_opts(C.Structure):
     _fields_ = [("strategy", C.c_int32), ("tile", C.c_int32), ("chooser", C.c_int32),
-                ("kprime_mult", C.c_int32), ("n_valid", C.c_void_p), ("certified", C.c_void_p)]
+                ("kprime_mult", C.c_int32), ("n_valid", C.c_void_p), ("certified", C.c_void_p),
+                ("passes", C.c_int32)]
 
 
 _lib = None
@@ -247,17 +248,19 @@ class Table:
                                 _stream(stream)))
         return ids[: int(cnt.item())]
 
-    def _opts(self, B, strategy, tile, chooser, kprime_mult, n_valid, certified):
+    def _opts(self, B, strategy, tile, chooser, kprime_mult, n_valid, certified, passes=0):
         o = vrs_opts()
-        o.strategy, o.tile, o.chooser, o.kprime_mult = strategy, tile, chooser, kprime_mult
+        o.strategy, o.tile, o.chooser, o.kprime_mult, o.passes = strategy, tile, chooser, kprime_mult, passes
         o.n_valid = n_valid.data_ptr()
         o.certified = certified.data_ptr()
         return o
 
     def scan_topk(self, q: torch.Tensor, terms, k: int, metric: int = L2SQ, strategy: int = STRATEGY_AUTO,
                   tile: int = -1, chooser: int = CHOOSER_LEARNED, kprime_mult: int = 0,
-                  ws: torch.Tensor | None = None, out: tuple | None = None, stream=None) -> ScanResult:
-        """Filtered exact top-k of the queries ``q`` [B, d] (one predicate)."""
+                  ws: torch.Tensor | None = None, out: tuple | None = None, stream=None,
+                  passes: int = 0) -> ScanResult:
+        """Filtered exact top-k of the queries ``q`` [B, d] (one predicate);
+        ``passes`` forces one- or two-pass MFMA screening (0 = planner's choice)."""
         q = q.contiguous()
         B = q.shape[0]
         if out is None:
@@ -267,7 +270,7 @@ class Table:
             cert = torch.empty(B, dtype=torch.uint8, device="cuda")
         else:
             idx, dist, nv, cert = out
-        o = self._opts(B, strategy, tile, chooser, kprime_mult, nv, cert)
+        o = self._opts(B, strategy, tile, chooser, kprime_mult, nv, cert, passes)
         if ws is None:
             ws = self.workspace(B, k, o)
         p = make_pred(terms)

@@ -38,7 +38,8 @@ def test_exports_every_declared_symbol(L):
 def test_header_struct_layout_matches_binding():
     assert C.sizeof(vrs.vrs_range) == 24
     assert C.sizeof(vrs.vrs_pred) == 8 + 24 * vrs.MAX_TERMS
-    assert C.sizeof(vrs.vrs_opts) == 32
+    assert C.sizeof(vrs.vrs_opts) == 40  # 4 int32, 2 pointers, 1 int32 + tail padding
+    assert vrs.vrs_opts.passes.offset == 32
 
 
 def test_host_side_argument_errors(L):

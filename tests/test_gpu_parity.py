@@ -304,3 +304,28 @@ def test_lowprec_largest_k_prime(B):
     for strategy in (vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER):
         r = T.scan_topk(_dev(q), pred, k, vrs.IP, strategy=strategy)
         _check(r, ref, f"B {B} strategy {strategy}")
+
+
+@pytest.mark.parametrize("store,metric", [(vrs.F32, vrs.L2SQ), (vrs.F32, vrs.IP), (vrs.BF16, vrs.IP),
+                                          (vrs.FP8E4M3, vrs.IP)])
+def test_two_pass_mfma_screening(store, metric):
+    # one and two MFMA screening passes (prefix of every chunk, merged bound,
+    # the rest) give the oracle's result, also when the first pass sees fewer
+    # qualifying rows than k' (dense and very selective predicates, gather)
+    n, d, B = 90001, 128, 150
+    x = inputs.table(7, n, d, 60)
+    a = inputs.attributes(7, n, 2, 10 ** 6)
+    q = inputs.queries(7, B, d, 60)
+    normalize = metric == vrs.IP
+    T = vrs.Table(_dev(x), _dev(a), store=store, normalize=normalize)
+    ot = O.Table.build(x, a, {vrs.F32: O.F32, vrs.BF16: O.BF16, vrs.FP8E4M3: O.FP8}[store], normalize)
+    om = O.L2SQ if metric == vrs.L2SQ else O.IP
+    for sel, k in ((1.0, 100), (0.3, 10), (0.002, 100)):
+        w = inputs.two_term_width(sel, 10 ** 6)
+        pred = [(0, 0, w), (1, 0, w)] if sel < 1.0 else []
+        ref = O.scan_topk(ot, q, pred, k, om)
+        for tile in (4, 7):
+            for strategy in (vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER):
+                for passes in (1, 2):
+                    r = T.scan_topk(_dev(q), pred, k, metric, tile=tile, strategy=strategy, passes=passes)
+                    _check(r, ref, f"store {store} sel {sel} k {k} tile {tile} strategy {strategy} passes {passes}")
