@@ -43,6 +43,7 @@ struct BPlan {
     int nsub;
     int64_t dense_lists, lists;
     int fb_chunks, fb_rows_per_chunk;
+    bool two_pass;  // dense side in two passes (prefix of every chunk, merged bound, rest)
     size_t o_qp, o_qnorm, o_qn2, o_qhl, o_gthr, o_ctl, o_pred_o, o_pred_p, o_qr, o_cands, o_sq, o_kc_o, o_kps_o, o_kc_p,
         o_kps_p, o_cand, o_subcnt, o_tot, o_perm, o_spoff, o_spcnt, o_segpre, o_listoff, o_nlists,
         o_pool, o_part, o_cbuf, o_merged, o_rrdist, o_rrcnt, o_fail, o_failcnt, o_fb, total;
@@ -61,6 +62,8 @@ BPlan make_bplan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, in
     P.sparse_grid = NUM_CU * SPARSE_WG_PER_CU;
     P.items_target = c.rounds * P.dense_grid;
     P.rows_cap = (int64_t)floor(c.cap_frac * (double)t->n);
+    const int passes = opts ? opts->passes : 0;
+    P.two_pass = passes == 2 || (passes != 1 && t->n >= ((int64_t)1 << 20));
     P.nsub = (int)((t->n + BSUB_ROWS - 1) / BSUB_ROWS);
     const int qm = dense_qm(t);
     const int64_t ntiles = (B + qm - 1) / qm;
@@ -250,16 +253,6 @@ hipError_t run_batched(const vrs_table_s *t, const float *q, int B, const vrs_pr
     sa.seg_pre = ba.seg_pre;
     sa.sp_pool = ba.pool;
     sa.kps = kps_p;
-    prof_begin(2, s);
-    e = t->store == VRS_F32 ? launch_screen_mfma_persistent(sa, 64, P.dense_grid, s)
-                            : launch_screen_mfma_bf16_persistent(sa, P.dense_grid, s);
-    if (e != hipSuccess) return e;
-    if (ba.rows_cap > 0) {
-        e = launch_screen_sparse(sa, P.sparse_grid, s);
-        if (e != hipSuccess) return e;
-    }
-    prof_end(2, s);
-
     FinishArgs fa{};
     fa.rows = t->rows;
     fa.scale = t->scale;
@@ -310,6 +303,36 @@ hipError_t run_batched(const vrs_table_s *t, const float *q, int B, const vrs_pr
     fa.fb_chunks = P.fb_chunks;
     fa.fb_slots = B;
     fa.fb_partials = (uint64_t *)(w + P.o_fb);
+    // Dense side in two passes (as in the single-predicate scan): a prefix of
+    // every chunk, a merge of the dense positions' lists whose (k'+1)-th key
+    // then bounds each dense query, the rest of every chunk.
+    auto dense = [&]() -> hipError_t {
+        return t->store == VRS_F32 ? launch_screen_mfma_persistent(sa, 64, P.dense_grid, s)
+                                   : launch_screen_mfma_bf16_persistent(sa, P.dense_grid, s);
+    };
+    prof_begin(2, s);
+    if (P.two_pass) {
+        sa.pass = 1;
+        sa.prefix_shift = 4;
+        if ((e = dense()) != hipSuccess) return e;
+        prof_end(2, s);
+        prof_begin(3, s);
+        fa.merge_limit = ctl + BC_NDENSE;
+        if ((e = launch_merge(fa, s)) != hipSuccess) return e;
+        // the bound, and fresh work queues for the second pass
+        if ((e = launch_set_bound(fa, gthr, ctl + BC_QDENSE, s)) != hipSuccess) return e;
+        fa.merge_limit = nullptr;
+        prof_end(3, s);
+        prof_begin(2, s);
+        sa.pass = 2;
+    }
+    if ((e = dense()) != hipSuccess) return e;
+    if (ba.rows_cap > 0) {
+        e = launch_screen_sparse(sa, P.sparse_grid, s);
+        if (e != hipSuccess) return e;
+    }
+    prof_end(2, s);
+
     prof_begin(3, s);
     e = launch_merge(fa, s);
     if (e != hipSuccess) return e;

@@ -296,6 +296,7 @@ struct FinishArgs {
     const int32_t *perm;           // position -> query index (null: identity)
     uint64_t *merge_mid;           // [B][ceil(n_chunks/2048)][K] (two-level merge)
     uint64_t *merged;              // [B][K]
+    const int32_t *merge_limit;    // positions >= *merge_limit get an empty merged list (or null)
     double *rr_dist;               // [B][K] exact distances of the candidates
     int32_t *rr_count;             // [B] rerank arrival counters (zeroed by the merge)
     double rel, abs_ip, abs_l2, max_norm;  // screening error model
@@ -310,9 +311,10 @@ struct FinishArgs {
     uint64_t *fb_partials;         // [fb_slots][fb_chunks][kmax][2]
 };
 hipError_t launch_merge(const FinishArgs &a, hipStream_t s);
-// gthr[b] = min(gthr[b], merged[b][K-1]): the K-th smallest key of the merged
-// lists bounds the K-th key of every superset of their rows.
-hipError_t launch_set_bound(const FinishArgs &a, uint64_t *gthr, hipStream_t s);
+// gthr[b] = min(gthr[b], merged[b][Kb-1]) with Kb = the query's k'+1: the
+// Kb-th smallest key of the merged lists bounds the Kb-th key of every
+// superset of their rows.  zero8 (or null): 8 counters cleared on the way.
+hipError_t launch_set_bound(const FinishArgs &a, uint64_t *gthr, int32_t *zero8, hipStream_t s);
 hipError_t launch_rerank(const FinishArgs &a, hipStream_t s);
 hipError_t launch_fallback(const FinishArgs &a, hipStream_t s);
 

@@ -212,7 +212,8 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
                                                               const int64_t *__restrict__ list_off,
                                                               const int32_t *__restrict__ nlists,
                                                               const uint64_t *__restrict__ heads,
-                                                              int32_t *__restrict__ rr_count) {
+                                                              int32_t *__restrict__ rr_count,
+                                                              const int32_t *__restrict__ limit) {
     constexpr int T = MERGE_THREADS;
     const int g = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
     if (rr_count && tid == 0) rr_count[b] = 0;  // the rerank's arrival counter
@@ -221,9 +222,9 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
     // form) nlists[b] of them at list_off[b]
     const int nb = nlists ? nlists[b] : n_lists;
     const int64_t first = nlists ? list_off[b] : (int64_t)b * n_lists;
-    const int l0 = g * G, l1 = min(nb, l0 + G), L = l1 - l0;
+    const int l0 = g * G, l1 = min(nb, l0 + G), L = (limit && b >= *limit) ? 0 : l1 - l0;
     uint64_t *out = dst + ((int64_t)b * n_out + g) * K;
-    if (L <= 0) {  // no list: an empty result
+    if (L <= 0) {  // no list (or a position past the limit): an empty result
         for (int i = tid; i < K; i += T) out[i] = KEY_INF;
         return;
     }
@@ -742,10 +743,13 @@ __global__ __launch_bounds__(256) void fallback_merge_kernel(FinishArgs a) {
 }
 
 __global__ void set_bound_kernel(const uint64_t *__restrict__ merged, int K, int B,
-                                 uint64_t *__restrict__ gthr) {
+                                 const int32_t *__restrict__ kps, uint64_t *__restrict__ gthr,
+                                 int32_t *__restrict__ zero8) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (zero8 && b < 8) zero8[b] = 0;
     if (b >= B) return;
-    const uint64_t v = merged[(int64_t)b * K + K - 1];
+    const int kb = kps ? min(K, kps[b] + 1) : K;
+    const uint64_t v = merged[(int64_t)b * K + kb - 1];
     if (v < gthr[b]) gthr[b] = v;
 }
 
@@ -796,8 +800,8 @@ hipError_t launch_prep_batched(const vrs_pred *preds, const int32_t *ks, int32_t
 
 static int merge_cb(int Kp) { return next_pow2(Kp + MERGE_THREADS * 4) - Kp; }
 
-hipError_t launch_set_bound(const FinishArgs &a, uint64_t *gthr, hipStream_t s) {
-    set_bound_kernel<<<(a.B + 255) / 256, 256, 0, s>>>(a.merged, a.K, a.B, gthr);
+hipError_t launch_set_bound(const FinishArgs &a, uint64_t *gthr, int32_t *zero8, hipStream_t s) {
+    set_bound_kernel<<<(std::max(a.B, 8) + 255) / 256, 256, 0, s>>>(a.merged, a.K, a.B, a.kps, gthr, zero8);
     return hipGetLastError();
 }
 
@@ -808,16 +812,18 @@ hipError_t launch_merge(const FinishArgs &a, hipStream_t s) {
     if (a.n_chunks <= G) {
         merge_kernel<<<dim3(1, a.B), MERGE_THREADS, lds, s>>>(a.partials, a.n_chunks, G, a.K, Kp,
                                                              CB, a.merged, 1, a.list_off, a.nlists,
-                                                             a.heads, a.rr_count);
+                                                             a.heads, a.rr_count, a.merge_limit);
         return hipGetLastError();
     }
     // two levels: groups of G lists, then the group results
     const int ng = (a.n_chunks + G - 1) / G;
     uint64_t *mid = a.merge_mid;
     merge_kernel<<<dim3(ng, a.B), MERGE_THREADS, lds, s>>>(a.partials, a.n_chunks, G, a.K, Kp, CB,
-                                                          mid, ng, a.list_off, a.nlists, a.heads, nullptr);
+                                                          mid, ng, a.list_off, a.nlists, a.heads, nullptr,
+                                                          a.merge_limit);
     merge_kernel<<<dim3(1, a.B), MERGE_THREADS, lds, s>>>(mid, ng, ng, a.K, Kp, CB, a.merged, 1,
-                                                         nullptr, nullptr, nullptr, a.rr_count);
+                                                         nullptr, nullptr, nullptr, a.rr_count,
+                                                         a.merge_limit);
     return hipGetLastError();
 }
 

@@ -243,7 +243,7 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
                 full &= full - 1;
                 const int q = wave * QW + j, qa = q0 + q;
                 const int64_t base = (int64_t)qa * nchunks + chunk;
-                flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, cnt[q], K, Kp, &thr[q],
+                flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, cnt[q], list_len(a, qa, K), Kp, &thr[q],
                                a.gthr + qa);
                 if (lane == 0) cnt[q] = 0;
             }
@@ -259,7 +259,7 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
         pend &= pend - 1;
         const int q = wave * QW + j, qa = q0 + q;
         const int64_t base = (int64_t)qa * nchunks + chunk;
-        flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, cnt[q], K, Kp, &thr[q],
+        flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, cnt[q], list_len(a, qa, K), Kp, &thr[q],
                        a.gthr + qa);
     }
 }

@@ -317,7 +317,7 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
                 full &= full - 1;
                 const int q = wave * QW + j, qa = q0 + q;
                 const int64_t base = (int64_t)qa * nchunks + chunk;
-                flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, L.cnt[q], K, Kp, &L.thr[q],
+                flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, L.cnt[q], list_len(a, qa, K), Kp, &L.thr[q],
                                a.gthr + qa);
                 if (lane == 0) L.cnt[q] = 0;
             }
@@ -331,7 +331,7 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
         pend &= pend - 1;
         const int q = wave * QW + j, qa = q0 + q;
         const int64_t base = (int64_t)qa * nchunks + chunk;
-        flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, L.cnt[q], K, Kp, &L.thr[q],
+        flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, L.cnt[q], list_len(a, qa, K), Kp, &L.thr[q],
                        a.gthr + qa);
     }
 }

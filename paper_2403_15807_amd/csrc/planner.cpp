@@ -448,7 +448,7 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
         if ((e = screen()) != hipSuccess) return e;
         prof_begin(3, s);
         if ((e = launch_merge(fa, s)) != hipSuccess) return e;
-        if ((e = launch_set_bound(fa, gthr, s)) != hipSuccess) return e;
+        if ((e = launch_set_bound(fa, gthr, nullptr, s)) != hipSuccess) return e;
         prof_end(3, s);
         sa.pass = 2;
     }

@@ -8,6 +8,13 @@
 
 namespace vrs {
 
+// Keys a query keeps per list: its own k'+1 in the batched uneven form
+// (lists are K = max k'+1 long, the tail stays KEY_INF), else K.  A shorter
+// list gives the query its own, tighter admission bound.
+__device__ __forceinline__ int list_len(const ScreenArgs &a, int qa, int K) {
+    return a.kps ? min(K, a.kps[qa] + 1) : K;
+}
+
 // Merge the append buffer of one query into its sorted list (one wave).
 template <int E>
 __device__ inline void flush_one(uint64_t *list, const uint64_t *buf, int n, int K, int Kp,

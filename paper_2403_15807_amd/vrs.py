@@ -284,7 +284,7 @@ class Table:
                                                  None if opts is None else C.byref(opts), C.byref(out)))
         return out.value
 
-    def _batched_args(self, q, k_max, metric, tile, kprime_mult, ws, out):
+    def _batched_args(self, q, k_max, metric, tile, kprime_mult, ws, out, passes=0):
         q = q.contiguous()
         B = q.shape[0]
         if out is None:
@@ -293,7 +293,7 @@ class Table:
                    torch.empty(B, dtype=torch.int32, device="cuda"),
                    torch.empty(B, dtype=torch.uint8, device="cuda"))
         idx, dist, nv, cert = out
-        o = self._opts(B, STRATEGY_MASK, tile, CHOOSER_HEURISTIC, kprime_mult, nv, cert)
+        o = self._opts(B, STRATEGY_MASK, tile, CHOOSER_HEURISTIC, kprime_mult, nv, cert, passes)
         if ws is None:
             ws = torch.empty(max(self.batched_workspace_bytes(B, k_max, metric, o), 256), dtype=torch.uint8,
                              device="cuda")
@@ -302,10 +302,12 @@ class Table:
     def scan_topk_batched(self, q: torch.Tensor, preds: torch.Tensor, ks: torch.Tensor, k_max: int,
                           metric: int = IP, tile: int = -1, kprime_mult: int = 0,
                           ws: torch.Tensor | None = None, out: tuple | None = None,
-                          stream=None) -> ScanResult:
+                          stream=None, passes: int = 0) -> ScanResult:
         """Per-query predicates (``preds_tensor``) and k (int32 device tensor).
-        ``tile`` is a batched configuration index (-1: tuned or default)."""
-        q, B, o, ws, (idx, dist, nv, cert) = self._batched_args(q, k_max, metric, tile, kprime_mult, ws, out)
+        ``tile`` is a batched configuration index (-1: tuned or default);
+        ``passes`` forces one- or two-pass dense screening (0 = by table size)."""
+        q, B, o, ws, (idx, dist, nv, cert) = self._batched_args(q, k_max, metric, tile, kprime_mult, ws, out,
+                                                                passes)
         _check(lib().vrs_scan_topk_batched(self._h, _ptr(q), B, _ptr(preds), _ptr(ks), k_max, metric,
                                            _ptr(idx), _ptr(dist), _ptr(ws), ws.numel(), C.byref(o),
                                            _stream(stream)))

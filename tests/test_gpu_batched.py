@@ -73,8 +73,9 @@ def test_batched_every_config_matches_oracle(store, metric, d):
     ref = O.scan_topk(ot, q, oracle_preds, kref, O.L2SQ if metric == vrs.L2SQ else O.IP, out_stride=kmax)
     pd, kd, qd = vrs.preds_tensor(preds), _dev(ks), _dev(q)
     for cfg in range(vrs.batched_num_configs()):
-        r = T.scan_topk_batched(qd, pd, kd, kmax, metric, tile=cfg)
-        _check(r, ref, f"store {store} metric {metric} config {cfg}")
+        for passes in (1, 2):
+            r = T.scan_topk_batched(qd, pd, kd, kmax, metric, tile=cfg, passes=passes)
+            _check(r, ref, f"store {store} metric {metric} config {cfg} passes {passes}")
 
 
 def test_batched_k_prime_one_forces_fallback_and_stays_exact():
