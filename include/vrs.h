@@ -96,7 +96,7 @@ enum { VRS_CHOOSER_LEARNED = 0, VRS_CHOOSER_HEURISTIC = 1 };
  *   passes:      MFMA screening in one pass (1) or in two (2: a prefix of
  *                every row chunk, a merge whose K-th key then bounds every
  *                chunk, the rest of every chunk); 0 = two when a chunk holds
- *                at least 8192 rows.  Results do not depend on it; streaming
+ *                at least 2048 rows.  Results do not depend on it; streaming
  *                tiles always use one pass. */
 typedef struct {
     int32_t strategy;

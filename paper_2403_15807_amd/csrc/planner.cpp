@@ -64,12 +64,12 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
         int64_t nc = std::max<int64_t>(1, std::min<int64_t>(max_chunks, slots / P.n_qtiles));
         if (nc >= 8) nc = nc / 8 * 8;  // whole XCD groups: a row chunk's query tiles share an L2
         P.n_chunks = (int)nc;
-        // two passes once a chunk holds 8192 rows or more: the first pass
-        // (1/16 of every chunk) then still sees 16 x K rows per query and
-        // chunk for K <= 32 and, across all chunks, far more than K
+        // two passes once a chunk holds 2048 rows or more (the first pass
+        // covers 1/16 of every chunk's tiles, at least one; the extra merge
+        // costs tens of microseconds)
         P.prefix_shift = 4;
         const int passes = opts ? opts->passes : 0;
-        P.two_pass = passes == 2 || (passes != 1 && rows / nc >= 8192);
+        P.two_pass = passes == 2 || (passes != 1 && rows / nc >= 2048);
     } else {
         P.CB = screen_cb(P.Kp);
         P.qt = fit_qt(std::min(cfg.qt, next_pow2(B)), P.Kp, P.CB, t->dp);
