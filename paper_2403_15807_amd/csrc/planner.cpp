@@ -267,12 +267,18 @@ void plan_decide(const vrs_table_s *t, int B, const PredDev &p, bool batched, in
         bool any_mfma = false;
         for (int tile = 0; tile < kNumTiles; ++tile)
             if (kTiles[tile].kind == 1 && tile_ok(t, B, k, opts, tile, metric)) any_mfma = true;
+        // When the predicate keeps (almost) every row, the gathered scan can
+        // skip nothing and still pays the selection pass and the id reads:
+        // only masked arms are offered (the network has seen few such
+        // workloads and can misjudge the small margin).
+        const bool dense = est_sel >= 0.9;
         bool allowed[2 * kNumTiles];
         for (int sidx = 0; sidx < 2; ++sidx)
             for (int tile = 0; tile < kNumTiles; ++tile) {
                 const int st = sidx + 1;
                 bool ok = tile_ok(t, B, k, opts, tile, metric);
                 if (want_s != VRS_STRATEGY_AUTO && st != want_s) ok = false;
+                if (want_s == VRS_STRATEGY_AUTO && dense && st == VRS_STRATEGY_GATHER) ok = false;
                 if (batched && st != VRS_STRATEGY_MASK) ok = false;
                 if (want_t >= 0 && tile != want_t) ok = false;
                 if (want_t < 0 && any_mfma && kTiles[tile].kind == 0 &&
