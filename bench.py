@@ -301,7 +301,7 @@ def run_sweep(args, T, T_other, n, d, metric, vrs, torch, dev):
 def cpu_baseline_scan(args, x, attr, q, pred, k, metric, B, idx, vrs):
     import oracle as O
     cores = len(os.sched_getaffinity(0))
-    nq = args.cpu_queries or min(cores, 16)
+    nq = args.cpu_queries or min(3 * cores, 48)  # about 10-20 s of oracle work
     ot = O.Table.build(x, attr, {"f32": O.F32, "bf16": O.BF16, "fp8": O.FP8}[args.store],
                        normalize=(metric == vrs.IP))
     qs = np.ascontiguousarray(q[np.arange(nq) % B])
@@ -474,7 +474,8 @@ def main():
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--passes", type=int, default=0, choices=[0, 1, 2],
                     help="MFMA screening passes (0 = planner's choice)")
-    ap.add_argument("--cpu-queries", type=int, default=0, help="oracle sample size (0 = #cores, at most 16)")
+    ap.add_argument("--cpu-queries", type=int, default=0,
+                    help="oracle sample size (0 = 3 x #cores, at most 48, for the scan form)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", dest="sweep", action="store_false",
                     help="skip the batch x selectivity x strategy sweep")
