@@ -70,6 +70,10 @@ typedef struct {
 
 #define VRS_MAX_TERMS 4
 
+/* Largest query batch B of one call (queries are a grid dimension of the
+ * merge and rerank launches); larger batches are VRS_E_ARG. */
+#define VRS_MAX_BATCH 65535
+
 /* A conjunction of nterms range terms; nterms == 0 selects every row. */
 typedef struct {
     int32_t nterms;

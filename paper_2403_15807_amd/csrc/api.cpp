@@ -313,7 +313,7 @@ vrs_status vrs_chooser_clear(void) {
 vrs_status vrs_plan(vrs_table t, int32_t B, const vrs_pred *pred, int32_t k, vrs_metric metric,
                     const vrs_opts *opts, float *features, int32_t *strategy, int32_t *tile) {
     if (!t) return fail(VRS_E_ARG, "table is NULL");
-    if (B < 1 || k < 1 || k > 256) return fail(VRS_E_ARG, "bad B or k");
+    if (B < 1 || B > VRS_MAX_BATCH || k < 1 || k > 256) return fail(VRS_E_ARG, "bad B or k");
     PredDev p;
     vrs_status st = fold_pred(pred, t->n_attr, &p);
     if (st != VRS_OK) return st;
@@ -365,7 +365,7 @@ vrs_status vrs_mlp_adam(float *params, const float *grad, float *m, float *v, in
 vrs_status vrs_scan_workspace_bytes(vrs_table t, int32_t B, int32_t k_max, const vrs_opts *opts,
                                     size_t *bytes) {
     if (!t || !bytes) return fail(VRS_E_ARG, "NULL argument");
-    if (B < 1) return fail(VRS_E_ARG, "B=%d < 1", B);
+    if (B < 1 || B > VRS_MAX_BATCH) return fail(VRS_E_ARG, "B=%d outside [1, %d]", B, VRS_MAX_BATCH);
     if (k_max < 1 || k_max > 256) return fail(VRS_E_ARG, "k=%d outside [1, 256]", k_max);
     *bytes = plan_workspace(t, B, k_max, opts);
     return ok();
@@ -378,7 +378,7 @@ static vrs_status scan_common(vrs_table t, const float *q, int32_t B, const vrs_
     if (!t) return fail(VRS_E_ARG, "table is NULL");
     if (!q) return fail(VRS_E_ARG, "queries are NULL");
     if (!out_idx || !out_dist) return fail(VRS_E_ARG, "outputs are NULL");
-    if (B < 1) return fail(VRS_E_ARG, "B=%d < 1", B);
+    if (B < 1 || B > VRS_MAX_BATCH) return fail(VRS_E_ARG, "B=%d outside [1, %d]", B, VRS_MAX_BATCH);
     if (k < 1 || k > 256) return fail(VRS_E_ARG, "k=%d outside [1, 256]", k);
     if (metric != VRS_L2SQ && metric != VRS_IP) return fail(VRS_E_ARG, "unknown metric %d", (int)metric);
     if (metric == VRS_L2SQ && t->store != VRS_F32)
@@ -430,7 +430,7 @@ static vrs_status batched_check(vrs_table t, const float *q, int32_t B, const vr
     if (!t) return fail(VRS_E_ARG, "table is NULL");
     if (!q || !preds || !ks) return fail(VRS_E_ARG, "queries, preds or ks is NULL");
     if (!out_idx || !out_dist) return fail(VRS_E_ARG, "outputs are NULL");
-    if (B < 1) return fail(VRS_E_ARG, "B=%d < 1", B);
+    if (B < 1 || B > VRS_MAX_BATCH) return fail(VRS_E_ARG, "B=%d outside [1, %d]", B, VRS_MAX_BATCH);
     if (k_max < 1 || k_max > 256) return fail(VRS_E_ARG, "k_max=%d outside [1, 256]", k_max);
     if (metric != VRS_L2SQ && metric != VRS_IP) return fail(VRS_E_ARG, "unknown metric %d", (int)metric);
     if (metric == VRS_L2SQ && t->store != VRS_F32)
@@ -477,7 +477,7 @@ vrs_status vrs_scan_topk_batched(vrs_table t, const float *q, int32_t B, const v
 vrs_status vrs_batched_workspace_bytes(vrs_table t, int32_t B, int32_t k_max, vrs_metric metric,
                                        const vrs_opts *opts, size_t *bytes) {
     if (!t || !bytes) return fail(VRS_E_ARG, "NULL argument");
-    if (B < 1) return fail(VRS_E_ARG, "B=%d < 1", B);
+    if (B < 1 || B > VRS_MAX_BATCH) return fail(VRS_E_ARG, "B=%d outside [1, %d]", B, VRS_MAX_BATCH);
     if (k_max < 1 || k_max > 256) return fail(VRS_E_ARG, "k_max=%d outside [1, 256]", k_max);
     if (metric != VRS_L2SQ && metric != VRS_IP) return fail(VRS_E_ARG, "unknown metric %d", (int)metric);
     *bytes = batched_bytes(t, B, k_max, metric, opts);

@@ -24,6 +24,7 @@ F32, BF16, FP8E4M3 = 0, 1, 2
 STRATEGY_AUTO, STRATEGY_MASK, STRATEGY_GATHER = 0, 1, 2
 CHOOSER_LEARNED, CHOOSER_HEURISTIC = 0, 1
 MAX_TERMS = 4
+MAX_BATCH = 65535  # largest B of one call (VRS_MAX_BATCH)
 
 EXPORTS = [
     "vrs_build_table", "vrs_destroy_table", "vrs_table_info", "vrs_table_export",

@@ -329,3 +329,12 @@ def test_two_pass_mfma_screening(store, metric):
                 for passes in (1, 2):
                     r = T.scan_topk(_dev(q), pred, k, metric, tile=tile, strategy=strategy, passes=passes)
                     _check(r, ref, f"store {store} sel {sel} k {k} tile {tile} strategy {strategy} passes {passes}")
+
+
+def test_batch_limit_is_an_argument_error(cfg0):
+    T = cfg0[3]
+    assert T.workspace_bytes(vrs.MAX_BATCH, 10) > 0
+    with pytest.raises(vrs.VrsError):
+        T.workspace_bytes(vrs.MAX_BATCH + 1, 10)
+    with pytest.raises(vrs.VrsError):
+        T.batched_workspace_bytes(vrs.MAX_BATCH + 1, 10)
