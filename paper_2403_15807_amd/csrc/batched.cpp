@@ -57,7 +57,7 @@ BPlan make_bplan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, in
     P.K = P.kprime + 1;
     P.Kp = next_pow2(P.K);
     P.CB = mfma_cb(P.Kp);
-    P.occ = t->store == VRS_F32 ? screen_mfma_occupancy(P.Kp, P.CB, 64) : 2;
+    P.occ = t->store == VRS_F32 ? screen_mfma_occupancy(P.Kp, P.CB, 64) : 1;
     P.dense_grid = NUM_CU * P.occ;
     P.sparse_grid = NUM_CU * SPARSE_WG_PER_CU;
     P.items_target = c.rounds * P.dense_grid;

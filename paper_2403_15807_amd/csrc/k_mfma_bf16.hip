@@ -10,9 +10,10 @@
 // The screening distance therefore differs from the exact one by less than
 // (gamma_dp + 2^-16 + ...) |q| max|x|, which the rerank's certificate uses.
 //
-// Workgroup = 4 waves x 32 queries (two 16-query MFMA blocks per wave) = 128
+// Workgroup = 8 waves x 32 queries (two 16-query MFMA blocks per wave) = 256
 // queries against one chunk of rows, rows in tiles of 128, coordinates in
-// chunks of 64.  Only the rows go through LDS (double-buffered: the next
+// chunks of 64 (a batch of up to 256 queries reads every row once; at 256
+// VGPRs per lane one such workgroup fills a CU).  Only the rows go through LDS (double-buffered: the next
 // chunk's loads are in flight while the current one is multiplied, one
 // barrier per chunk); the query parts are read straight into registers
 // from a fragment-ordered copy made by the query preparation (one 1 KB
@@ -31,7 +32,9 @@ typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
 
 constexpr int QW = 32;          // queries per wave
-constexpr int QM = 4 * QW;      // queries per workgroup
+constexpr int NWAVE = 8;        // waves per workgroup
+constexpr int NT = 64 * NWAVE;  // threads per workgroup
+constexpr int QM = NWAVE * QW;  // queries per workgroup
 constexpr int BR = 128;         // rows per tile
 constexpr int NB = BR / 16;     // 16-row MFMA blocks per tile
 constexpr int KC = 64;          // coordinates per chunk (two k-steps of 32)
@@ -81,7 +84,9 @@ __device__ __forceinline__ Lds carve(unsigned char *smem) {
 template <int STORE, bool GATHER, bool BATCHED, int E>
 __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, const int nchunks,
                                           const int q0, const int Bq, unsigned char *smem) {
-    constexpr int XLD = STORE == VRS_BF16 ? 4 : 2;  // 16-byte row loads per thread per chunk
+    // 16-byte row loads per thread per chunk (BR rows x KC coordinates over NT threads)
+    constexpr int XLD = BR * KC * (STORE == VRS_BF16 ? 2 : 1) / (16 * NT);
+    static_assert(XLD >= 1, "a chunk must give every thread a load");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int dp = a.dp;
     const int nkc = dp / KC, nks = dp / 32;
@@ -177,7 +182,7 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
         int rr[XLD];
 #pragma unroll
         for (int i = 0; i < XLD; ++i) {
-            const int r = STORE == VRS_BF16 ? (tid + 256 * i) >> 3 : (tid + 256 * i) >> 2;
+            const int r = STORE == VRS_BF16 ? (tid + NT * i) >> 3 : (tid + NT * i) >> 2;
             rr[i] = L.rid[slot * BR + r];
             xm[i] = 0u - (uint32_t)(L.rok[slot * BR + r] != 0);
         }
@@ -185,7 +190,7 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
         // the loads are unconditional; unwanted rows are zeroed at commit
 #pragma unroll
         for (int i = 0; i < XLD; ++i) {
-            const int cc = STORE == VRS_BF16 ? (tid + 256 * i) & 7 : (tid + 256 * i) & 3;
+            const int cc = STORE == VRS_BF16 ? (tid + NT * i) & 7 : (tid + NT * i) & 3;
             xr[i] = *(const uint4 *)(X + (int64_t)rr[i] * row_bytes + kc * KC * EB + cc * 16);
         }
     };
@@ -194,7 +199,7 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
 #pragma unroll
         for (int i = 0; i < XLD; ++i) {
             xr[i] = make_uint4(xr[i].x & xm[i], xr[i].y & xm[i], xr[i].z & xm[i], xr[i].w & xm[i]);
-            const int idx = tid + 256 * i;
+            const int idx = tid + NT * i;
             if (STORE == VRS_BF16) {
                 *(uint4 *)(xb + (idx >> 3) * LDK + (idx & 7) * 8) = xr[i];
             } else {
@@ -337,7 +342,7 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
 }
 
 template <int STORE, bool GATHER, bool BATCHED, int E>
-__global__ __launch_bounds__(256, 2) void screen_mfma_bf16_kernel(ScreenArgs a) {
+__global__ __launch_bounds__(NT) void screen_mfma_bf16_kernel(ScreenArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     bf16_tile<STORE, GATHER, BATCHED, E>(a, blockIdx.x, a.n_chunks, blockIdx.y * QM, a.B, smem);
 }
@@ -350,7 +355,7 @@ __global__ __launch_bounds__(256, 2) void screen_mfma_bf16_kernel(ScreenArgs a) 
 // one XCD and read its rows through the same L2.  An empty queue sends the
 // workgroup to the other XCDs' queues.
 template <int STORE, int E>
-__global__ __launch_bounds__(256, 2) void screen_mfma_bf16_persistent(ScreenArgs a) {
+__global__ __launch_bounds__(NT) void screen_mfma_bf16_persistent(ScreenArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int item_s;
     const int Bq = a.bctl[BC_NDENSE], nc = a.bctl[BC_NC];
@@ -385,7 +390,7 @@ __global__ __launch_bounds__(256, 2) void screen_mfma_bf16_persistent(ScreenArgs
 
 template <int STORE, int E>
 hipError_t launch_se(const ScreenArgs &a, hipStream_t s) {
-    dim3 grid(a.n_chunks, (a.B + QM - 1) / QM), block(256);
+    dim3 grid(a.n_chunks, (a.B + QM - 1) / QM), block(NT);
     const size_t lds = screen_mfma_bf16_lds();
     if (a.preds) {
         auto k = screen_mfma_bf16_kernel<STORE, false, true, E>;
@@ -418,7 +423,7 @@ hipError_t launch_pe(const ScreenArgs &a, int grid, hipStream_t s) {
     const size_t lds = screen_mfma_bf16_lds();
     auto k = screen_mfma_bf16_persistent<STORE, E>;
     ensure_dyn_lds((const void *)k, lds);
-    k<<<grid, 256, lds, s>>>(a);
+    k<<<grid, NT, lds, s>>>(a);
     return hipGetLastError();
 }
 

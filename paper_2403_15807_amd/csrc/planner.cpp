@@ -57,7 +57,7 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
         P.CB = mfma_cb(P.Kp);
         P.qt = t->store == VRS_F32 ? cfg.qt : screen_mfma_bf16_qm();
         P.n_qtiles = (B + P.qt - 1) / P.qt;
-        const int occ = t->store == VRS_F32 ? screen_mfma_occupancy(P.Kp, P.CB, P.qt) : 2;
+        const int occ = t->store == VRS_F32 ? screen_mfma_occupancy(P.Kp, P.CB, P.qt) : 1;
         const int64_t slots = (int64_t)256 * occ * cfg.wg_target / 4;
         const int64_t rows = est_rows < 0 ? t->n : std::max<int64_t>(est_rows, 1);
         int64_t max_chunks = std::max<int64_t>(1, rows / 1024);
