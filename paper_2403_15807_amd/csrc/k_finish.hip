@@ -97,13 +97,22 @@ __device__ __forceinline__ void decode16<VRS_BF16>(const uint4 &w, float *x) {
         x[2 * i + 1] = __uint_as_float(v[i] & 0xffff0000u);
     }
 }
+// An e4m3fn code's 7 magnitude bits, placed as the top of an f32 exponent
+// and mantissa field (a normal or subnormal f32), times 2^(127-7) give its
+// value exactly: normal codes stay normal, subnormal codes m * 2^-9 come
+// from subnormal f32 inputs, which these kernels keep (FP32 denormals are
+// not flushed).  Four instructions instead of a branch on the exponent.
+__device__ __forceinline__ float e4m3_value(uint32_t c) {
+    const float mag = __uint_as_float((c & 0x7fu) << 20) * 0x1p120f;
+    return __uint_as_float(__float_as_uint(mag) | ((c & 0x80u) << 24));
+}
 template <>
 __device__ __forceinline__ void decode16<VRS_FP8E4M3>(const uint4 &w, float *x) {
     const uint32_t v[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) x[4 * i + j] = e4m3_to_f32((v[i] >> (8 * j)) & 0xffu);
+        for (int j = 0; j < 4; ++j) x[4 * i + j] = e4m3_value((v[i] >> (8 * j)) & 0xffu);
 }
 
 template <int STORE, int METRIC>

@@ -338,3 +338,26 @@ def test_batch_limit_is_an_argument_error(cfg0):
         T.workspace_bytes(vrs.MAX_BATCH + 1, 10)
     with pytest.raises(vrs.VrsError):
         T.batched_workspace_bytes(vrs.MAX_BATCH + 1, 10)
+
+
+def test_fp8_subnormal_codes_rerank_exactly():
+    # one large coordinate per row sets the row scale (max|x| / 448), so the
+    # small coordinates encode to subnormal e4m3 codes (|x| / scale < 2^-6):
+    # screening, rerank and fallback must still reproduce the oracle's FP64
+    # distances of the stored codes bit for bit
+    rng = np.random.default_rng(11)
+    n, d, B = 6000, 64, 9
+    x = (rng.standard_normal((n, d)) * 1e-5).astype(np.float32)
+    x[np.arange(n), rng.integers(0, d, n)] = rng.uniform(0.5, 2.0, n).astype(np.float32)
+    a = inputs.attributes(3, n, 1, 1000)
+    q = rng.standard_normal((B, d)).astype(np.float32)
+    T = vrs.Table(_dev(x), _dev(a), store=vrs.FP8E4M3)
+    ot = O.Table.build(x, a, O.FP8, False)
+    mag = T.export()[0].cpu().numpy() & 0x7F
+    assert ((mag > 0) & (mag < 8)).sum() > n  # plenty of subnormal codes
+    for k in (1, 50):
+        ref = O.scan_topk(ot, q, [], k, O.IP)
+        for strategy in (vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER):
+            for kp in (0, 1):  # k' = k forces the exact fallback pass too
+                r = T.scan_topk(_dev(q), [], k, vrs.IP, strategy=strategy, kprime_mult=kp)
+                _check(r, ref, f"k {k} strategy {strategy} kprime_mult {kp}")
