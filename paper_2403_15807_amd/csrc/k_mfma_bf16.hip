@@ -41,12 +41,20 @@ constexpr int KC = 64;          // coordinates per chunk (two k-steps of 32)
 constexpr int LDK = 72;         // LDS row stride in bfloat16 elements (144 bytes)
 constexpr int SLOTS = 3;        // rotating row-record slots
 
+// An e4m3fn code's value as an f32: its 7 magnitude bits placed as the top
+// of an f32 exponent and mantissa field, times 2^(127-7) (exact for normal
+// codes, and for subnormal ones since FP32 denormals are kept).  Every e4m3
+// value has at most 4 significant bits, so its f32 has a zero low half and
+// the high half is the exact bfloat16.
+__device__ __forceinline__ uint32_t e4m3_f32_bits(uint32_t c) {
+    return __float_as_uint(__uint_as_float((c & 0x7fu) << 20) * 0x1p120f) | ((c & 0x80u) << 24);
+}
+
 // 4 e4m3fn codes -> 4 bfloat16 (exact), packed in two 32-bit words.
 __device__ __forceinline__ uint2 e4m3x4_to_bf16x4(uint32_t w) {
-    uint32_t h[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) h[j] = __float_as_uint(e4m3_to_f32((w >> (8 * j)) & 0xffu)) >> 16;
-    return make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+    const uint32_t f0 = e4m3_f32_bits(w & 0xffu), f1 = e4m3_f32_bits((w >> 8) & 0xffu);
+    const uint32_t f2 = e4m3_f32_bits((w >> 16) & 0xffu), f3 = e4m3_f32_bits(w >> 24);
+    return make_uint2((f0 >> 16) | (f1 & 0xffff0000u), (f2 >> 16) | (f3 & 0xffff0000u));
 }
 
 __device__ __forceinline__ bf8v as_bf8(const uint4 &u) {
