@@ -41,7 +41,9 @@ int fit_qt(int qt, int Kp, int CB, int dp) {
 
 // est_rows: rows the screening kernel is expected to visit (the qualifying
 // rows for gather, every row for mask); bounds the number of row chunks so
-// that a workgroup always has enough rows to amortise its top-k state.
+// that a workgroup always has enough rows to amortise its top-k state.  It
+// is clamped to the table's rows: the workspace is sized for est_rows = n,
+// and a plan must never need more chunks than that sizing assumed.
 Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int tile,
                int strategy, int64_t est_rows = -1) {
     Plan P{};
@@ -59,7 +61,7 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
         P.n_qtiles = (B + P.qt - 1) / P.qt;
         const int occ = t->store == VRS_F32 ? screen_mfma_occupancy(P.Kp, P.CB, P.qt) : 1;
         const int64_t slots = (int64_t)256 * occ * cfg.wg_target / 4;
-        const int64_t rows = est_rows < 0 ? t->n : std::max<int64_t>(est_rows, 1);
+        const int64_t rows = est_rows < 0 ? t->n : std::min<int64_t>(std::max<int64_t>(est_rows, 1), t->n);
         int64_t max_chunks = std::max<int64_t>(1, rows / 1024);
         int64_t nc = std::max<int64_t>(1, std::min<int64_t>(max_chunks, slots / P.n_qtiles));
         if (nc >= 8) nc = nc / 8 * 8;  // whole XCD groups: a row chunk's query tiles share an L2
@@ -318,6 +320,9 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     const int64_t est_rows =
         strategy == VRS_STRATEGY_GATHER ? (int64_t)(est_sel * (double)t->n * 1.25) + 4096 : t->n;
     Plan P = make_plan(t, B, k, opts, tile, strategy, est_rows);
+    // the caller's workspace holds plan_workspace() bytes: a plan larger than
+    // that is refused rather than run past the end of the buffer
+    if (P.total > plan_workspace(t, B, k, opts)) return hipErrorInvalidValue;
     char *w = (char *)ws;
     float *qp = (float *)(w + P.o_qp);
     double *qnorm = (double *)(w + P.o_qnorm);

@@ -361,3 +361,26 @@ def test_fp8_subnormal_codes_rerank_exactly():
             for kp in (0, 1):  # k' = k forces the exact fallback pass too
                 r = T.scan_topk(_dev(q), [], k, vrs.IP, strategy=strategy, kprime_mult=kp)
                 _check(r, ref, f"k {k} strategy {strategy} kprime_mult {kp}")
+
+
+@pytest.mark.parametrize("store", [vrs.F32, vrs.BF16])
+def test_dense_gather_plan_fits_its_workspace(store):
+    # gather at a high estimated selectivity: the planner's row estimate
+    # (1.25 x the estimated qualifying rows) exceeds the table, and its chunk
+    # count must still fit the workspace sized for the whole table; the
+    # workspace here is exactly the advertised size
+    n, d, B, k = 40000, 128, 8, 100
+    x = inputs.table(4, n, d, 100)
+    a = inputs.attributes(4, n, 2, 10 ** 6)
+    q = inputs.queries(4, B, d, 100)
+    T = vrs.Table(_dev(x), _dev(a), store=store, normalize=True)
+    ot = O.Table.build(x, a, {vrs.F32: O.F32, vrs.BF16: O.BF16}[store], True)
+    w = inputs.two_term_width(0.9, 10 ** 6)
+    pred = [(0, 0, w), (1, 0, w)]
+    ref = O.scan_topk(ot, q, pred, k, O.IP)
+    for tile in (4, 5, 6, 7):
+        o = vrs.vrs_opts()
+        o.strategy, o.tile = vrs.STRATEGY_GATHER, tile
+        ws = torch.empty(T.workspace_bytes(B, k, o), dtype=torch.uint8, device="cuda")
+        r = T.scan_topk(_dev(q), pred, k, vrs.IP, strategy=vrs.STRATEGY_GATHER, tile=tile, ws=ws)
+        _check(r, ref, f"store {store} tile {tile}")
