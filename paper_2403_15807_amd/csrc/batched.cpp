@@ -43,7 +43,7 @@ struct BPlan {
     int nsub;
     int64_t dense_lists, lists;
     int fb_chunks, fb_rows_per_chunk;
-    bool two_pass;  // dense side in two passes (prefix of every chunk, merged bound, rest)
+    bool two_pass;  // dense side in two passes (prefix of every chunk, merged bound, all rows)
     size_t o_qp, o_qnorm, o_qn2, o_qhl, o_gthr, o_ctl, o_pred_o, o_pred_p, o_qr, o_cands, o_sq, o_kc_o, o_kps_o, o_kc_p,
         o_kps_p, o_cand, o_subcnt, o_tot, o_perm, o_spoff, o_spcnt, o_segpre, o_listoff, o_nlists,
         o_pool, o_part, o_cbuf, o_merged, o_rrdist, o_rrcnt, o_fail, o_failcnt, o_fb, total;
@@ -305,7 +305,7 @@ hipError_t run_batched(const vrs_table_s *t, const float *q, int B, const vrs_pr
     fa.fb_partials = (uint64_t *)(w + P.o_fb);
     // Dense side in two passes (as in the single-predicate scan): a prefix of
     // every chunk, a merge of the dense positions' lists whose (k'+1)-th key
-    // then bounds each dense query, the rest of every chunk.
+    // then bounds each dense query, every chunk in full with fresh lists.
     auto dense = [&]() -> hipError_t {
         return t->store == VRS_F32 ? launch_screen_mfma_persistent(sa, 64, P.dense_grid, s)
                                    : launch_screen_mfma_bf16_persistent(sa, P.dense_grid, s);
@@ -313,7 +313,8 @@ hipError_t run_batched(const vrs_table_s *t, const float *q, int B, const vrs_pr
     prof_begin(2, s);
     if (P.two_pass) {
         sa.pass = 1;
-        sa.prefix_shift = 4;
+        // a dense query keeps more than cap_frac of the rows (at least 1/1024)
+        sa.prefix_sel = (float)std::max(kCfgs[cfg].cap_frac, 1.0 / 1024);
         if ((e = dense()) != hipSuccess) return e;
         prof_end(2, s);
         prof_begin(3, s);

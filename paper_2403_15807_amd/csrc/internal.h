@@ -101,10 +101,13 @@ struct ScreenArgs {
     uint64_t *heads;               // [B][n_chunks] first key of each list, or null
     uint64_t *cbuf;                // [B][n_chunks][CB] candidate buffers (MFMA kernels)
     uint64_t *gthr;                // [B] smallest K-th key published by any chunk
-    // Two-pass screening (MFMA kernels): pass 1 covers the first
-    // ceil(tiles / 2^prefix_shift) row tiles of every chunk, pass 2 the rest,
-    // continuing pass 1's lists; pass 0 = one pass over everything.
-    int32_t pass, prefix_shift;
+    // Two-pass screening (MFMA kernels): pass 1 covers the first tiles of
+    // every chunk (a sample whose merged K-th key bounds the result), pass 2
+    // all of every chunk again with fresh lists, admitting keys below that
+    // bound; pass 0 = one pass over everything.  prefix_sel: the fraction of
+    // the visited rows expected to qualify (1 with a selection vector).
+    int32_t pass;
+    float prefix_sel;
     // batched uneven form only (null otherwise): control words written on the
     // device (dense query count, row chunks per dense query, work queues) and
     // the sparse queries' id lists; see BatchCtl.
@@ -116,16 +119,20 @@ struct ScreenArgs {
     const int32_t *kps;            // [B] by position: per-query k'
 };
 
-// Rows [c0, c1) of a chunk that this screening pass covers (tiles of br rows).
-__device__ __forceinline__ void pass_range(const ScreenArgs &a, int64_t &c0, int64_t &c1, int br) {
-    if (a.pass == 0) return;
+// Rows [c0, c1) of a chunk (one of nchunks) that this screening pass covers
+// (tiles of br rows).  The first pass screens a prefix of every chunk sized
+// so that the K-th smallest key of all prefixes leaves about 64 keys per
+// list for the second pass (a sample of K * rows / 64 / nchunks rows) and
+// holds 2K qualifying rows, between one tile and an eighth of the chunk.
+__device__ __forceinline__ void pass_range(const ScreenArgs &a, int64_t &c0, int64_t &c1, int br,
+                                           int64_t total, int nchunks) {
+    if (a.pass != 1 || c1 <= c0) return;
     const int64_t nt = (c1 - c0 + br - 1) / br;
-    const int64_t tp = (nt + ((int64_t)1 << a.prefix_shift) - 1) >> a.prefix_shift;
-    const int64_t cs = c1 < c0 + tp * br ? c1 : c0 + tp * br;
-    if (a.pass == 1)
-        c1 = cs;
-    else
-        c0 = cs;
+    const double per_list = (double)a.K * (double)total / (64.0 * nchunks * (double)nchunks);
+    const double qual = 2.0 * a.K / ((double)nchunks * fmax((double)a.prefix_sel, 1e-3));
+    int64_t tp = (int64_t)ceil(fmax(per_list, qual) / br);
+    tp = max((int64_t)1, min(tp, nt / 8));
+    c1 = min(c1, c0 + tp * br);
 }
 
 // Control words of a batched launch (int32, in the workspace).
@@ -311,9 +318,10 @@ struct FinishArgs {
     uint64_t *fb_partials;         // [fb_slots][fb_chunks][kmax][2]
 };
 hipError_t launch_merge(const FinishArgs &a, hipStream_t s);
-// gthr[b] = min(gthr[b], merged[b][Kb-1]) with Kb = the query's k'+1: the
-// Kb-th smallest key of the merged lists bounds the Kb-th key of every
-// superset of their rows.  zero8 (or null): 8 counters cleared on the way.
+// gthr[b] = merged[b][Kb-1] + 1 with Kb = the query's k'+1: the Kb-th
+// smallest key of the merged lists bounds the Kb-th key of every superset of
+// their rows, and a pass that admits keys below gthr then keeps that key too.
+// zero8 (or null): 8 counters cleared on the way.
 hipError_t launch_set_bound(const FinishArgs &a, uint64_t *gthr, int32_t *zero8, hipStream_t s);
 hipError_t launch_rerank(const FinishArgs &a, hipStream_t s);
 hipError_t launch_fallback(const FinishArgs &a, hipStream_t s);

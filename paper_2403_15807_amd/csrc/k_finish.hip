@@ -759,7 +759,10 @@ __global__ void set_bound_kernel(const uint64_t *__restrict__ merged, int K, int
     if (b >= B) return;
     const int kb = kps ? min(K, kps[b] + 1) : K;
     const uint64_t v = merged[(int64_t)b * K + kb - 1];
-    if (v < gthr[b]) gthr[b] = v;
+    // the next pass rebuilds its lists from empty and admits keys strictly
+    // below the bound, so the bound is the key after v (v itself must come
+    // back); bounds the first pass's lists published are all at or above v
+    gthr[b] = v == KEY_INF ? KEY_INF : v + 1;
 }
 
 }  // namespace

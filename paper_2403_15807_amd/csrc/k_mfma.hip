@@ -59,11 +59,12 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
     int *rq = rid + BR;                                          // [BR] qualifies
     float *xn2 = (float *)(rq + BR);                             // [BR]
     float *qn2 = xn2 + BR;                                       // [QM]
-    int *cnt = (int *)(qn2 + QM);                                // [QM]
-    uint64_t *thr = (uint64_t *)(((uintptr_t)(cnt + QM) + 7) & ~(uintptr_t)7);  // [QM]
+    int *cnt = (int *)(qn2 + QM);                                // [QM] keys in the append buffer
+    int *fill = cnt + QM;                                        // [QM] keys in the list
+    uint64_t *thr = (uint64_t *)(((uintptr_t)(fill + QM) + 7) & ~(uintptr_t)7);  // [QM]
     PredDev *qpred = (PredDev *)(thr + QM);                      // [QM] (batched form)
 
-    const int K = a.K, Kp = a.Kp, CBq = a.CB;
+    const int K = a.K, CBq = a.CB;
 
     // A fragments: lane (m = lane % 16, kq = lane / 16) of wave w holds, for
     // block mb, query q0 + QW*w + 16*mb + m at coordinates 16t + 4kq + c.
@@ -81,17 +82,12 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
     for (int i = lane; i < QW; i += 64) {
         const int q = wave * QW + i;
         cnt[q] = 0;
+        fill[q] = 0;
         const int qa = q0 + q;
         // start from the best bound any chunk (or a first pass) has published
         thr[q] = qa < Bq ? __atomic_load_n((const unsigned long long *)(a.gthr + qa), __ATOMIC_RELAXED)
                          : KEY_INF;
         qn2[q] = qa < Bq ? a.qn2[qa] : 0.0f;
-    }
-    if (a.pass != 2) {  // a second pass continues the first pass's lists
-        for (int i = lane; i < QW * K; i += 64) {
-            const int qa = q0 + wave * QW + i / K;
-            if (qa < Bq) a.partials[((int64_t)qa * nchunks + chunk) * K + (i % K)] = KEY_INF;
-        }
     }
     __syncthreads();
 
@@ -100,7 +96,7 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
     per = (per + BR - 1) / BR * BR;
     int64_t c0 = (int64_t)chunk * per;
     int64_t c1 = min(total, c0 + per);
-    pass_range(a, c0, c1, BR);
+    pass_range(a, c0, c1, BR, total, nchunks);
     const float *X = (const float *)a.rows;
 
     // Tile pipeline: the row ids of tile t+1 (gather: sid) and the per-row
@@ -243,9 +239,12 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
                 full &= full - 1;
                 const int q = wave * QW + j, qa = q0 + q;
                 const int64_t base = (int64_t)qa * nchunks + chunk;
-                flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, cnt[q], list_len(a, qa, K), Kp, &thr[q],
-                               a.gthr + qa);
-                if (lane == 0) cnt[q] = 0;
+                const int nq = cnt[q], fq = fill[q], Kq = list_len(a, qa, K);
+                flush_fit<E>(a.partials + base * K, a.cbuf + base * CBq, nq, Kq, fq, &thr[q], a.gthr + qa);
+                if (lane == 0) {
+                    cnt[q] = 0;
+                    fill[q] = min(Kq, fq + nq);
+                }
             }
         }
         __syncthreads();  // the LDS tile is reused
@@ -259,8 +258,15 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
         pend &= pend - 1;
         const int q = wave * QW + j, qa = q0 + q;
         const int64_t base = (int64_t)qa * nchunks + chunk;
-        flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, cnt[q], list_len(a, qa, K), Kp, &thr[q],
-                       a.gthr + qa);
+        const int nq = cnt[q], fq = fill[q], Kq = list_len(a, qa, K);
+        flush_fit<E>(a.partials + base * K, a.cbuf + base * CBq, nq, Kq, fq, &thr[q], a.gthr + qa);
+        if (lane == 0) fill[q] = min(Kq, fq + nq);
+    }
+    // the list entries past each query's keys (the whole list length K)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    for (int j = 0; j < QW; ++j) {
+        const int q = wave * QW + j, qa = q0 + q;
+        if (qa < Bq) list_tail_inf(a.partials + ((int64_t)qa * nchunks + chunk) * K, fill[q], K);
     }
 }
 
@@ -354,7 +360,7 @@ hipError_t launch_m(const ScreenArgs &a, hipStream_t s) {
 }  // namespace
 
 size_t screen_mfma_lds(int dp, int qm) {
-    return (size_t)BR * (dp + 4) * 4 + BR * 12 + qm * 8 + 8 + qm * 8 + qm * sizeof(PredDev) + 16;
+    return (size_t)BR * (dp + 4) * 4 + BR * 12 + qm * 12 + 8 + qm * 8 + qm * sizeof(PredDev) + 16;
 }
 
 // Resident workgroups per CU (register budget of the kernel, set by E and MB).

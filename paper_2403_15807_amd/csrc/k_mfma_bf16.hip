@@ -69,7 +69,8 @@ struct Lds {
     int *rok;          // [SLOTS][BR] row exists (and, shared predicate, qualifies)
     float *rsc;        // [SLOTS][BR] FP8 row scale
     uint32_t *pm;      // [SLOTS][BR][QM/32] per-query predicates: query q qualifies row r
-    int *cnt;          // [QM]
+    int *cnt;          // [QM] keys in the append buffer
+    int *fill;         // [QM] keys in the list (its first entries)
     uint64_t *thr;     // [QM]
     QRange *qrg;       // [QM] per-query predicates (range form)
 };
@@ -82,7 +83,8 @@ __device__ __forceinline__ Lds carve(unsigned char *smem) {
     L.rsc = (float *)(L.rok + SLOTS * BR);
     L.pm = (uint32_t *)(L.rsc + SLOTS * BR);
     L.cnt = (int *)(L.pm + SLOTS * BR * (QM / 32));
-    L.thr = (uint64_t *)(L.cnt + QM);
+    L.fill = L.cnt + QM;
+    L.thr = (uint64_t *)(L.fill + QM);
     L.qrg = (QRange *)(L.thr + QM);
     return L;
 }
@@ -100,9 +102,10 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
     const int nkc = dp / KC, nks = dp / 32;
     const Lds L = carve(smem);
 
-    const int K = a.K, Kp = a.Kp, CBq = a.CB;
+    const int K = a.K, CBq = a.CB;
     if (tid < QM) {
         L.cnt[tid] = 0;
+        L.fill[tid] = 0;
         // start from the best bound any chunk (or a first pass) has published
         L.thr[tid] = q0 + tid < Bq
                          ? __atomic_load_n((const unsigned long long *)(a.gthr + q0 + tid), __ATOMIC_RELAXED)
@@ -113,19 +116,14 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
             L.qrg[tid] = range_form(q0 + tid, p);
         }
     }
-    if (a.pass != 2) {  // a second pass continues the first pass's lists
-        for (int i = lane; i < QW * K; i += 64) {
-            const int qa = q0 + wave * QW + i / K;
-            if (qa < Bq) a.partials[((int64_t)qa * nchunks + chunk) * K + (i % K)] = KEY_INF;
-        }
-    }
+    __syncthreads();  // per-query state is written by other waves than its owner's
 
     const int64_t total = GATHER ? *a.sel_count : a.n;
     int64_t per = (total + nchunks - 1) / nchunks;
     per = (per + BR - 1) / BR * BR;
     int64_t c0 = (int64_t)chunk * per;
     int64_t c1 = min(total, c0 + per);
-    pass_range(a, c0, c1, BR);
+    pass_range(a, c0, c1, BR, total, nchunks);
     const int ntile = c1 > c0 ? (int)((c1 - c0 + BR - 1) / BR) : 0;
     const int EB = STORE == VRS_BF16 ? 2 : 1;
     const char *X = (const char *)a.rows;
@@ -226,7 +224,6 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
     // chunk's rows, then the next chunk's first k-step of query fragments.
     uint4 A0[2][2], A1[2][2];
     if (nch > 0) {
-        if (BATCHED) __syncthreads();  // query ranges are in LDS
         rowinfo(0);
         __syncthreads();
         issue(0);
@@ -330,9 +327,12 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
                 full &= full - 1;
                 const int q = wave * QW + j, qa = q0 + q;
                 const int64_t base = (int64_t)qa * nchunks + chunk;
-                flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, L.cnt[q], list_len(a, qa, K), Kp, &L.thr[q],
-                               a.gthr + qa);
-                if (lane == 0) L.cnt[q] = 0;
+                const int nq = L.cnt[q], fq = L.fill[q], Kq = list_len(a, qa, K);
+                flush_fit<E>(a.partials + base * K, a.cbuf + base * CBq, nq, Kq, fq, &L.thr[q], a.gthr + qa);
+                if (lane == 0) {
+                    L.cnt[q] = 0;
+                    L.fill[q] = min(Kq, fq + nq);
+                }
             }
         }
     }
@@ -344,8 +344,15 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
         pend &= pend - 1;
         const int q = wave * QW + j, qa = q0 + q;
         const int64_t base = (int64_t)qa * nchunks + chunk;
-        flush_query<E>(a.partials + base * K, a.cbuf + base * CBq, L.cnt[q], list_len(a, qa, K), Kp, &L.thr[q],
-                       a.gthr + qa);
+        const int nq = L.cnt[q], fq = L.fill[q], Kq = list_len(a, qa, K);
+        flush_fit<E>(a.partials + base * K, a.cbuf + base * CBq, nq, Kq, fq, &L.thr[q], a.gthr + qa);
+        if (lane == 0) L.fill[q] = min(Kq, fq + nq);
+    }
+    // the list entries past each query's keys (the whole list length K)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    for (int j = 0; j < QW; ++j) {
+        const int q = wave * QW + j, qa = q0 + q;
+        if (qa < Bq) list_tail_inf(a.partials + ((int64_t)qa * nchunks + chunk) * K, L.fill[q], K);
     }
 }
 
@@ -449,7 +456,7 @@ hipError_t launch_p(const ScreenArgs &a, int grid, hipStream_t s) {
 
 size_t screen_mfma_bf16_lds() {
     return (size_t)2 * BR * LDK * 2 + (size_t)3 * SLOTS * BR * 4 + (size_t)SLOTS * BR * (QM / 32) * 4 +
-           QM * 4 + QM * 8 + QM * sizeof(QRange) + 16;
+           QM * 4 * 2 + QM * 8 + QM * sizeof(QRange) + 16;
 }
 
 int screen_mfma_bf16_qm() { return QM; }

@@ -67,9 +67,8 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
         if (nc >= 8) nc = nc / 8 * 8;  // whole XCD groups: a row chunk's query tiles share an L2
         P.n_chunks = (int)nc;
         // two passes once a chunk holds 2048 rows or more (the first pass
-        // covers 1/16 of every chunk's tiles, at least one; the extra merge
-        // costs tens of microseconds)
-        P.prefix_shift = 4;
+        // screens a short prefix of every chunk; the extra merge costs tens
+        // of microseconds)
         const int passes = opts ? opts->passes : 0;
         P.two_pass = passes == 2 || (passes != 1 && rows / nc >= 2048);
     } else {
@@ -365,6 +364,9 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     sa.sel_ids = sel;
     sa.sel_count = selcnt;
     sa.gather = gather;
+    // qualifying fraction of the rows a chunk visits (per-query predicates:
+    // not known here, taken low so the first pass samples enough rows)
+    sa.prefix_sel = gather ? 1.0f : (batched ? 0.01f : (float)std::max(est_sel, 1e-3));
     sa.qp = qp;
     sa.qn2 = qn2;
     sa.qhl = qhl;
@@ -438,9 +440,9 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     fa.fb_partials = (uint64_t *)(w + P.o_fb);
     // MFMA kernels keep one bound per query and row chunk, so every chunk
     // pays for its own list fills.  With long chunks the scan runs in two
-    // passes: a prefix of every chunk, a merge of those lists whose K-th key
-    // bounds the result (K keys are at or below it), then the rest of every
-    // chunk with that bound, continuing the same lists.
+    // passes: a short prefix of every chunk, a merge of those lists whose
+    // K-th key bounds the result (K keys are at or below it), then every
+    // chunk in full with fresh lists that admit only keys up to that bound.
     auto screen = [&]() -> hipError_t {
         prof_begin(2, s);
         hipError_t r;
@@ -455,7 +457,6 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     };
     if (P.two_pass) {
         sa.pass = 1;
-        sa.prefix_shift = P.prefix_shift;
         if ((e = screen()) != hipSuccess) return e;
         prof_begin(3, s);
         if ((e = launch_merge(fa, s)) != hipSuccess) return e;
