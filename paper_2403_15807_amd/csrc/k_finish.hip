@@ -394,29 +394,25 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
 }
 
 // ----------------------------------------------------------------- rerank
-// Workgroup (s, b) holds candidates [s*RR_ROWS, (s+1)*RR_ROWS) of query b's
-// first k' screening keys, RR_WROWS per wave.  A wave stages its rows through
-// LDS in column chunks of RR_CH 16-byte blocks (one coalesced load per row
-// per chunk, the next chunk in flight while the current one is summed), and
-// its lane r runs the exact FP64 formula over candidate r in coordinate
-// order.  Spreading one query's candidates over several workgroups puts
-// several CUs' load queues on the scattered rows.  The last workgroup of a
-// query to finish (an arrival counter, zeroed by the final merge level)
+// Workgroup s of query b takes rounds g = s, s + S, ... of RR_ROWS of the
+// query's first k' screening keys, RR_WROWS candidates per wave.  Lane c of
+// a wave loads the 16-byte blocks c, c + 64, ... of each of its wave's rows
+// (one coalesced load per row and 64 blocks, RR_NW windows of them in flight)
+// and accumulates the exact FP64 formula over its blocks' coordinates for
+// every row; a butterfly over the 64 lanes then sums the partial sums (the
+// same association in every lane, so the value is fixed by the inputs).
+// Spreading one query's candidates over several workgroups (small batches)
+// puts several CUs' load queues on the scattered rows.  The last workgroup
+// of a query to finish (an arrival counter, zeroed by the final merge level)
 // ranks the candidates by exact distance, checks the certificate and writes
 // the result.
 constexpr int RR_WROWS = 8;
-constexpr int RR_THREADS = 256;
+constexpr int RR_THREADS = 512;
 constexpr int RR_ROWS = RR_WROWS * (RR_THREADS / 64);
-constexpr int RR_CH = 64;
+constexpr int RR_NW = 2;
+// k' <= 1024 = 2 RR_THREADS: the candidate sort holds at most two keys per thread
+static_assert(2 * RR_THREADS >= 1024, "rerank sort width");
 typedef unsigned int rr_u32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ void rr_load(rr_u32x4 (&w)[RR_WROWS],
-                                        const char *const (&rp)[RR_WROWS], int c0, int nb16,
-                                        int lane) {
-    const int c = min(c0 + lane, nb16 - 1);
-#pragma unroll
-    for (int r = 0; r < RR_WROWS; ++r) w[r] = *(const rr_u32x4 *)(rp[r] + (int64_t)c * 16);
-}
 
 __device__ __forceinline__ bool k128_less(uint64_t ah, uint32_t al, uint64_t bh, uint32_t bl) {
     return ah < bh || (ah == bh && al < bl);
@@ -521,66 +517,85 @@ __global__ __launch_bounds__(RR_THREADS) void rerank_kernel(FinishArgs a) {
     if (s >= ns) return;
     const int ob = a.perm ? a.perm[b] : b;  // the query at position b
     extern __shared__ __align__(16) unsigned char smem[];
-    rr_u32x4 *stage = (rr_u32x4 *)smem + wave * RR_WROWS * (RR_CH + 1);  // [RR_WROWS][RR_CH + 1]
-    float *qrow = (float *)((rr_u32x4 *)smem + (T / 64) * RR_WROWS * (RR_CH + 1));  // [dp]
+    // exchange buffers of the sort, the query, the candidates, the result
+    uint64_t *xh = (uint64_t *)smem;                       // [2T]
+    uint32_t *xl = (uint32_t *)(xh + 2 * T);               // [2T]
+    float *qrow = (float *)(xl + 2 * T);                   // [dp]
     Key128 *cand = (Key128 *)(qrow + ((a.dp + 3) & ~3));  // [round8(k')] (last workgroup)
     Key128 *srt = cand + ((a.K + 7) & ~7);                 // [k] in exact order
     __shared__ int last_s, n_cand_s;
     for (int j = tid; j < a.dp; j += T) qrow[j] = j < a.d ? a.q[(int64_t)ob * a.d + j] : 0.0f;
     if (tid == 0) n_cand_s = 0;
+    __syncthreads();
     const uint64_t *lst = a.merged + (int64_t)b * a.K;
     const int nb16 = a.dp / V;  // 16-byte blocks per row
     const int64_t row_bytes = (int64_t)a.dp * EB;
     double *dist = a.rr_dist + (int64_t)b * a.K;
     for (int g = s; g * RR_ROWS < kpb; g += S) {
         const int ci0 = g * RR_ROWS + wave * RR_WROWS;
+        if (ci0 >= kpb) break;  // (waves are independent here)
         // candidate rows (a slot without a candidate reads row 0 and drops it)
         const char *rp[RR_WROWS];
-        int64_t myrow = -1;
+        double sc[RR_WROWS];
+        bool has[RR_WROWS];
 #pragma unroll
         for (int r = 0; r < RR_WROWS; ++r) {
             const int ci = ci0 + r;
             const uint64_t key = lst[min(ci, kpb - 1)];
             const int64_t row = (ci < kpb && key != KEY_INF) ? (int64_t)(uint32_t)key : -1;
             rp[r] = (const char *)a.rows + (row < 0 ? 0 : row) * row_bytes;
-            if (lane == r) myrow = row;
+            has[r] = row >= 0;
+            sc[r] = (STORE == VRS_FP8E4M3 && row >= 0) ? (double)a.scale[row] : 1.0;
         }
-        const double sc = (STORE == VRS_FP8E4M3 && myrow >= 0) ? (double)a.scale[myrow] : 1.0;
-        double acc = 0.0;
-        rr_u32x4 w[RR_WROWS];
-        rr_load(w, rp, 0, nb16, lane);
-        for (int c0 = 0; c0 < nb16; c0 += RR_CH) {
-            const int chn = min(RR_CH, nb16 - c0);
-            __syncthreads();  // previous chunk consumed (and, first time, qrow written)
-            if (lane < chn) {
+        double acc[RR_WROWS];
 #pragma unroll
-                for (int r = 0; r < RR_WROWS; ++r) stage[r * (RR_CH + 1) + lane] = w[r];
+        for (int r = 0; r < RR_WROWS; ++r) acc[r] = 0.0;
+        for (int c0 = 0; c0 < nb16; c0 += 64 * RR_NW) {
+            rr_u32x4 w[RR_NW][RR_WROWS];
+#pragma unroll
+            for (int k = 0; k < RR_NW; ++k) {
+                if (c0 + 64 * k >= nb16) break;  // (the same for the whole wave)
+                const int c = min(c0 + 64 * k + lane, nb16 - 1);  // past the row: rereads its last block
+#pragma unroll
+                for (int r = 0; r < RR_WROWS; ++r) w[k][r] = *(const rr_u32x4 *)(rp[r] + (int64_t)c * 16);
             }
-            __syncthreads();
-            rr_load(w, rp, c0 + RR_CH, nb16, lane);  // clamped: harmless past the end
-            if (lane < RR_WROWS) {
-                const rr_u32x4 *my = stage + lane * (RR_CH + 1);
-                for (int c = 0; c < chn; ++c) {
+#pragma unroll
+            for (int k = 0; k < RR_NW; ++k) {
+                const int c = c0 + 64 * k + lane;
+                if (c >= nb16) break;
+                double qd[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) qd[v] = (double)qrow[c * V + v];
+#pragma unroll
+                for (int r = 0; r < RR_WROWS; ++r) {
                     float x[V];
-                    const rr_u32x4 u = my[c];
-                    decode16<STORE>(make_uint4(u.x, u.y, u.z, u.w), x);
-                    const float *qj = qrow + (c0 + c) * V;
+                    decode16<STORE>(make_uint4(w[k][r].x, w[k][r].y, w[k][r].z, w[k][r].w), x);
 #pragma unroll
                     for (int v = 0; v < V; ++v) {
                         if (METRIC == VRS_L2SQ) {
-                            const double t = (double)qj[v] - sc * (double)x[v];
-                            acc = fma(t, t, acc);
+                            const double t = qd[v] - sc[r] * (double)x[v];
+                            acc[r] = fma(t, t, acc[r]);
                         } else {
-                            acc = fma((double)qj[v], (double)x[v], acc);
+                            acc[r] = fma(qd[v], (double)x[v], acc[r]);
                         }
                     }
                 }
             }
         }
-        if (lane < RR_WROWS && myrow >= 0) {
-            if (METRIC == VRS_IP) acc = -(sc * acc);
-            dist[ci0 + lane] = acc;
-        }
+#pragma unroll
+        for (int r = 0; r < RR_WROWS; ++r)
+#pragma unroll
+            for (int m = 32; m > 0; m >>= 1) acc[r] += __shfl_xor(acc[r], m);
+        double mine = 0.0, msc = 1.0;
+        bool mhas = false;
+#pragma unroll
+        for (int r = 0; r < RR_WROWS; ++r)
+            if (lane == r) {
+                mine = acc[r];
+                msc = sc[r];
+                mhas = has[r];
+            }
+        if (lane < RR_WROWS && mhas) dist[ci0 + lane] = METRIC == VRS_IP ? -(msc * mine) : mine;
     }
     // arrival: the last workgroup of query b finishes it (a single workgroup
     // needs no counter and no device-scope fences)
@@ -610,15 +625,10 @@ __global__ __launch_bounds__(RR_THREADS) void rerank_kernel(FinishArgs a) {
     if (valid) atomicAdd(&n_cand_s, valid);
     __syncthreads();
     const int n_cand = n_cand_s;
-    // exchange buffers of the sort: the row staging area, free by now
-    uint64_t *xh = (uint64_t *)smem;
-    uint32_t *xl = (uint32_t *)(xh + 4 * T);
     if (n_cand <= T)
         rr_sort<1>(cand, n_cand, kb, srt, xh, xl);
-    else if (n_cand <= 2 * T)
-        rr_sort<2>(cand, n_cand, kb, srt, xh, xl);
     else
-        rr_sort<4>(cand, n_cand, kb, srt, xh, xl);
+        rr_sort<2>(cand, n_cand, kb, srt, xh, xl);
     __syncthreads();
     bool ok = true;
     const uint64_t akey = lst[kpb];  // (k'+1)-th smallest screening key
@@ -841,7 +851,7 @@ hipError_t launch_merge(const FinishArgs &a, hipStream_t s) {
 
 template <int STORE, int METRIC>
 static hipError_t rerank_t(const FinishArgs &a, hipStream_t s, int kpmax) {
-    const size_t lds = (size_t)RR_ROWS * (RR_CH + 1) * 16 + (size_t)((a.dp + 3) & ~3) * 4 +
+    const size_t lds = (size_t)2 * RR_THREADS * 12 + (size_t)((a.dp + 3) & ~3) * 4 +
                        (size_t)2 * ((a.K + 7) & ~7) * sizeof(Key128);
     ensure_dyn_lds((const void *)rerank_kernel<STORE, METRIC>, lds);
     // Several workgroups per query when the batch alone cannot fill the GPU
