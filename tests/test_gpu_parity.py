@@ -331,6 +331,32 @@ def test_two_pass_mfma_screening(store, metric):
                     _check(r, ref, f"store {store} sel {sel} k {k} tile {tile} strategy {strategy} passes {passes}")
 
 
+@pytest.mark.parametrize("store, metric", [(vrs.F32, vrs.L2SQ), (vrs.BF16, vrs.IP)])
+def test_two_pass_bound_inside_a_run_of_ties(store, metric):
+    # every vector appears 8 times (scattered over the table) and the
+    # queries are table vectors, so the (k'+1)-th screening key sits inside
+    # a run of equal distances: the second pass admits keys up to and
+    # including the first pass's bound key (distance, then row id) and
+    # must reproduce the oracle's ids exactly with one and two passes
+    rng = np.random.default_rng(23)
+    base = inputs.table(9, 20000, 128, 40)
+    perm = rng.permutation(8 * 20000)
+    x = np.ascontiguousarray(np.tile(base, (8, 1))[perm])
+    n = x.shape[0]
+    a = inputs.attributes(9, n, 2, 10 ** 6)
+    q = np.ascontiguousarray(base[rng.integers(0, 20000, 40)])
+    normalize = metric == vrs.IP
+    T = vrs.Table(_dev(x), _dev(a), store=store, normalize=normalize)
+    ot = O.Table.build(x, a, {vrs.F32: O.F32, vrs.BF16: O.BF16}[store], normalize)
+    om = O.L2SQ if metric == vrs.L2SQ else O.IP
+    for k in (1, 100):
+        ref = O.scan_topk(ot, q, [], k, om)
+        for tile in (4, 7):
+            for passes in (1, 2):
+                r = T.scan_topk(_dev(q), [], k, metric, tile=tile, strategy=vrs.STRATEGY_MASK, passes=passes)
+                _check(r, ref, f"store {store} k {k} tile {tile} passes {passes}")
+
+
 def test_batch_limit_is_an_argument_error(cfg0):
     T = cfg0[3]
     assert T.workspace_bytes(vrs.MAX_BATCH, 10) > 0
