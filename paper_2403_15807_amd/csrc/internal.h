@@ -163,7 +163,7 @@ size_t screen_stream_lds(int qt, int Kp, int CB, int dp);
 hipError_t launch_screen_mfma(const ScreenArgs &a, int qm, hipStream_t s);
 size_t screen_mfma_lds(int dp, int qm);
 hipError_t launch_screen_mfma_bf16(const ScreenArgs &a, hipStream_t s);
-size_t screen_mfma_bf16_lds();
+size_t screen_mfma_bf16_lds(int kc);  // kc = coordinates per chunk (64 or 128)
 int screen_mfma_bf16_qm();                              // queries per workgroup
 size_t screen_mfma_bf16_qfrag_bytes(int B, int dp);     // fragment-ordered query copy
 bool screen_mfma_bf16_supported(int dp, vrs_dtype store, int metric, int Kp, int CB);

@@ -12,13 +12,15 @@
 //
 // Workgroup = 8 waves x 32 queries (two 16-query MFMA blocks per wave) = 256
 // queries against one chunk of rows, rows in tiles of 128, coordinates in
-// chunks of 64 (a batch of up to 256 queries reads every row once; at 256
-// VGPRs per lane one such workgroup fills a CU).  Only the rows go through LDS (double-buffered: the next
-// chunk's loads are in flight while the current one is multiplied, one
-// barrier per chunk); the query parts are read straight into registers
-// from a fragment-ordered copy made by the query preparation (one 1 KB
-// load per wave and operand), one k-step ahead.  Every 16-row B fragment
-// read from LDS feeds four MFMAs (two query blocks x hi/lo).  Top-k state is
+// chunks of 128 (or 64 where 128 does not divide the padded dimension, and
+// in the persistent form); a batch of up to 256 queries reads every row
+// once, and one such workgroup fills a CU.  Only the rows go through LDS
+// (double-buffered: the next chunk's loads are in flight while the current
+// one is multiplied, one barrier per chunk); the query parts are read
+// straight into registers from a fragment-ordered copy made by the query
+// preparation (one 1 KB load per wave and operand), one k-step ahead, in
+// two register sets that alternate by k-step.  Every 16-row B fragment read
+// from LDS feeds four MFMAs (two query blocks x hi/lo).  Top-k state is
 // wave-private as in the float32 kernel.
 #include "internal.h"
 #include "wave_topk.h"
@@ -37,8 +39,11 @@ constexpr int NT = 64 * NWAVE;  // threads per workgroup
 constexpr int QM = NWAVE * QW;  // queries per workgroup
 constexpr int BR = 128;         // rows per tile
 constexpr int NB = BR / 16;     // 16-row MFMA blocks per tile
-constexpr int KC = 64;          // coordinates per chunk (two k-steps of 32)
-constexpr int LDK = 72;         // LDS row stride in bfloat16 elements (144 bytes)
+// KC = coordinates per chunk (one workgroup barrier each): 128 (four
+// k-steps of 32) when it divides the padded dimension, else 64; LDS rows are
+// KC + 8 bfloat16 long (144 or 272 bytes: the 16 rows of a B fragment start
+// on distinct bank quads)
+constexpr int kc_for(int dp) { return dp % 128 == 0 ? 128 : 64; }
 constexpr int SLOTS = 3;        // rotating row-record slots
 
 // An e4m3fn code's value as an f32: its 7 magnitude bits placed as the top
@@ -64,7 +69,7 @@ __device__ __forceinline__ bf8v as_bf8(const uint4 &u) {
 }
 
 struct Lds {
-    uint16_t *xs;      // [2][BR][LDK]
+    uint16_t *xs;      // [2][BR][KC + 8]
     int *rid;          // [SLOTS][BR]
     int *rok;          // [SLOTS][BR] row exists (and, shared predicate, qualifies)
     float *rsc;        // [SLOTS][BR] FP8 row scale
@@ -75,10 +80,11 @@ struct Lds {
     QRange *qrg;       // [QM] per-query predicates (range form)
 };
 
+template <int KC>
 __device__ __forceinline__ Lds carve(unsigned char *smem) {
     Lds L;
     L.xs = (uint16_t *)smem;
-    L.rid = (int *)(L.xs + 2 * BR * LDK);
+    L.rid = (int *)(L.xs + 2 * BR * (KC + 8));
     L.rok = L.rid + SLOTS * BR;
     L.rsc = (float *)(L.rok + SLOTS * BR);
     L.pm = (uint32_t *)(L.rsc + SLOTS * BR);
@@ -91,16 +97,18 @@ __device__ __forceinline__ Lds carve(unsigned char *smem) {
 
 // One work item: queries [q0, q0 + QM) (of Bq) against row chunk `chunk` of
 // `nchunks`; its lists are (query, chunk) lists of the partials.
-template <int STORE, bool GATHER, bool BATCHED, int E>
+template <int STORE, bool GATHER, bool BATCHED, int E, int KC>
 __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, const int nchunks,
                                           const int q0, const int Bq, unsigned char *smem) {
     // 16-byte row loads per thread per chunk (BR rows x KC coordinates over NT threads)
-    constexpr int XLD = BR * KC * (STORE == VRS_BF16 ? 2 : 1) / (16 * NT);
-    static_assert(XLD >= 1, "a chunk must give every thread a load");
+    constexpr int LDK = KC + 8;
+    constexpr int TPR = KC * (STORE == VRS_BF16 ? 2 : 1) / 16;  // threads per row of a chunk
+    constexpr int XLD = BR * TPR / NT;
+    static_assert(XLD >= 1 && XLD * NT == BR * TPR, "a chunk must give every thread the same loads");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int dp = a.dp;
     const int nkc = dp / KC, nks = dp / 32;
-    const Lds L = carve(smem);
+    const Lds L = carve<KC>(smem);
 
     const int K = a.K, CBq = a.CB;
     if (tid < QM) {
@@ -188,7 +196,7 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
         int rr[XLD];
 #pragma unroll
         for (int i = 0; i < XLD; ++i) {
-            const int r = STORE == VRS_BF16 ? (tid + NT * i) >> 3 : (tid + NT * i) >> 2;
+            const int r = (tid + NT * i) / TPR;
             rr[i] = L.rid[slot * BR + r];
             xm[i] = 0u - (uint32_t)(L.rok[slot * BR + r] != 0);
         }
@@ -196,7 +204,7 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
         // the loads are unconditional; unwanted rows are zeroed at commit
 #pragma unroll
         for (int i = 0; i < XLD; ++i) {
-            const int cc = STORE == VRS_BF16 ? (tid + NT * i) & 7 : (tid + NT * i) & 3;
+            const int cc = (tid + NT * i) % TPR;
             xr[i] = *(const uint4 *)(X + (int64_t)rr[i] * row_bytes + kc * KC * EB + cc * 16);
         }
     };
@@ -207,9 +215,9 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
             xr[i] = make_uint4(xr[i].x & xm[i], xr[i].y & xm[i], xr[i].z & xm[i], xr[i].w & xm[i]);
             const int idx = tid + NT * i;
             if (STORE == VRS_BF16) {
-                *(uint4 *)(xb + (idx >> 3) * LDK + (idx & 7) * 8) = xr[i];
+                *(uint4 *)(xb + (idx / TPR) * LDK + (idx % TPR) * 8) = xr[i];
             } else {
-                uint16_t *d = xb + (idx >> 2) * LDK + (idx & 3) * 16;
+                uint16_t *d = xb + (idx / TPR) * LDK + (idx % TPR) * 16;
                 const uint2 p0 = e4m3x4_to_bf16x4(xr[i].x), p1 = e4m3x4_to_bf16x4(xr[i].y);
                 const uint2 p2 = e4m3x4_to_bf16x4(xr[i].z), p3 = e4m3x4_to_bf16x4(xr[i].w);
                 *(uint4 *)d = make_uint4(p0.x, p0.y, p1.x, p1.y);
@@ -222,12 +230,18 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
     // Loads are issued in the order they are consumed (they retire in
     // order): this chunk's second k-step of query fragments, the next
     // chunk's rows, then the next chunk's first k-step of query fragments.
-    uint4 A0[2][2], A1[2][2];
+    // query fragments alternate between two register sets by k-step parity
+    // (KC / 32 is even, so a chunk's k-step 0 always uses set 0); a chunk
+    // loads its k-steps 1 and 3 before its rows and its k-step 2 and the next
+    // chunk's k-step 0 after them, so no wait on query fragments waits for
+    // rows issued in the same chunk except at the chunk's end
+    static_assert((KC / 32) % 2 == 0, "k-steps per chunk");
+    uint4 Ab[2][2][2];
     if (nch > 0) {
         rowinfo(0);
         __syncthreads();
         issue(0);
-        loadA(0, A0);
+        loadA(0, Ab[0]);
     }
     int c = 0;  // running chunk index (tile t, coordinate chunk kc)
     for (int t = 0; t < ntile; ++t) {
@@ -243,17 +257,24 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
             commit(buf);
             if (kc == nkc - 1 && t + 1 < ntile) rowinfo(t + 1);
             __syncthreads();
-            loadA(kc * 2 + 1, A1);
-            __builtin_amdgcn_sched_barrier(0);
-            issue(c + 1 < nch ? c + 1 : c);  // (the last chunk reloads itself, unused)
-            __builtin_amdgcn_sched_barrier(0);
-            uint4 An[2][2];
-            loadA(kc * 2 + 2 < nks ? kc * 2 + 2 : 0, An);  // the next tile starts at k-step 0
-            __builtin_amdgcn_sched_barrier(0);
+            const int ks0 = kc * (KC / 32);
             const uint16_t *xb = L.xs + buf * BR * LDK + (lane & 15) * LDK + (lane >> 4) * 8;
 #pragma unroll
             for (int s = 0; s < KC / 32; ++s) {
-                const uint4(&A)[2][2] = s == 0 ? A0 : A1;
+                // the next k-step's query fragments (past the chunk: the next
+                // chunk's first, past the tile: k-step 0), and after the
+                // second-to-last k-step's fragments, the next chunk's rows
+                if (s + 1 < KC / 32) {
+                    loadA(ks0 + s + 1, Ab[(s + 1) & 1]);
+                } else {
+                    loadA(ks0 + s + 1 < nks ? ks0 + s + 1 : 0, Ab[0]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                if (s == KC / 32 - 2) {
+                    issue(c + 1 < nch ? c + 1 : c);  // (the last chunk reloads itself, unused)
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                const uint4(&A)[2][2] = Ab[s & 1];
                 const bf8v a00 = as_bf8(A[0][0]), a01 = as_bf8(A[0][1]);
                 const bf8v a10 = as_bf8(A[1][0]), a11 = as_bf8(A[1][1]);
                 bf8v Bc = *(const bf8v *)(xb + s * 32);
@@ -270,10 +291,6 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
                     Bc = Bn;
                 }
             }
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int hl = 0; hl < 2; ++hl) A0[b][hl] = An[b][hl];
         }
 
         // ---- epilogue of tile t: lane holds, per query block b, queries
@@ -356,10 +373,10 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
     }
 }
 
-template <int STORE, bool GATHER, bool BATCHED, int E>
+template <int STORE, bool GATHER, bool BATCHED, int E, int KC>
 __global__ __launch_bounds__(NT) void screen_mfma_bf16_kernel(ScreenArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    bf16_tile<STORE, GATHER, BATCHED, E>(a, blockIdx.x, a.n_chunks, blockIdx.y * QM, a.B, smem);
+    bf16_tile<STORE, GATHER, BATCHED, E, KC>(a, blockIdx.x, a.n_chunks, blockIdx.y * QM, a.B, smem);
 }
 
 // Persistent form (batched uneven launch): the dense queries are positions
@@ -369,7 +386,7 @@ __global__ __launch_bounds__(NT) void screen_mfma_bf16_kernel(ScreenArgs a) {
 // tile, chunk-major: the query tiles of one chunk run at the same time on
 // one XCD and read its rows through the same L2.  An empty queue sends the
 // workgroup to the other XCDs' queues.
-template <int STORE, int E>
+template <int STORE, int E, int KC>
 __global__ __launch_bounds__(NT) void screen_mfma_bf16_persistent(ScreenArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int item_s;
@@ -398,29 +415,34 @@ __global__ __launch_bounds__(NT) void screen_mfma_bf16_persistent(ScreenArgs a) 
         if (it < 0) break;
         const int qx = it / per, i = it - qx * per;
         const int chunk = qx + 8 * (i / ntiles), qt = i - (i / ntiles) * ntiles;
-        bf16_tile<STORE, false, true, E>(a, chunk, nc, qt * QM, Bq, smem);
+        bf16_tile<STORE, false, true, E, KC>(a, chunk, nc, qt * QM, Bq, smem);
         __syncthreads();
     }
 }
 
-template <int STORE, int E>
-hipError_t launch_se(const ScreenArgs &a, hipStream_t s) {
+template <int STORE, int E, int KC>
+hipError_t launch_sek(const ScreenArgs &a, hipStream_t s) {
     dim3 grid(a.n_chunks, (a.B + QM - 1) / QM), block(NT);
-    const size_t lds = screen_mfma_bf16_lds();
+    const size_t lds = screen_mfma_bf16_lds(KC);
     if (a.preds) {
-        auto k = screen_mfma_bf16_kernel<STORE, false, true, E>;
+        auto k = screen_mfma_bf16_kernel<STORE, false, true, E, KC>;
         ensure_dyn_lds((const void *)k, lds);
         k<<<grid, block, lds, s>>>(a);
     } else if (a.gather) {
-        auto k = screen_mfma_bf16_kernel<STORE, true, false, E>;
+        auto k = screen_mfma_bf16_kernel<STORE, true, false, E, KC>;
         ensure_dyn_lds((const void *)k, lds);
         k<<<grid, block, lds, s>>>(a);
     } else {
-        auto k = screen_mfma_bf16_kernel<STORE, false, false, E>;
+        auto k = screen_mfma_bf16_kernel<STORE, false, false, E, KC>;
         ensure_dyn_lds((const void *)k, lds);
         k<<<grid, block, lds, s>>>(a);
     }
     return hipGetLastError();
+}
+
+template <int STORE, int E>
+hipError_t launch_se(const ScreenArgs &a, hipStream_t s) {
+    return kc_for(a.dp) == 128 ? launch_sek<STORE, E, 128>(a, s) : launch_sek<STORE, E, 64>(a, s);
 }
 
 template <int STORE>
@@ -433,13 +455,20 @@ hipError_t launch_s(const ScreenArgs &a, hipStream_t s) {
     }
 }
 
-template <int STORE, int E>
-hipError_t launch_pe(const ScreenArgs &a, int grid, hipStream_t s) {
-    const size_t lds = screen_mfma_bf16_lds();
-    auto k = screen_mfma_bf16_persistent<STORE, E>;
+template <int STORE, int E, int KC>
+hipError_t launch_pek(const ScreenArgs &a, int grid, hipStream_t s) {
+    const size_t lds = screen_mfma_bf16_lds(KC);
+    auto k = screen_mfma_bf16_persistent<STORE, E, KC>;
     ensure_dyn_lds((const void *)k, lds);
     k<<<grid, NT, lds, s>>>(a);
     return hipGetLastError();
+}
+
+// (the persistent form keeps 64-coordinate chunks: its per-query predicate
+// masks leave no registers for the wider chunk's loads, which spill)
+template <int STORE, int E>
+hipError_t launch_pe(const ScreenArgs &a, int grid, hipStream_t s) {
+    return launch_pek<STORE, E, 64>(a, grid, s);
 }
 
 template <int STORE>
@@ -454,8 +483,8 @@ hipError_t launch_p(const ScreenArgs &a, int grid, hipStream_t s) {
 
 }  // namespace
 
-size_t screen_mfma_bf16_lds() {
-    return (size_t)2 * BR * LDK * 2 + (size_t)3 * SLOTS * BR * 4 + (size_t)SLOTS * BR * (QM / 32) * 4 +
+size_t screen_mfma_bf16_lds(int kc) {
+    return (size_t)2 * BR * (kc + 8) * 2 + (size_t)3 * SLOTS * BR * 4 + (size_t)SLOTS * BR * (QM / 32) * 4 +
            QM * 4 * 2 + QM * 8 + QM * sizeof(QRange) + 16;
 }
 
@@ -469,7 +498,7 @@ size_t screen_mfma_bf16_qfrag_bytes(int B, int dp) { return (size_t)((B + 15) / 
 
 bool screen_mfma_bf16_supported(int dp, vrs_dtype store, int metric, int Kp, int CB) {
     const int E = (Kp + CB) / 64;
-    return (store == VRS_BF16 || store == VRS_FP8E4M3) && metric == VRS_IP && dp % KC == 0 &&
+    return (store == VRS_BF16 || store == VRS_FP8E4M3) && metric == VRS_IP && dp % 64 == 0 &&
            (E == 4 || E == 8 || E == 16 || E == 32) && (Kp + CB) == 64 * E;
 }
 
