@@ -99,6 +99,9 @@ struct ScreenArgs {
     int32_t shared_rows;           // rows are read by several query tiles: keep them cacheable
     uint64_t *partials;            // [B][n_chunks][K]
     uint64_t *heads;               // [B][n_chunks] first key of each list, or null
+    // [B][n_chunks] keys each list holds (MFMA kernels), or null: the list
+    // entries past them are then left unwritten instead of set to KEY_INF
+    int32_t *fills;
     uint64_t *cbuf;                // [B][n_chunks][CB] candidate buffers (MFMA kernels)
     uint64_t *gthr;                // [B] smallest K-th key published by any chunk
     // Two-pass screening (MFMA kernels): pass 1 covers the first tiles of
@@ -298,6 +301,7 @@ struct FinishArgs {
     int32_t n_chunks;
     const uint64_t *partials;
     const uint64_t *heads;         // [B][n_chunks] first key of each list, or null
+    const int32_t *fills;          // [B][n_chunks] keys each list holds (entries past them unread), or null
     const int64_t *list_off;       // batched uneven form: [B] first list of each position
     const int32_t *nlists;         // and its list count (null: n_chunks lists per query)
     const int32_t *perm;           // position -> query index (null: identity)

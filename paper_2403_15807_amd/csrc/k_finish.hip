@@ -222,7 +222,8 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
                                                               const int32_t *__restrict__ nlists,
                                                               const uint64_t *__restrict__ heads,
                                                               int32_t *__restrict__ rr_count,
-                                                              const int32_t *__restrict__ limit) {
+                                                              const int32_t *__restrict__ limit,
+                                                              const int32_t *__restrict__ fills) {
     constexpr int T = MERGE_THREADS;
     const int g = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
     if (rr_count && tid == 0) rr_count[b] = 0;  // the rerank's arrival counter
@@ -238,6 +239,8 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
         return;
     }
     const uint64_t *lists = src + (first + l0) * K;
+    // keys list l holds (with a count array its later entries are unread)
+    const int32_t *fl = fills ? fills + first + l0 : nullptr;
     const int M = Kp + CB;
     uint64_t *keys = (uint64_t *)smem;  // heads, then the collected keys
     const int region = max(M, MERGE_HMAX);
@@ -263,7 +266,8 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
 #pragma unroll
         for (int e = 0; e < S; ++e) {
             const int i = min(e * T + tid, H - 1);
-            const uint64_t key = hd ? hd[i] : lists[(int64_t)(i / m) * K + (i % m)];
+            const int li = i / m, lj = i - li * m;
+            const uint64_t key = hd ? hd[i] : ((!fl || lj < fl[li]) ? lists[(int64_t)li * K + lj] : KEY_INF);
             v[e] = (uint32_t)(key >> 32);
         }
         uint32_t *hist = (uint32_t *)keys;  // the collection area is free until phase 2
@@ -278,11 +282,13 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
     // next two entries of up to two of its lists, so most lists cost one
     // round.
     int pos[4] = {0, 0, 0, 0};
+    int len[4];
     bool live[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int l = tid + j * T;
-        live[j] = l < L && (!hd || hd[min(l, L - 1)] <= bound);
+        len[j] = (fl && l < L) ? fl[l] : K;
+        live[j] = l < L && len[j] > 0 && (!hd || hd[min(l, L - 1)] <= bound);
     }
     for (;;) {
         int sel0 = -1, sel1 = -1;
@@ -295,10 +301,14 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
             const int j = x == 0 ? sel0 : sel1;
+            int n = 0;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+                if (jj == j) n = len[jj];
             const int p = j >= 0 ? pos[j] : K;
             const uint64_t *lp = lists + (int64_t)(tid + max(j, 0) * T) * K;
-            v[x][0] = (j >= 0 && p < K) ? lp[p] : KEY_INF;
-            v[x][1] = (j >= 0 && p + 1 < K) ? lp[p + 1] : KEY_INF;
+            v[x][0] = (j >= 0 && p < n) ? lp[p] : KEY_INF;
+            v[x][1] = (j >= 0 && p + 1 < n) ? lp[p + 1] : KEY_INF;
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
@@ -319,7 +329,7 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
             for (int jj = 0; jj < 4; ++jj)
                 if (jj == j) {
                     pos[jj] += 2;
-                    live[jj] = keep && pos[jj] < K;
+                    live[jj] = keep && pos[jj] < len[jj];
                 }
         }
         bool any = false;
@@ -834,7 +844,7 @@ hipError_t launch_merge(const FinishArgs &a, hipStream_t s) {
     if (a.n_chunks <= G) {
         merge_kernel<<<dim3(1, a.B), MERGE_THREADS, lds, s>>>(a.partials, a.n_chunks, G, a.K, Kp,
                                                              CB, a.merged, 1, a.list_off, a.nlists,
-                                                             a.heads, a.rr_count, a.merge_limit);
+                                                             a.heads, a.rr_count, a.merge_limit, a.fills);
         return hipGetLastError();
     }
     // two levels: groups of G lists, then the group results
@@ -842,10 +852,10 @@ hipError_t launch_merge(const FinishArgs &a, hipStream_t s) {
     uint64_t *mid = a.merge_mid;
     merge_kernel<<<dim3(ng, a.B), MERGE_THREADS, lds, s>>>(a.partials, a.n_chunks, G, a.K, Kp, CB,
                                                           mid, ng, a.list_off, a.nlists, a.heads, nullptr,
-                                                          a.merge_limit);
+                                                          a.merge_limit, a.fills);
     merge_kernel<<<dim3(1, a.B), MERGE_THREADS, lds, s>>>(mid, ng, ng, a.K, Kp, CB, a.merged, 1,
                                                          nullptr, nullptr, nullptr, a.rr_count,
-                                                         a.merge_limit);
+                                                         a.merge_limit, nullptr);
     return hipGetLastError();
 }
 

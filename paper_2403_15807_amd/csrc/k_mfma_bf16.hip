@@ -365,11 +365,17 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
         flush_fit<E>(a.partials + base * K, a.cbuf + base * CBq, nq, Kq, fq, &L.thr[q], a.gthr + qa);
         if (lane == 0) L.fill[q] = min(Kq, fq + nq);
     }
-    // the list entries past each query's keys (the whole list length K)
+    // each list's key count, or (no count array) KEY_INF in the list
+    // entries past its keys (the whole list length K)
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    for (int j = 0; j < QW; ++j) {
-        const int q = wave * QW + j, qa = q0 + q;
-        if (qa < Bq) list_tail_inf(a.partials + ((int64_t)qa * nchunks + chunk) * K, L.fill[q], K);
+    if (a.fills) {
+        if (lane < QW && q0 + wave * QW + lane < Bq)
+            a.fills[(int64_t)(q0 + wave * QW + lane) * nchunks + chunk] = L.fill[wave * QW + lane];
+    } else {
+        for (int j = 0; j < QW; ++j) {
+            const int q = wave * QW + j, qa = q0 + q;
+            if (qa < Bq) list_tail_inf(a.partials + ((int64_t)qa * nchunks + chunk) * K, L.fill[q], K);
+        }
     }
 }
 

@@ -103,6 +103,7 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
     P.o_selcnt = take(8);
     P.o_part = take((size_t)B * P.n_chunks * P.K * 8);
     P.o_heads = take(P.mfma ? 0 : (size_t)B * P.n_chunks * 8);
+    P.o_fills = take(P.mfma ? (size_t)B * P.n_chunks * 4 : 0);
     P.o_mid = take((size_t)B * ((P.n_chunks + 2047) / 2048) * P.K * 8);
     P.o_merged = take((size_t)B * P.K * 8);
     P.o_rrdist = take((size_t)B * P.K * 8);
@@ -382,6 +383,7 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     sa.shared_rows = P.n_qtiles > 1;
     sa.partials = (uint64_t *)(w + P.o_part);
     sa.heads = P.mfma ? nullptr : (uint64_t *)(w + P.o_heads);
+    sa.fills = P.mfma ? (int32_t *)(w + P.o_fills) : nullptr;
     FinishArgs fa{};
     fa.rows = t->rows;
     fa.scale = t->scale;
@@ -406,6 +408,7 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     fa.n_chunks = P.n_chunks;
     fa.partials = sa.partials;
     fa.heads = sa.heads;
+    fa.fills = sa.fills;
     fa.merge_mid = (uint64_t *)(w + P.o_mid);
     fa.merged = (uint64_t *)(w + P.o_merged);
     fa.rr_dist = (double *)(w + P.o_rrdist);
