@@ -235,6 +235,56 @@ __host__ __device__ inline int next_pow2(int x) {
 
 namespace vrs {
 
+// The K-th smallest (1 <= K <= H) of H values spread over the T threads of
+// a workgroup (value i in thread i % T, slot i / T of v), by an 8-bit radix
+// select: each pass counts the values that share the digits fixed so far
+// by their next digit and keeps the digit whose bucket holds the K-th.
+// Every thread returns the same value.
+template <int S, int T>
+__device__ uint32_t block_kth_u32(const uint32_t (&v)[S], int H, int K, uint32_t *hist,
+                                  uint32_t *sel) {
+    const int tid = threadIdx.x;
+    uint32_t prefix = 0, mask = 0, kk = (uint32_t)K;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int i = tid; i < 256; i += T) hist[i] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < S; ++e)
+            if (e * T + tid < H && (v[e] & mask) == prefix) atomicAdd(&hist[(v[e] >> shift) & 255u], 1u);
+        __syncthreads();
+        if (tid < 64) {
+            uint32_t c[4], sum = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                c[e] = hist[tid * 4 + e];
+                sum += c[e];
+            }
+            uint32_t incl = sum;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(incl, o);
+                if (tid >= o) incl += t;
+            }
+            uint32_t run = incl - sum;
+            if (run < kk && kk <= incl) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (run < kk && kk <= run + c[e]) {
+                        sel[0] = prefix | ((uint32_t)(tid * 4 + e) << shift);
+                        sel[1] = kk - run;
+                    }
+                    run += c[e];
+                }
+            }
+        }
+        __syncthreads();
+        prefix = sel[0];
+        kk = sel[1];
+        mask |= 255u << shift;
+    }
+    return prefix;
+}
+
 // ------------------------------------------------- wave-level bitonic sort
 // 64*E keys held E per lane (element index lane*E + e), sorted ascending by
 // one wave without LDS or barriers: strides below E are swaps inside a lane,

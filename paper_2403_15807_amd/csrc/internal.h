@@ -57,9 +57,10 @@ hipError_t launch_select(const int32_t *attr, int64_t n, int64_t an, const PredD
                          hipStream_t s);
 
 // ---- query preparation (k_finish.hip)
+// heads (or null): [B][n_heads] keys set to KEY_INF (see ScreenArgs::heads_bound)
 hipError_t launch_prep_queries(const float *q, int32_t B, int32_t d, int32_t dp, float *qp,
                                double *qnorm, float *qn2, uint16_t *qhl, uint64_t *gthr,
-                               int32_t *fail_count, hipStream_t s);
+                               int32_t *fail_count, uint64_t *heads, int32_t n_heads, hipStream_t s);
 int screen_mfma_occupancy(int Kp, int CB, int qm);
 hipError_t launch_prep_batched(const vrs_pred *preds, const int32_t *ks, int32_t B, int32_t kmax,
                                int32_t n_attr, int kmult, int f32_rule, PredDev *out,
@@ -99,6 +100,10 @@ struct ScreenArgs {
     int32_t shared_rows;           // rows are read by several query tiles: keep them cacheable
     uint64_t *partials;            // [B][n_chunks][K]
     uint64_t *heads;               // [B][n_chunks] first key of each list, or null
+    // heads were set to KEY_INF before the launch: a one-query streaming
+    // workgroup then publishes its best key there at every flush and bounds
+    // its list by the K-th smallest published key
+    int32_t heads_bound;
     // [B][n_chunks] keys each list holds (MFMA kernels), or null: the list
     // entries past them are then left unwritten instead of set to KEY_INF
     int32_t *fills;

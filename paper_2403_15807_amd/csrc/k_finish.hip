@@ -28,9 +28,13 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, 
                                                    const int32_t *__restrict__ kps_o,
                                                    PredDev *__restrict__ pred_p,
                                                    int32_t *__restrict__ kc_p,
-                                                   int32_t *__restrict__ kps_p) {
+                                                   int32_t *__restrict__ kps_p,
+                                                   uint64_t *__restrict__ heads, int n_heads) {
     const int b = blockIdx.x;                 // position
     const int src = perm ? perm[b] : b;       // query
+    // the query's per-chunk best keys of the streaming screen start empty
+    if (heads)
+        for (int j = threadIdx.x; j < n_heads; j += 256) heads[(int64_t)b * n_heads + j] = KEY_INF;
     if (threadIdx.x == 0) {
         gthr[b] = KEY_INF;
         if (perm) {
@@ -163,56 +167,6 @@ __device__ __forceinline__ int kp_of(const FinishArgs &a, int b) {
 constexpr int MERGE_THREADS = 512;
 constexpr int MERGE_HMAX = 4096;
 constexpr int MERGE_RANK_MAX = 1024;  // collected keys sorted by ranking
-
-// The K-th smallest (1 <= K <= H) of H values spread over the T threads of
-// a workgroup (value i in thread i % T, slot i / T of v), by an 8-bit radix
-// select: each pass counts the values that share the digits fixed so far
-// by their next digit and keeps the digit whose bucket holds the K-th.
-// Every thread returns the same value.
-template <int S, int T>
-__device__ uint32_t block_kth_u32(const uint32_t (&v)[S], int H, int K, uint32_t *hist,
-                                  uint32_t *sel) {
-    const int tid = threadIdx.x;
-    uint32_t prefix = 0, mask = 0, kk = (uint32_t)K;
-    for (int shift = 24; shift >= 0; shift -= 8) {
-        for (int i = tid; i < 256; i += T) hist[i] = 0;
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < S; ++e)
-            if (e * T + tid < H && (v[e] & mask) == prefix) atomicAdd(&hist[(v[e] >> shift) & 255u], 1u);
-        __syncthreads();
-        if (tid < 64) {
-            uint32_t c[4], sum = 0;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                c[e] = hist[tid * 4 + e];
-                sum += c[e];
-            }
-            uint32_t incl = sum;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t t = __shfl_up(incl, o);
-                if (tid >= o) incl += t;
-            }
-            uint32_t run = incl - sum;
-            if (run < kk && kk <= incl) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if (run < kk && kk <= run + c[e]) {
-                        sel[0] = prefix | ((uint32_t)(tid * 4 + e) << shift);
-                        sel[1] = kk - run;
-                    }
-                    run += c[e];
-                }
-            }
-        }
-        __syncthreads();
-        prefix = sel[0];
-        kk = sel[1];
-        mask |= 255u << shift;
-    }
-    return prefix;
-}
 
 __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__restrict__ src,
                                                               int n_lists, int G, int K, int Kp,
@@ -789,9 +743,9 @@ __global__ void set_bound_kernel(const uint64_t *__restrict__ merged, int K, int
 
 hipError_t launch_prep_queries(const float *q, int32_t B, int32_t d, int32_t dp, float *qp,
                                double *qnorm, float *qn2, uint16_t *qhl, uint64_t *gthr,
-                               int32_t *fail_count, hipStream_t s) {
+                               int32_t *fail_count, uint64_t *heads, int32_t n_heads, hipStream_t s) {
     prep_kernel<<<B, 256, 0, s>>>(q, d, dp, qp, qnorm, qn2, qhl, gthr, fail_count, nullptr, nullptr,
-                                  nullptr, nullptr, nullptr, nullptr, nullptr);
+                                  nullptr, nullptr, nullptr, nullptr, nullptr, heads, n_heads);
     return hipGetLastError();
 }
 
@@ -801,7 +755,7 @@ hipError_t launch_prep_permuted(const float *q, const int32_t *perm, int32_t B, 
                                 uint16_t *qhl, uint64_t *gthr, int32_t *fail_count,
                                 PredDev *pred_p, int32_t *kc_p, int32_t *kps_p, hipStream_t s) {
     prep_kernel<<<B, 256, 0, s>>>(q, d, dp, qp, qnorm, qn2, qhl, gthr, fail_count, perm, pred_o, kc_o,
-                                  kps_o, pred_p, kc_p, kps_p);
+                                  kps_o, pred_p, kc_p, kps_p, nullptr, 0);
     return hipGetLastError();
 }
 

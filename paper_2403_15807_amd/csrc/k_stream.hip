@@ -21,6 +21,34 @@ constexpr int TILE = 4 * 8 * U;      // rows per workgroup iteration
 constexpr int NB = 4;                // 128-byte column blocks loaded together
 
 typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+
+// One-query workgroups: publish this chunk's best key (its list's first)
+// in the query's row of heads, then take the K-th smallest distance of all
+// chunks' published best keys as a bound: K chunks each hold a key at or
+// below it, so the query's K-th key is too (unpublished chunks read
+// KEY_INF; a stale entry is a larger key of the same chunk, still valid).
+// Early in the scan this is far tighter than any one chunk's own K-th key,
+// which is the K-th of the few rows that chunk has seen.  Whole workgroup.
+__device__ void bound_from_heads(const ScreenArgs &a, int chunk, uint64_t best, uint64_t *thr,
+                                 uint32_t *hist, int tid) {
+    uint64_t *hq = a.heads + (int64_t)(blockIdx.y) * a.n_chunks;  // one query per workgroup row
+    if (tid == 0) __atomic_store_n((unsigned long long *)(hq + chunk), (unsigned long long)best,
+                                   __ATOMIC_RELAXED);
+    constexpr int S = 4;
+    uint32_t v[S];
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+        const int i = e * 256 + tid;
+        v[e] = i < a.n_chunks
+                   ? (uint32_t)(__atomic_load_n((const unsigned long long *)(hq + i), __ATOMIC_RELAXED) >> 32)
+                   : 0xffffffffu;
+    }
+    const uint32_t bd = block_kth_u32<S, 256>(v, a.n_chunks, a.K, hist, hist + 256);
+    if (tid == 0 && bd != 0xffffffffu) {
+        const uint64_t bk = ((uint64_t)bd << 32) | 0xffffffffu;
+        if (bk < thr[0]) thr[0] = bk;
+    }
+}
 __device__ __forceinline__ uint4 load_nt(const uint4 *p) {
     v4u32 v = __builtin_nontemporal_load((const v4u32 *)p);
     return make_uint4(v.x, v.y, v.z, v.w);
@@ -41,6 +69,7 @@ __global__ __launch_bounds__(256) void screen_stream_kernel(ScreenArgs a) {
     int *cnt = (int *)(thr + QT);
     float *qs = (float *)(cnt + QT + 2);  // 8-byte aligned; [QT][dp]
     qs = (float *)(((uintptr_t)qs + 15) & ~(uintptr_t)15);
+    uint32_t *hist = (uint32_t *)(qs + QT * a.dp);  // [256 + 2] radix-select scratch
 
     TopkLds<uint64_t> tk{keys, cnt, thr, QT, a.K, a.Kp, a.CB};
     for (int i = tid; i < QT * a.dp; i += 256) {
@@ -200,6 +229,8 @@ __global__ __launch_bounds__(256) void screen_stream_kernel(ScreenArgs a) {
                                                 (unsigned long long)thr[tid]);
                 if (prev < thr[tid]) thr[tid] = prev;
             }
+            if (QT == 1 && !BATCHED && a.heads_bound && a.n_chunks >= a.K && a.n_chunks <= 4 * 256)
+                bound_from_heads(a, chunk, keys[0], thr, hist, tid);
             __syncthreads();
         }
     }
@@ -245,7 +276,7 @@ hipError_t launch_qt(const ScreenArgs &a, hipStream_t s) {
 }  // namespace
 
 size_t screen_stream_lds(int qt, int Kp, int CB, int dp) {
-    return (size_t)qt * (Kp + CB) * 8 + qt * 8 + (qt + 2) * 4 + 16 + (size_t)qt * dp * 4;
+    return (size_t)qt * (Kp + CB) * 8 + qt * 8 + (qt + 2) * 4 + 16 + (size_t)qt * dp * 4 + 258 * 4;
 }
 
 hipError_t launch_screen_stream(const ScreenArgs &a, int qt, hipStream_t s) {

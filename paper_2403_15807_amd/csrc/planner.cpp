@@ -331,7 +331,10 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     uint64_t *gthr = (uint64_t *)(w + P.o_gthr);
     int32_t *fail_count = (int32_t *)(w + P.o_failcnt);
     prof_begin(0, s);
-    hipError_t e = launch_prep_queries(q, B, t->d, t->dp, qp, qnorm, qn2, qhl, gthr, fail_count, s);
+    // (a streaming scan's per-chunk best keys start empty: they bound the lists)
+    uint64_t *heads = P.mfma ? nullptr : (uint64_t *)(w + P.o_heads);
+    hipError_t e = launch_prep_queries(q, B, t->d, t->dp, qp, qnorm, qn2, qhl, gthr, fail_count, heads,
+                                       heads ? P.n_chunks : 0, s);
     if (e != hipSuccess) return e;
     PredDev *pdev = (PredDev *)(w + P.o_preds);
     int32_t *kc = (int32_t *)(w + P.o_kc), *kps = (int32_t *)(w + P.o_kps);
@@ -382,7 +385,8 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     sa.n_chunks = P.n_chunks;
     sa.shared_rows = P.n_qtiles > 1;
     sa.partials = (uint64_t *)(w + P.o_part);
-    sa.heads = P.mfma ? nullptr : (uint64_t *)(w + P.o_heads);
+    sa.heads = heads;
+    sa.heads_bound = heads != nullptr;
     sa.fills = P.mfma ? (int32_t *)(w + P.o_fills) : nullptr;
     FinishArgs fa{};
     fa.rows = t->rows;
