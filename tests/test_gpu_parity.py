@@ -357,6 +357,34 @@ def test_two_pass_bound_inside_a_run_of_ties(store, metric):
                 _check(r, ref, f"store {store} k {k} tile {tile} passes {passes}")
 
 
+@pytest.mark.parametrize("metric", [vrs.L2SQ, vrs.IP])
+def test_one_query_stream_bound_from_published_heads(metric):
+    # one-query streaming scans over enough row chunks (>= k'+1) bound each
+    # chunk's list by the k'+1-th smallest best key any chunk has published;
+    # with 4 copies of every vector the bound falls inside runs of tied
+    # distances, and ids must still match the oracle exactly
+    rng = np.random.default_rng(31)
+    base = inputs.table(12, 75000, 96, 50)
+    x = np.ascontiguousarray(np.tile(base, (4, 1))[rng.permutation(4 * 75000)])
+    n = x.shape[0]
+    a = inputs.attributes(12, n, 2, 10 ** 6)
+    normalize = metric == vrs.IP
+    T = vrs.Table(_dev(x), _dev(a), normalize=normalize)
+    ot = O.Table.build(x, a, O.F32, normalize)
+    om = O.L2SQ if metric == vrs.L2SQ else O.IP
+    q = np.ascontiguousarray(np.concatenate([base[rng.integers(0, 75000, 3)], inputs.queries(12, 3, 96, 50)]))
+    for sel in (1.0, 0.2):
+        w = inputs.two_term_width(sel, 10 ** 6)
+        pred = [(0, 0, w), (1, 0, w)] if sel < 1.0 else []
+        for k in (1, 10, 50):
+            for strategy in (vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER):
+                for i in range(q.shape[0]):
+                    qi = q[i:i + 1]
+                    ref = O.scan_topk(ot, qi, pred, k, om)
+                    r = T.scan_topk(_dev(qi), pred, k, metric, tile=0, strategy=strategy)
+                    _check(r, ref, f"metric {metric} sel {sel} k {k} strategy {strategy} query {i}")
+
+
 def test_batch_limit_is_an_argument_error(cfg0):
     T = cfg0[3]
     assert T.workspace_bytes(vrs.MAX_BATCH, 10) > 0
