@@ -183,6 +183,15 @@ def bench_scan(args):
     ms_step = elapsed * 1e3 / args.steps
     qps = B * args.steps / elapsed
     certified = float(cert.float().mean().item())
+    diag = diagnostics(T, qd, pred, k, metric, strategy, args.tile, ws, args.passes, idx, torch)
+    # end to end: the call plus the copy of its results to host memory
+    e2e = []
+    for _ in range(min(args.steps, 10)):
+        t1 = time.perf_counter()
+        step()
+        idx.cpu(), dist.cpu()
+        e2e.append(time.perf_counter() - t1)
+    diag["end_to_end_ms_with_d2h"] = round(float(np.median(e2e)) * 1e3, 4)
 
     used_gather = stages["select"][1] > 0
     used_mfma = mfma_used(T, vrs, B, pred, k, metric, strategy, args.tile)
@@ -208,9 +217,11 @@ def bench_scan(args):
         log(f"copy calibration: 3 copies of {args.copy_calibration} MiB")
         del src, dst
 
-    sweep = None
+    sweep = sweep_check = None
     if args.sweep:
-        sweep = run_sweep(args, T, T_other, n, d, metric, vrs, torch, dev)
+        sweep, checks = run_sweep(args, T, T_other, n, d, metric, vrs, torch, dev)
+        if not args.no_cpu:
+            sweep_check = sweep_oracle_check(args, x, attr, checks, metric, vrs)
 
     cpu = None
     if not args.no_cpu:
@@ -240,12 +251,26 @@ def bench_scan(args):
         "cpu_baseline": cpu,
         "stages_ms_per_step": {s: round(v[0] / max(1, args.steps), 4) for s, v in stages.items()},
         "certified_frac": certified,
+        "fallback_rate": round(1.0 - certified, 6),
+        "diagnostics": diag,
     }
     if sweep is not None:
         rec["sweep"] = sweep
+        rec["sweep_check"] = sweep_check
     if precision is not None:
         rec["precision"] = precision
     print(json.dumps(rec), flush=True)
+
+
+def diagnostics(T, qd, pred, k, metric, strategy, tile, ws, passes, idx, torch):
+    """One untimed call with the screening-error diagnostic: the largest
+    |screening - exact| / bound over every reranked key of every query, the
+    certified fraction, and that the result equals the timed calls' one."""
+    r = T.scan_topk(qd, pred, k, metric, strategy=strategy, tile=tile, ws=ws, passes=passes, diag=True)
+    torch.cuda.synchronize()
+    return {"err_ratio_max": float(r.err_ratio.max().item()),
+            "certified_frac": float(r.certified.float().mean().item()),
+            "same_ids_as_timed": bool(torch.equal(r.idx, idx))}
 
 
 def run_sweep(args, T, T_other, n, d, metric, vrs, torch, dev):
@@ -258,7 +283,9 @@ def run_sweep(args, T, T_other, n, d, metric, vrs, torch, dev):
     if T_other is not None:
         om = "ip" if metric == vrs.L2SQ else "l2"
         tables.append((om, T_other, vrs.IP if metric == vrs.L2SQ else vrs.L2SQ))
-    qs = {B: torch.from_numpy(inputs.queries(1, B, d, args.clusters, stream_offset=7)).to(dev) for B in batches}
+    qs_h = {B: inputs.queries(1, B, d, args.clusters, stream_offset=7) for B in batches}
+    qs = {B: torch.from_numpy(v).to(dev) for B, v in qs_h.items()}
+    checks = []  # (metric name, query, predicate, ids) for the oracle
     t_start = time.time()
     for mname, TT, mm in tables:
         for B in batches:
@@ -269,12 +296,19 @@ def run_sweep(args, T, T_other, n, d, metric, vrs, torch, dev):
                 strategies = [("mask", vrs.STRATEGY_MASK), ("gather", vrs.STRATEGY_GATHER)]
                 if mname != args.metric:
                     strategies = [("auto", vrs.STRATEGY_AUTO)]
+                ids_first = None
                 for sname, st in strategies:
                     o = vrs.vrs_opts()
                     o.strategy, o.tile = st, -1
                     ws = TT.workspace(B, args.k, o)
-                    TT.scan_topk(qs[B], pred, args.k, mm, strategy=st, ws=ws)
+                    res = TT.scan_topk(qs[B], pred, args.k, mm, strategy=st, ws=ws)
                     torch.cuda.synchronize()
+                    ids = res.idx.cpu().numpy()
+                    if ids_first is None:
+                        ids_first = ids
+                        checks.append((mname, qs_h[B][0], pred, ids[0]))
+                    elif not np.array_equal(ids, ids_first):
+                        raise SystemExit(f"sweep: {sname} ids differ from mask at B={B} sel={s} {mname}")
                     vrs.stage_times()
                     vrs.profile(True)
                     t0 = time.perf_counter()
@@ -294,8 +328,26 @@ def run_sweep(args, T, T_other, n, d, metric, vrs, torch, dev):
                                    "qps": round(B * reps / el, 1), "ms": round(el * 1e3 / reps, 4),
                                    "screen_ms": round(sms * nl, 4), "passes": nl,
                                    "bound": r["bound"], "frac": r["frac"]})
-    log(f"sweep: {len(points)} points in {time.time() - t_start:.1f}s")
-    return points
+    log(f"sweep: {len(points)} points in {time.time() - t_start:.1f}s (mask and gather ids equal at every point)")
+    return points, checks
+
+
+def sweep_oracle_check(args, x, attr, checks, metric, vrs):
+    """Query 0 of every sweep point against the FP64 oracle (one call per
+    metric, each query with its point's predicate)."""
+    import oracle as O
+    cores = len(os.sched_getaffinity(0))
+    ok, t0 = 0, time.perf_counter()
+    for mname in sorted(set(c[0] for c in checks)):
+        cs = [c for c in checks if c[0] == mname]
+        ot = O.Table.build(x, attr, O.F32, normalize=(mname == "ip"))
+        q = np.stack([c[1] for c in cs])
+        ref = O.scan_topk(ot, q, [c[2] for c in cs], args.k, O.IP if mname == "ip" else O.L2SQ, nthreads=cores)
+        ok += sum(bool(np.array_equal(ref[0][i], c[3])) for i, c in enumerate(cs))
+        del ot
+    log(f"sweep oracle check: {ok}/{len(checks)} points match in {time.perf_counter() - t0:.1f}s")
+    return {"points_checked": len(checks), "points_matching_oracle": ok,
+            "what": "query 0 of every sweep point against the FP64 oracle; mask and gather ids equal at every point"}
 
 
 def cpu_baseline_scan(args, x, attr, q, pred, k, metric, B, idx, vrs):
@@ -399,13 +451,21 @@ def bench_batched(args):
     torch.cuda.synchronize()
     vrs.profile(False)
     stages = vrs.stage_times()
-    screen_ms = stages["screen"][0] / max(1, stages["screen"][1])
+    # the screening stage of one batch (dense and sparse kernels, both passes)
+    screen_ms = stages["screen"][0] / 3
+    launches = max(1, round(stages["screen"][1] / 3))
     pair_flops = 2.0 * d * float(sel_rows.sum())
     tf = pair_flops / (screen_ms * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(tf, 2), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None, "kernel": "screen (dense + sparse)",
-            "kernel_ms": round(screen_ms, 4), "alg_flops_per_launch": int(pair_flops),
-            "note": "algorithmic work = 2 d per qualifying (query, row) pair"}
+            "kernel_ms": round(screen_ms / launches, 4), "launches_per_step": launches,
+            "screen_ms_per_batch": round(screen_ms, 4), "alg_flops_per_batch": int(pair_flops),
+            "note": "algorithmic work = 2 d per qualifying (query, row) pair, over the batch's screening time"}
+    rd = T.scan_topk_batched(qd, pd, kd, kmax, vrs.IP, tile=best, ws=ws, diag=True)
+    torch.cuda.synchronize()
+    diag = {"err_ratio_max": float(rd.err_ratio.max().item()),
+            "certified_frac": float(rd.certified.float().mean().item()),
+            "same_ids_as_graph": bool(torch.equal(rd.idx, out[0]))}
 
     # the plain path, one launch per query (own predicate and k), on a sample
     m = min(B, args.per_query_sample)
@@ -446,7 +506,115 @@ def bench_batched(args):
         "per_query_launches_qps": round(pq_qps, 2),
         "speedup_vs_per_query_launches": round(qps / pq_qps, 2),
         "cpu_baseline": cpu,
+        "fallback_rate": round(1.0 - diag["certified_frac"], 6),
+        "diagnostics": diag,
         "stages_ms_per_step": {s: round(v[0] / 3, 4) for s, v in stages.items()},
+    }
+    print(json.dumps(rec), flush=True)
+
+# ----------------------------------------------------------- precision form
+def bench_precision(args):
+    """4M x 768 normalised rows stored as float32, bfloat16 and FP8 e4m3 with
+    row scales; 256 queries per call; IP top-k for k in {10, 100} at
+    selectivity 1% and 30%.  The float32 form's ids equal the FP64 oracle on
+    the float32 rows (checked on sampled queries); the bf16 / FP8 forms' ids
+    are exact for their stored rows and are reported against the float32
+    form: recall@k, and the largest |returned distance - FP64 distance of the
+    same row on the float32 rows|."""
+    import torch
+
+    import oracle as O
+    from paper_2403_15807_amd import inputs, vrs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    n, d, B = args.n or 4_000_000, args.d or 768, args.batch or 256
+    t0 = time.time()
+    x = inputs.table(2, n, d, 2000)
+    attr = inputs.attributes(2, n, 2, ATTR)
+    q = inputs.queries(2, B, d, 2000)
+    log(f"generated {n}x{d} in {time.time() - t0:.1f}s")
+    xd, ad = torch.from_numpy(x).to(dev), torch.from_numpy(attr).to(dev)
+    tables = {name: vrs.Table(xd, ad, store=st, normalize=True)
+              for name, st in (("f32", vrs.F32), ("bf16", vrs.BF16), ("fp8", vrs.FP8E4M3))}
+    del xd
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    qd = torch.from_numpy(q).to(dev)
+    cores = len(os.sched_getaffinity(0))
+    ot = O.Table.build(x, attr, O.F32, normalize=True)  # the float32 rows (R2)
+    rows = np.arange(min(B, args.cpu_queries or cores))
+    results, head = [], None
+    for sel, k in ((0.01, 10), (0.01, 100), (0.3, 10), (0.3, 100)):
+        w = inputs.two_term_width(sel, ATTR)
+        pred = [(0, 0, w), (1, 0, w)]
+        n_sel = int(tables["f32"].select(pred).numel())
+        ref_ids = ref_d = None
+        for name in ("f32", "bf16", "fp8"):
+            T = tables[name]
+            o = vrs.vrs_opts()
+            ws = T.workspace(B, k, o)
+            r = T.scan_topk(qd, pred, k, vrs.IP, ws=ws)
+            torch.cuda.synchronize()
+            vrs.stage_times()
+            vrs.profile(True)
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                T.scan_topk(qd, pred, k, vrs.IP, ws=ws)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            vrs.profile(False)
+            stg = vrs.stage_times()
+            rd = T.scan_topk(qd, pred, k, vrs.IP, ws=ws, diag=True)
+            torch.cuda.synchronize()
+            ids, dist = rd.idx.cpu().numpy(), rd.dist.cpu().numpy().astype(np.float64)
+            gather = stg["select"][1] > 0
+            sms = stg["screen"][0] / max(1, stg["screen"][1])
+            nl = max(1, round(stg["screen"][1] / args.steps))
+            roof = roofline(n_sel, n, d, B, name, gather, 2, sms, nl)
+            e = {"store": name, "sel": sel, "k": k, "qps": round(B * args.steps / el, 1),
+                 "ms": round(el * 1e3 / args.steps, 4), "screen_ms": round(sms * nl, 4),
+                 "strategy": "gather" if gather else "mask", "bound": roof["bound"], "frac": roof["frac"],
+                 "certified_frac": float(rd.certified.float().mean().item()),
+                 "err_ratio_max": float(rd.err_ratio.max().item())}
+            if name == "f32":
+                ref_ids, ref_d = ids, dist
+                orc = O.scan_topk(ot, q[rows], pred, k, O.IP, nthreads=cores)
+                e["ids_match_fp64_oracle_on_sample"] = bool(np.array_equal(orc[0], ids[rows]))
+                e["oracle_sample"] = int(rows.size)
+            else:
+                rec_ = [len(set(ids[b][ids[b] >= 0]) & set(ref_ids[b][ref_ids[b] >= 0])) /
+                        max(1, int((ref_ids[b] >= 0).sum())) for b in range(B)]
+                err = 0.0
+                for b in range(B):
+                    v = ids[b] >= 0
+                    if v.any():
+                        d64 = O.distances(ot, q[b], ids[b][v], O.IP)
+                        err = max(err, float(np.max(np.abs(dist[b][v] - d64))))
+                e["recall_at_k_vs_fp32_form"] = round(float(np.mean(rec_)), 4)
+                e["max_abs_dist_error_vs_fp64_on_fp32_rows"] = err
+            results.append(e)
+            log(json.dumps(e))
+            if name == "bf16" and sel == 0.3 and k == 100:
+                head = (e, roof)
+    e, roof = head
+    kname = "screen_mfma_bf16"
+    wkey = f"scan-{n}x{d}-bf16-ip-b{B}-s0.3-k100-{e['strategy']}"
+    roof["traffic"] = traffic_from_profiles(kname, wkey)
+    roof["kernel"] = kname
+    roof["traffic_key"] = wkey
+    rec = {
+        "metric": "filtered exact top-k queries/s (precision form)",
+        "value": e["qps"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": e["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"clustered-gaussian N={n} d={d} normalised, stored f32 / bf16 / fp8, "
+                               f"IP, batch {B}, k in {{10, 100}}, selectivity 1% and 30%; value = bf16, 30%, k=100",
+                   "batch": B},
+        "roofline": roof,
+        "precision": results,
+        "note": "ids of every form are exact for its stored rows; recall and distance error compare the "
+                "bf16/fp8 forms with the float32 form (= FP64 oracle on the float32 rows)",
     }
     print(json.dumps(rec), flush=True)
 
@@ -456,7 +624,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["scan", "batched"], default="scan")
+    ap.add_argument("--workload", choices=["scan", "batched", "precision"], default="scan")
     ap.add_argument("--n", type=int, default=0, help="rows (default 10M scan, 2M batched)")
     ap.add_argument("--d", type=int, default=0, help="dimension (default 128 scan, 1536 batched)")
     ap.add_argument("--clusters", type=int, default=1000)
@@ -492,6 +660,8 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         bench_batched(args)
+    elif args.workload == "precision":
+        bench_precision(args)
     else:
         bench_scan(args)
 

@@ -101,7 +101,14 @@ enum { VRS_CHOOSER_LEARNED = 0, VRS_CHOOSER_HEURISTIC = 1 };
  *                every row chunk, a merge whose K-th key then bounds every
  *                chunk, the rest of every chunk); 0 = two when a chunk holds
  *                at least 2048 rows.  Results do not depend on it; streaming
- *                tiles always use one pass. */
+ *                tiles always use one pass.
+ *   err_ratio:   [B] float out, or NULL: a diagnostic of the certificate's
+ *                screening error model.  For query b, the largest
+ *                |screening distance - exact distance| / E over its reranked
+ *                keys (the k' survivors and the (k'+1)-th key, whose exact
+ *                distance is then computed as well), where E is the bound the
+ *                certificate uses for that distance.  Values below 1 mean the
+ *                model held on every key seen. */
 typedef struct {
     int32_t strategy;
     int32_t tile;
@@ -110,6 +117,8 @@ typedef struct {
     int32_t *n_valid;
     uint8_t *certified;
     int32_t passes;
+    int32_t _pad;
+    float *err_ratio;
 } vrs_opts;
 
 /* Build a table (the column store of Section 3) from float32 rows.

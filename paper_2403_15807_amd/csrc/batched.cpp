@@ -283,11 +283,13 @@ hipError_t run_batched(const vrs_table_s *t, const float *q, int B, const vrs_pr
     fa.rr_dist = (double *)(w + P.o_rrdist);
     fa.rr_count = (int32_t *)(w + P.o_rrcnt);
     // Screening error: the larger of the two kernels' models (the sparse
-    // kernel is the VALU form, the dense one the MFMA form).
-    const double u32 = ldexp(1.0, -24), u64 = ldexp(1.0, -53);
+    // kernel is the VALU form with IEEE round-to-nearest, unit roundoff
+    // 2^-24; the dense one the MFMA form, whose internal rounding is only
+    // assumed faithful, unit roundoff 2^-23).
+    const double u32 = ldexp(1.0, -24), u64 = ldexp(1.0, -53), um = ldexp(1.0, -23);
     const double g = (gamma_n(t->dp + 3, u32) + gamma_n(t->dp + 3, u64)) * 1.001;
-    const double g6 = (gamma_n(t->dp + 6, u32) + gamma_n(t->dp + 3, u64)) * 1.001;
-    const double gb = (gamma_n(t->dp + 2, u32) * (1.0 + ldexp(1.0, -7)) + ldexp(1.0, -16) + 3.0 * u32 +
+    const double g6 = (gamma_n(t->dp + 6, um) + gamma_n(t->dp + 3, u64)) * 1.001;
+    const double gb = (gamma_n(t->dp + 2, um) * (1.0 + ldexp(1.0, -7)) + ldexp(1.0, -16) + 3.0 * um +
                        gamma_n(t->dp + 2, u64)) * 1.001;
     fa.rel = metric == VRS_L2SQ ? g : 0.0;
     fa.abs_l2 = metric == VRS_L2SQ ? g6 : 0.0;
@@ -299,6 +301,7 @@ hipError_t run_batched(const vrs_table_s *t, const float *q, int B, const vrs_pr
     fa.out_dist = out_dist;
     fa.n_valid = opts ? opts->n_valid : nullptr;
     fa.certified = opts ? opts->certified : nullptr;
+    fa.err_ratio = opts ? opts->err_ratio : nullptr;
     fa.fb_rows_per_chunk = P.fb_rows_per_chunk;
     fa.fb_chunks = P.fb_chunks;
     fa.fb_slots = B;

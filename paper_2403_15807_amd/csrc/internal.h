@@ -322,6 +322,9 @@ struct FinishArgs {
     float *out_dist;
     int32_t *n_valid;
     uint8_t *certified;
+    // [B] out or null: largest |screening distance - exact distance| / bound
+    // over the query's reranked keys (the k' survivors and the (k'+1)-th key)
+    float *err_ratio;
     // exact fallback
     int32_t fb_rows_per_chunk, fb_chunks, fb_slots;
     uint64_t *fb_partials;         // [fb_slots][fb_chunks][kmax][2]

@@ -358,22 +358,25 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
 }
 
 // ----------------------------------------------------------------- rerank
-// Workgroup s of query b takes rounds g = s, s + S, ... of RR_ROWS of the
-// query's first k' screening keys, RR_WROWS candidates per wave.  Lane c of
-// a wave loads the 16-byte blocks c, c + 64, ... of each of its wave's rows
-// (one coalesced load per row and 64 blocks, RR_NW windows of them in flight)
-// and accumulates the exact FP64 formula over its blocks' coordinates for
-// every row; a butterfly over the 64 lanes then sums the partial sums (the
-// same association in every lane, so the value is fixed by the inputs).
-// Spreading one query's candidates over several workgroups (small batches)
-// puts several CUs' load queues on the scattered rows.  The last workgroup
-// of a query to finish (an arrival counter, zeroed by the final merge level)
-// ranks the candidates by exact distance, checks the certificate and writes
-// the result.
-constexpr int RR_WROWS = 8;
+// One candidate per lane, so that every exact distance is the definition's
+// single chain: coordinates in ascending order, one fused multiply-add each
+// (the same order as exact_dist and the fallback; a different association
+// can round differently, and rows with equal exact distances would then
+// rank differently).  A task is 64 consecutive candidates of a query, taken
+// by one wave; workgroup s of S takes tasks s, s + S, ... over its waves.
+// The wave stages its 64 rows through its own LDS area one 128-byte column
+// chunk at a time (coalesced 16-byte loads: eight lanes per row chunk, two
+// chunks in flight in registers), then every lane runs its chain over its
+// row's chunk.  Spreading one query's tasks over several workgroups (small
+// batches) puts several CUs' load queues on the scattered rows.  The last
+// workgroup of a query to finish (an arrival counter, zeroed by the final
+// merge level) ranks the candidates by exact distance, checks the
+// certificate and writes the result.
 constexpr int RR_THREADS = 512;
-constexpr int RR_ROWS = RR_WROWS * (RR_THREADS / 64);
-constexpr int RR_NW = 2;
+constexpr int RR_WAVES = RR_THREADS / 64;
+constexpr int RR_CHUNK = 128;                  // bytes of a row staged per step
+constexpr int RR_STRIDE = RR_CHUNK / 16 + 1;   // 16-byte slots per staged row (one pad slot)
+constexpr size_t RR_STAGE_BYTES = (size_t)RR_WAVES * 64 * RR_STRIDE * 16;
 // k' <= 1024 = 2 RR_THREADS: the candidate sort holds at most two keys per thread
 static_assert(2 * RR_THREADS >= 1024, "rerank sort width");
 typedef unsigned int rr_u32x4 __attribute__((ext_vector_type(4)));
@@ -467,99 +470,112 @@ __device__ void rr_sort(const Key128 *cand, int n, int kb, Key128 *srt, uint64_t
     }
 }
 
+// LDS of the rerank: the FP64 query [dp], then one area used first for the
+// waves' row staging and afterwards (every wave done) for the sort buffers,
+// the candidates and the ranked result.
+__host__ __device__ inline size_t rr_sort_bytes(int K) {
+    return (size_t)2 * RR_THREADS * 12 + (size_t)2 * ((K + 7) & ~7) * sizeof(Key128);
+}
+__host__ __device__ inline size_t rr_lds_bytes(int dp, int K) {
+    const size_t sb = rr_sort_bytes(K);
+    return (size_t)dp * 8 + (sb > RR_STAGE_BYTES ? sb : RR_STAGE_BYTES);
+}
+
 template <int STORE, int METRIC>
 __global__ __launch_bounds__(RR_THREADS) void rerank_kernel(FinishArgs a) {
-    constexpr int V = STORE == VRS_F32 ? 4 : (STORE == VRS_BF16 ? 8 : 16);
+    constexpr int V = STORE == VRS_F32 ? 4 : (STORE == VRS_BF16 ? 8 : 16);  // elements per 16 B
     constexpr int EB = 16 / V;
     constexpr int T = RR_THREADS;
+    constexpr int SLOTS = RR_CHUNK / 16;      // 16-byte slots per staged row chunk
+    constexpr int CE = RR_CHUNK / EB;         // coordinates per chunk
     const int s = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int kpb = kp_of(a, b);
-    // workgroup s takes candidate groups s, s + S, ... (S = gridDim.x); ns of
-    // them have work for query b
+    // the k' survivors, and with error diagnostics also the (k'+1)-th key
+    const int nc = kpb + (a.err_ratio ? 1 : 0);
+    const int ntask = (nc + 63) / 64;
     const int S = gridDim.x;
-    const int ns = min(S, (kpb + RR_ROWS - 1) / RR_ROWS);
+    const int ns = min(S, ntask);  // workgroups with work for query b
     if (s >= ns) return;
     const int ob = a.perm ? a.perm[b] : b;  // the query at position b
     extern __shared__ __align__(16) unsigned char smem[];
-    // exchange buffers of the sort, the query, the candidates, the result
-    uint64_t *xh = (uint64_t *)smem;                       // [2T]
-    uint32_t *xl = (uint32_t *)(xh + 2 * T);               // [2T]
-    float *qrow = (float *)(xl + 2 * T);                   // [dp]
-    Key128 *cand = (Key128 *)(qrow + ((a.dp + 3) & ~3));  // [round8(k')] (last workgroup)
-    Key128 *srt = cand + ((a.K + 7) & ~7);                 // [k] in exact order
-    __shared__ int last_s, n_cand_s;
-    for (int j = tid; j < a.dp; j += T) qrow[j] = j < a.d ? a.q[(int64_t)ob * a.d + j] : 0.0f;
-    if (tid == 0) n_cand_s = 0;
+    double *qd = (double *)smem;                                  // [dp]
+    unsigned char *area = smem + (size_t)a.dp * 8;
+    rr_u32x4 *stage = (rr_u32x4 *)area + (size_t)wave * 64 * RR_STRIDE;  // this wave's rows
+    uint64_t *xh = (uint64_t *)area;                              // [2T]   (final phase)
+    uint32_t *xl = (uint32_t *)(xh + 2 * T);                      // [2T]
+    Key128 *cand = (Key128 *)(xl + 2 * T);                        // [round8(K)]
+    Key128 *srt = cand + ((a.K + 7) & ~7);                        // [k] in exact order
+    __shared__ int last_s, n_cand_s, ratio_s;
+    for (int j = tid; j < a.dp; j += T) qd[j] = j < a.d ? (double)a.q[(int64_t)ob * a.d + j] : 0.0;
+    if (tid == 0) {
+        n_cand_s = 0;
+        ratio_s = 0;
+    }
     __syncthreads();
     const uint64_t *lst = a.merged + (int64_t)b * a.K;
-    const int nb16 = a.dp / V;  // 16-byte blocks per row
+    const int nch = a.dp * EB / RR_CHUNK;  // whole chunks: a row is whole 128-byte blocks
     const int64_t row_bytes = (int64_t)a.dp * EB;
     double *dist = a.rr_dist + (int64_t)b * a.K;
-    for (int g = s; g * RR_ROWS < kpb; g += S) {
-        const int ci0 = g * RR_ROWS + wave * RR_WROWS;
-        if (ci0 >= kpb) break;  // (waves are independent here)
-        // candidate rows (a slot without a candidate reads row 0 and drops it)
-        const char *rp[RR_WROWS];
-        double sc[RR_WROWS];
-        bool has[RR_WROWS];
+    for (int t = s + S * wave; t < ntask; t += S * RR_WAVES) {
+        const int ci = t * 64 + lane;
+        const uint64_t key = ci < nc ? lst[ci] : KEY_INF;
+        const bool has = key != KEY_INF;
+        // a lane without a candidate stages row 0 and drops its value
+        const int row = has ? (int)(uint32_t)key : 0;
+        const double sc = (STORE == VRS_FP8E4M3 && has) ? (double)a.scale[row] : 1.0;
+        // the rows this lane stages: i * 8 + lane / 8, 16-byte slot lane % 8
+        const char *src[8];
 #pragma unroll
-        for (int r = 0; r < RR_WROWS; ++r) {
-            const int ci = ci0 + r;
-            const uint64_t key = lst[min(ci, kpb - 1)];
-            const int64_t row = (ci < kpb && key != KEY_INF) ? (int64_t)(uint32_t)key : -1;
-            rp[r] = (const char *)a.rows + (row < 0 ? 0 : row) * row_bytes;
-            has[r] = row >= 0;
-            sc[r] = (STORE == VRS_FP8E4M3 && row >= 0) ? (double)a.scale[row] : 1.0;
+        for (int i = 0; i < 8; ++i) {
+            const int r = __shfl(row, i * 8 + (lane >> 3));
+            src[i] = (const char *)a.rows + (int64_t)r * row_bytes + (lane & 7) * 16;
         }
-        double acc[RR_WROWS];
+        rr_u32x4 *dst = stage + (lane >> 3) * RR_STRIDE + (lane & 7);
+        const rr_u32x4 *mine = stage + lane * RR_STRIDE;
+        rr_u32x4 wa[8], wb[8];
+        auto load = [&](rr_u32x4(&w)[8], int c) {
 #pragma unroll
-        for (int r = 0; r < RR_WROWS; ++r) acc[r] = 0.0;
-        for (int c0 = 0; c0 < nb16; c0 += 64 * RR_NW) {
-            rr_u32x4 w[RR_NW][RR_WROWS];
+            for (int i = 0; i < 8; ++i) w[i] = *(const rr_u32x4 *)(src[i] + (int64_t)c * RR_CHUNK);
+        };
+        auto put = [&](const rr_u32x4(&w)[8]) {
 #pragma unroll
-            for (int k = 0; k < RR_NW; ++k) {
-                if (c0 + 64 * k >= nb16) break;  // (the same for the whole wave)
-                const int c = min(c0 + 64 * k + lane, nb16 - 1);  // past the row: rereads its last block
+            for (int i = 0; i < 8; ++i) dst[i * 8 * RR_STRIDE] = w[i];
+        };
+        double acc = 0.0;
+        auto chain = [&](int c) {
 #pragma unroll
-                for (int r = 0; r < RR_WROWS; ++r) w[k][r] = *(const rr_u32x4 *)(rp[r] + (int64_t)c * 16);
-            }
+            for (int u = 0; u < SLOTS; ++u) {
+                const rr_u32x4 w = mine[u];
+                float x[V];
+                decode16<STORE>(make_uint4(w.x, w.y, w.z, w.w), x);
+                const double *qq = qd + c * CE + u * V;
 #pragma unroll
-            for (int k = 0; k < RR_NW; ++k) {
-                const int c = c0 + 64 * k + lane;
-                if (c >= nb16) break;
-                double qd[V];
-#pragma unroll
-                for (int v = 0; v < V; ++v) qd[v] = (double)qrow[c * V + v];
-#pragma unroll
-                for (int r = 0; r < RR_WROWS; ++r) {
-                    float x[V];
-                    decode16<STORE>(make_uint4(w[k][r].x, w[k][r].y, w[k][r].z, w[k][r].w), x);
-#pragma unroll
-                    for (int v = 0; v < V; ++v) {
-                        if (METRIC == VRS_L2SQ) {
-                            const double t = qd[v] - sc[r] * (double)x[v];
-                            acc[r] = fma(t, t, acc[r]);
-                        } else {
-                            acc[r] = fma(qd[v], (double)x[v], acc[r]);
-                        }
+                for (int v = 0; v < V; ++v) {
+                    if (METRIC == VRS_L2SQ) {
+                        const double tv = qq[v] - sc * (double)x[v];
+                        acc = fma(tv, tv, acc);
+                    } else {
+                        acc = fma(qq[v], (double)x[v], acc);
                     }
                 }
             }
+        };
+        // two chunks in flight: wa holds the even chunks, wb the odd ones.
+        // The LDS area is the wave's own and a wave's LDS accesses complete
+        // in program order, so a chunk is written only after every lane has
+        // read the one before it.
+        load(wa, 0);
+        if (nch > 1) load(wb, 1);
+        for (int c = 0; c < nch; c += 2) {
+            put(wa);
+            if (c + 2 < nch) load(wa, c + 2);
+            chain(c);
+            if (c + 1 >= nch) break;
+            put(wb);
+            if (c + 3 < nch) load(wb, c + 3);
+            chain(c + 1);
         }
-#pragma unroll
-        for (int r = 0; r < RR_WROWS; ++r)
-#pragma unroll
-            for (int m = 32; m > 0; m >>= 1) acc[r] += __shfl_xor(acc[r], m);
-        double mine = 0.0, msc = 1.0;
-        bool mhas = false;
-#pragma unroll
-        for (int r = 0; r < RR_WROWS; ++r)
-            if (lane == r) {
-                mine = acc[r];
-                msc = sc[r];
-                mhas = has[r];
-            }
-        if (lane < RR_WROWS && mhas) dist[ci0 + lane] = METRIC == VRS_IP ? -(msc * mine) : mine;
+        if (ci < nc && has) dist[ci] = METRIC == VRS_IP ? -(sc * acc) : acc;
     }
     // arrival: the last workgroup of query b finishes it (a single workgroup
     // needs no counter and no device-scope fences)
@@ -571,23 +587,37 @@ __global__ __launch_bounds__(RR_THREADS) void rerank_kernel(FinishArgs a) {
         if (!last_s) return;
         __threadfence();
     } else {
-        __syncthreads();  // every wave's distances written
+        __syncthreads();  // every wave's distances written, the staging area free
     }
 
     // the screening keys are sorted with empty slots last, so the candidates
     // are the first n_cand of them
     const int kb = k_of(a, b);
+    const double qn = a.qnorm[b];
+    const double eabs = a.abs_ip * qn * a.max_norm + a.abs_l2 * (qn + a.max_norm) * (qn + a.max_norm);
     int valid = 0;
-    for (int ci = tid; ci < kpb; ci += T) {
+    float ratio = 0.0f;  // largest |screening - exact| / bound over the reranked keys
+    for (int ci = tid; ci < nc; ci += T) {
         const uint64_t key = lst[ci];
-        if (key != KEY_INF) {
-            const double dv = dist[ci];
+        if (key == KEY_INF) continue;
+        const double dv = dist[ci];
+        if (ci < kpb) {
             cand[ci] = Key128{ord64(dv == 0.0 ? 0.0 : dv), (uint64_t)(uint32_t)key};
             ++valid;
         }
+        if (a.err_ratio) {
+            const double sv = (double)unord32((uint32_t)(key >> 32));
+            const double E = a.rel * fabs(dv) + eabs;
+            const double err = fabs(sv - dv);
+            const float r = E > 0.0 ? (float)(err / E) : (err > 0.0 ? __int_as_float(0x7f800000) : 0.0f);
+            ratio = fmaxf(ratio, r);
+        }
     }
     if (valid) atomicAdd(&n_cand_s, valid);
+    // (non-negative floats order like their bit patterns)
+    if (a.err_ratio && ratio > 0.0f) atomicMax(&ratio_s, __float_as_int(ratio));
     __syncthreads();
+    if (a.err_ratio && tid == 0) a.err_ratio[ob] = __int_as_float(ratio_s);
     const int n_cand = n_cand_s;
     if (n_cand <= T)
         rr_sort<1>(cand, n_cand, kb, srt, xh, xl);
@@ -598,9 +628,7 @@ __global__ __launch_bounds__(RR_THREADS) void rerank_kernel(FinishArgs a) {
     const uint64_t akey = lst[kpb];  // (k'+1)-th smallest screening key
     if (akey != KEY_INF && n_cand >= kb) {
         const double av = (double)unord32((uint32_t)(akey >> 32));
-        const double qn = a.qnorm[b];
-        const double E = a.rel * fabs(av) + a.abs_ip * qn * a.max_norm +
-                         a.abs_l2 * (qn + a.max_norm) * (qn + a.max_norm);
+        const double E = a.rel * fabs(av) + eabs;
         ok = unord64(srt[kb - 1].hi) < av - E;
     }
     if (ok) {
@@ -815,14 +843,13 @@ hipError_t launch_merge(const FinishArgs &a, hipStream_t s) {
 
 template <int STORE, int METRIC>
 static hipError_t rerank_t(const FinishArgs &a, hipStream_t s, int kpmax) {
-    const size_t lds = (size_t)2 * RR_THREADS * 12 + (size_t)((a.dp + 3) & ~3) * 4 +
-                       (size_t)2 * ((a.K + 7) & ~7) * sizeof(Key128);
+    const size_t lds = rr_lds_bytes(a.dp, a.K);
     ensure_dyn_lds((const void *)rerank_kernel<STORE, METRIC>, lds);
     // Several workgroups per query when the batch alone cannot fill the GPU
     // (their rows come from many CUs at once); one per query, with no
     // arrival counter or device-scope fence, from 256 queries on.
-    const int groups = (kpmax + RR_ROWS - 1) / RR_ROWS;
-    const int S = std::max(1, std::min(groups, (256 + a.B - 1) / a.B));
+    const int tasks = (kpmax + (a.err_ratio ? 1 : 0) + 63) / 64;
+    const int S = std::max(1, std::min(tasks, (256 + a.B - 1) / a.B));
     rerank_kernel<STORE, METRIC><<<dim3(S, a.B), RR_THREADS, lds, s>>>(a);
     return hipGetLastError();
 }

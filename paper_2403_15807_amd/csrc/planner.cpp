@@ -423,17 +423,24 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     //   MFMA L2SQ: |q|^2 + |x|^2 - 2 q.x with every product possibly rounded
     //              -> absolute gamma_{dp+6} * (|q| + max|x|)^2;
     //   IP:        |error| <= gamma_{dp+3} * |q| * max|x|.
+    // The VALU kernels use IEEE fused multiply-adds rounded to nearest (unit
+    // roundoff u = 2^-24).  For the matrix instructions the internal rounding
+    // of the accumulation is not relied on: the model assumes only that every
+    // operation is faithful (error below one ulp of its result), i.e. unit
+    // roundoff 2^-23; the measured ratio error / bound is reported by the
+    // err_ratio diagnostic.
     const double u32 = ldexp(1.0, -24), u64 = ldexp(1.0, -53);
+    const double um = P.mfma ? ldexp(1.0, -23) : u32;
     const double g = (gamma_n(t->dp + 3, u32) + gamma_n(t->dp + 3, u64)) * 1.001;
-    const double g6 = (gamma_n(t->dp + 6, u32) + gamma_n(t->dp + 3, u64)) * 1.001;
+    const double g6 = (gamma_n(t->dp + 6, um) + gamma_n(t->dp + 3, u64)) * 1.001;
     //   bf16 MFMA IP (hi/lo query split, FP8 scale applied to the sum):
     //              gamma_{dp+2} (1 + 2^-7) + 2^-16 + 3u, times |q| max|x|.
     fa.rel = (metric == VRS_L2SQ && !P.mfma) ? g : 0.0;
     fa.abs_ip = metric == VRS_IP ? g6 : 0.0;
     fa.abs_l2 = (metric == VRS_L2SQ && P.mfma) ? g6 : 0.0;
     if (P.mfma && t->store != VRS_F32)
-        fa.abs_ip = (gamma_n(t->dp + 2, u32) * (1.0 + ldexp(1.0, -7)) + ldexp(1.0, -16) +
-                     3.0 * u32 + gamma_n(t->dp + 2, u64)) * 1.001;
+        fa.abs_ip = (gamma_n(t->dp + 2, um) * (1.0 + ldexp(1.0, -7)) + ldexp(1.0, -16) +
+                     3.0 * um + gamma_n(t->dp + 2, u64)) * 1.001;
     fa.max_norm = t->max_norm;
     fa.fail_list = (int32_t *)(w + P.o_fail);
     fa.fail_count = fail_count;
@@ -441,6 +448,7 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     fa.out_dist = out_dist;
     fa.n_valid = opts ? opts->n_valid : nullptr;
     fa.certified = opts ? opts->certified : nullptr;
+    fa.err_ratio = opts ? opts->err_ratio : nullptr;
     fa.fb_rows_per_chunk = P.fb_rows_per_chunk;
     fa.fb_chunks = P.fb_chunks;
     fa.fb_slots = B;

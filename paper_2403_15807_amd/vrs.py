@@ -57,7 +57,7 @@ class vrs_pred(C.Structure):
 class vrs_opts(C.Structure):
     _fields_ = [("strategy", C.c_int32), ("tile", C.c_int32), ("chooser", C.c_int32),
                 ("kprime_mult", C.c_int32), ("n_valid", C.c_void_p), ("certified", C.c_void_p),
-                ("passes", C.c_int32)]
+                ("passes", C.c_int32), ("_pad", C.c_int32), ("err_ratio", C.c_void_p)]
 
 
 _lib = None
@@ -155,6 +155,7 @@ class ScanResult:
     dist: torch.Tensor
     n_valid: torch.Tensor
     certified: torch.Tensor
+    err_ratio: torch.Tensor | None = None
 
 
 class Table:
@@ -249,19 +250,21 @@ class Table:
                                 _stream(stream)))
         return ids[: int(cnt.item())]
 
-    def _opts(self, B, strategy, tile, chooser, kprime_mult, n_valid, certified, passes=0):
+    def _opts(self, B, strategy, tile, chooser, kprime_mult, n_valid, certified, passes=0, err_ratio=None):
         o = vrs_opts()
         o.strategy, o.tile, o.chooser, o.kprime_mult, o.passes = strategy, tile, chooser, kprime_mult, passes
         o.n_valid = n_valid.data_ptr()
         o.certified = certified.data_ptr()
+        o.err_ratio = None if err_ratio is None else err_ratio.data_ptr()
         return o
 
     def scan_topk(self, q: torch.Tensor, terms, k: int, metric: int = L2SQ, strategy: int = STRATEGY_AUTO,
                   tile: int = -1, chooser: int = CHOOSER_LEARNED, kprime_mult: int = 0,
                   ws: torch.Tensor | None = None, out: tuple | None = None, stream=None,
-                  passes: int = 0) -> ScanResult:
+                  passes: int = 0, diag: bool = False) -> ScanResult:
         """Filtered exact top-k of the queries ``q`` [B, d] (one predicate);
-        ``passes`` forces one- or two-pass MFMA screening (0 = planner's choice)."""
+        ``passes`` forces one- or two-pass MFMA screening (0 = planner's choice);
+        ``diag`` also returns the screening error ratio per query (``err_ratio``)."""
         q = q.contiguous()
         B = q.shape[0]
         if out is None:
@@ -271,13 +274,14 @@ class Table:
             cert = torch.empty(B, dtype=torch.uint8, device="cuda")
         else:
             idx, dist, nv, cert = out
-        o = self._opts(B, strategy, tile, chooser, kprime_mult, nv, cert, passes)
+        er = torch.empty(B, dtype=torch.float32, device="cuda") if diag else None
+        o = self._opts(B, strategy, tile, chooser, kprime_mult, nv, cert, passes, er)
         if ws is None:
             ws = self.workspace(B, k, o)
         p = make_pred(terms)
         _check(lib().vrs_scan_topk(self._h, _ptr(q), B, C.byref(p), k, metric, _ptr(idx), _ptr(dist),
                                    _ptr(ws), ws.numel(), C.byref(o), _stream(stream)))
-        return ScanResult(idx, dist, nv, cert)
+        return ScanResult(idx, dist, nv, cert, er)
 
     def batched_workspace_bytes(self, B: int, k_max: int, metric: int = IP, opts: vrs_opts | None = None) -> int:
         out = C.c_size_t()
@@ -285,7 +289,7 @@ class Table:
                                                  None if opts is None else C.byref(opts), C.byref(out)))
         return out.value
 
-    def _batched_args(self, q, k_max, metric, tile, kprime_mult, ws, out, passes=0):
+    def _batched_args(self, q, k_max, metric, tile, kprime_mult, ws, out, passes=0, err_ratio=None):
         q = q.contiguous()
         B = q.shape[0]
         if out is None:
@@ -294,7 +298,7 @@ class Table:
                    torch.empty(B, dtype=torch.int32, device="cuda"),
                    torch.empty(B, dtype=torch.uint8, device="cuda"))
         idx, dist, nv, cert = out
-        o = self._opts(B, STRATEGY_MASK, tile, CHOOSER_HEURISTIC, kprime_mult, nv, cert, passes)
+        o = self._opts(B, STRATEGY_MASK, tile, CHOOSER_HEURISTIC, kprime_mult, nv, cert, passes, err_ratio)
         if ws is None:
             ws = torch.empty(max(self.batched_workspace_bytes(B, k_max, metric, o), 256), dtype=torch.uint8,
                              device="cuda")
@@ -303,16 +307,18 @@ class Table:
     def scan_topk_batched(self, q: torch.Tensor, preds: torch.Tensor, ks: torch.Tensor, k_max: int,
                           metric: int = IP, tile: int = -1, kprime_mult: int = 0,
                           ws: torch.Tensor | None = None, out: tuple | None = None,
-                          stream=None, passes: int = 0) -> ScanResult:
+                          stream=None, passes: int = 0, diag: bool = False) -> ScanResult:
         """Per-query predicates (``preds_tensor``) and k (int32 device tensor).
         ``tile`` is a batched configuration index (-1: tuned or default);
-        ``passes`` forces one- or two-pass dense screening (0 = by table size)."""
+        ``passes`` forces one- or two-pass dense screening (0 = by table size);
+        ``diag`` also returns the screening error ratio per query."""
+        er = torch.empty(q.shape[0], dtype=torch.float32, device="cuda") if diag else None
         q, B, o, ws, (idx, dist, nv, cert) = self._batched_args(q, k_max, metric, tile, kprime_mult, ws, out,
-                                                                passes)
+                                                                passes, er)
         _check(lib().vrs_scan_topk_batched(self._h, _ptr(q), B, _ptr(preds), _ptr(ks), k_max, metric,
                                            _ptr(idx), _ptr(dist), _ptr(ws), ws.numel(), C.byref(o),
                                            _stream(stream)))
-        return ScanResult(idx, dist, nv, cert)
+        return ScanResult(idx, dist, nv, cert, er)
 
     def batched_tune(self, q, preds, ks, k_max: int, metric: int = IP, kprime_mult: int = 0,
                      ws=None, out=None, stream=None):

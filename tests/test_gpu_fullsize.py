@@ -30,7 +30,17 @@ def _sample(B):
     return np.unique(np.linspace(0, B - 1, m).astype(int))
 
 
+def _ratio(res, what):
+    # the certificate's screening error model held on every reranked key of
+    # every query of the batch (largest |screening - exact| / bound)
+    er = res.err_ratio.cpu().numpy()
+    cert = res.certified.cpu().numpy()
+    _say(f"{what}: max screening error / bound {er.max():.3e}, certified {cert.mean():.4f}")
+    assert (er < 1.0).all(), f"{what}: screening error exceeds its bound ({er.max()})"
+
+
 def _check(res, ref, rows, what):
+    _ratio(res, what)
     gi = res.idx.cpu().numpy()[rows]
     gd = res.dist.cpu().numpy()[rows]
     assert np.array_equal(res.n_valid.cpu().numpy()[rows], ref[3]), f"{what}: n_valid"
@@ -51,13 +61,14 @@ def cfg1():
     return x, a, T
 
 
-@pytest.mark.parametrize("B,sel", [(1, 1.0), (1, 0.01), (16, 0.1), (1024, 1.0), (1024, 0.1)])
+@pytest.mark.parametrize("B,sel", [(1, 1.0), (1, 0.01), (16, 0.1), (128, 1.0), (128, 0.01), (1024, 1.0),
+                                   (1024, 0.1)])
 def test_10M_x_128_l2_top100(cfg1, B, sel):
     x, a, T = cfg1
     q = inputs.queries(1, B, 128, 1000)
     w = inputs.two_term_width(sel, ATTR)
     pred = [(0, 0, w), (1, 0, w)]
-    r = T.scan_topk(torch.from_numpy(q).cuda(), pred, 100, vrs.L2SQ)
+    r = T.scan_topk(torch.from_numpy(q).cuda(), pred, 100, vrs.L2SQ, diag=True)
     torch.cuda.synchronize()
     rows = _sample(B)
     ot = O.Table(O.F32, x, a)
@@ -73,7 +84,7 @@ def test_10M_x_128_ip_normalised_top100(cfg1, B, sel):
     q = inputs.queries(1, B, 128, 1000, stream_offset=1)
     w = inputs.two_term_width(sel, ATTR)
     pred = [(0, 0, w), (1, 0, w)]
-    r = T.scan_topk(torch.from_numpy(q).cuda(), pred, 100, vrs.IP)
+    r = T.scan_topk(torch.from_numpy(q).cuda(), pred, 100, vrs.IP, diag=True)
     torch.cuda.synchronize()
     rows = _sample(B)
     ot = O.Table.build(x, a, O.F32, normalize=True)
@@ -97,7 +108,7 @@ def test_4M_x_768_precision_form(store):
     for sel, k in ((0.3, 100), (0.01, 10)):
         w = inputs.two_term_width(sel, ATTR)
         pred = [(0, 0, w), (1, 0, w)]
-        r = T.scan_topk(torch.from_numpy(q).cuda(), pred, k, vrs.IP)
+        r = T.scan_topk(torch.from_numpy(q).cuda(), pred, k, vrs.IP, diag=True)
         torch.cuda.synchronize()
         _say(f"oracle sel={sel} k={k}")
         ref = O.scan_topk(ot, q[rows], pred, k, O.IP)
@@ -118,7 +129,7 @@ def test_2M_x_1536_batched_uneven():
     del x
     kmax = int(bp.k.max())
     r = T.scan_topk_batched(torch.from_numpy(q).cuda(), vrs.preds_tensor(preds),
-                            torch.from_numpy(bp.k).cuda(), kmax, vrs.IP)
+                            torch.from_numpy(bp.k).cuda(), kmax, vrs.IP, diag=True)
     torch.cuda.synchronize()
     rows = _sample(B)
     _say("oracle batched")

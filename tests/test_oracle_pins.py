@@ -389,3 +389,68 @@ def test_fraction_exactness_of_fp8_ip_distance():
         exact = -Fraction(float(T.scale[i])) * sum(Fraction(float(a)) * Fraction(float(c))
                                                     for a, c in zip(q, codes[i]))
         assert got[i] == float(exact)
+
+
+# ------------------------------------------------- summation order, pinned
+# The oracle's FP64 distance is one chain over the coordinates in ascending
+# order, one fused multiply-add each.  Emulated here with exact rationals
+# (Python's int division rounds correctly), independently of the C code, on
+# rows whose exact distances tie and whose FP64 sums round differently with
+# the order of the terms.  The same rows ranked by a blockwise butterfly sum
+# (per 16-byte block a chain, then a 64-lane xor butterfly of plain adds)
+# come out in a different order, so the GPU test on these inputs detects a
+# rerank that does not follow the definition's order.
+def _emu_values(ot, i):
+    if ot.dtype == O.F32:
+        return [float(v) for v in ot.rows[i]], 1.0
+    if ot.dtype == O.BF16:
+        return [float(v) for v in O.bf16_values(ot.rows[i])], 1.0
+    return [float(v) for v in O.e4m3_values(ot.rows[i])], float(ot.scale[i])
+
+
+def _emu_fma(a, b, c):
+    return float(Fraction(a) * Fraction(b) + Fraction(c))
+
+
+def _emu_chain(q, xs, sc, l2, js):
+    acc = 0.0
+    for j in js:
+        if l2:
+            t = float(q[j]) - sc * xs[j]
+            acc = _emu_fma(t, t, acc)
+        else:
+            acc = _emu_fma(float(q[j]), xs[j], acc)
+    return acc
+
+
+def _emu_finish(acc, sc, l2):
+    return (acc if l2 else -(sc * acc)) + 0.0
+
+
+@pytest.mark.parametrize("dtype,metric", [(O.F32, O.L2SQ), (O.F32, O.IP), (O.BF16, O.IP), (O.FP8, O.IP)])
+@pytest.mark.parametrize("B,seed", [(1, 13), (16, 27)])
+def test_distance_is_the_ascending_fma_chain_on_tied_rows(dtype, metric, B, seed):
+    import planted
+    x, a, q, pos = planted.planted(metric == O.L2SQ, B, seed)
+    ot = O.Table.build(x, a, dtype)
+    V = {O.F32: 4, O.BF16: 8, O.FP8: 16}[dtype]
+    l2 = metric == O.L2SQ
+    differs = 0
+    for b in range(min(B, 3)):
+        seq, bfly = [], []
+        for p in pos:
+            xs, sc = _emu_values(ot, p)
+            seq.append(_emu_finish(_emu_chain(q[b], xs, sc, l2, range(len(xs))), sc, l2))
+            part = [_emu_chain(q[b], xs, sc, l2, range(c * V, (c + 1) * V)) for c in range(len(xs) // V)]
+            part += [0.0] * (64 - len(part))
+            m = 32
+            while m:
+                part = [part[l_] + part[l_ ^ m] for l_ in range(64)]
+                m //= 2
+            bfly.append(_emu_finish(part[0], sc, l2))
+        seq = np.array(seq)
+        assert np.array_equal(O.distances(ot, q[b], pos, metric), seq)
+        top_seq = np.lexsort((pos, seq))[:100]
+        top_bfly = np.lexsort((pos, np.array(bfly)))[:100]
+        differs += not np.array_equal(top_seq, top_bfly)
+    assert differs > 0
