@@ -70,6 +70,10 @@ def lib():
         L.oracle_scan_topk.argtypes = [C.c_int32, C.c_int64, C.c_int32, P, P, P, P, C.c_int32,
                                        C.c_int32, P, P, P, P, P, C.c_int32, C.c_int32, C.c_int32,
                                        P, P, P, P]
+        L.oracle_scan_range.restype = C.c_int
+        L.oracle_scan_range.argtypes = [C.c_int32, C.c_int64, C.c_int32, P, P, P, P, C.c_int32,
+                                        C.c_int32, P, P, P, P, P, C.c_int32, C.c_int32, C.c_int32,
+                                        P, P, P, P]
         _lib = L
     return _lib
 
@@ -224,3 +228,30 @@ def scan_topk(table: Table, q, preds, k, metric, nthreads=None, out_stride=None)
     if rc != 0:
         raise MemoryError("oracle_scan_topk ran out of memory")
     return idx, dist, dist64, nvalid
+
+
+def scan_range(table: Table, q, preds, thr, cap, metric, nthreads=None):
+    """Threshold selection: for every query, the qualifying rows whose FP64
+    distance is below its threshold, ascending by id.  ``thr``: a float or
+    one per query; ``cap``: ids kept per query.  Returns ``(idx int64
+    [B, cap], dist float32 [B, cap], dist64 float64 [B, cap], count int64
+    [B])``, padded with -1 / +inf; ``count`` counts every selected row."""
+    q = _c(q, np.float32)
+    if q.ndim == 1:
+        q = q[None, :]
+    B, d = q.shape
+    assert d == table.d
+    th = np.ascontiguousarray(np.broadcast_to(np.asarray(thr, dtype=np.float64), (B,)))
+    tmax, nterms, cols, lo, hi = _terms(preds, B)
+    cap = int(cap)
+    idx = np.empty((B, max(cap, 1)), dtype=np.int64)
+    dist = np.empty((B, max(cap, 1)), dtype=np.float32)
+    dist64 = np.empty((B, max(cap, 1)), dtype=np.float64)
+    count = np.empty(B, dtype=np.int64)
+    if nthreads is None:
+        nthreads = len(os.sched_getaffinity(0))
+    lib().oracle_scan_range(table.dtype, table.n, table.d, _p(table.rows), _p(table.scale),
+                            _p(table.attr), _p(q), B, tmax, _p(nterms), _p(cols), _p(lo), _p(hi),
+                            _p(th), cap, int(metric), int(nthreads), _p(idx), _p(dist), _p(dist64),
+                            _p(count))
+    return idx[:, :cap], dist[:, :cap], dist64[:, :cap], count

@@ -409,6 +409,11 @@ typedef struct {
     float *out_dist;
     double *out_dist64;
     int64_t *out_nvalid;
+    /* threshold selection (range_mode = 1): thr[b], at most out_stride ids
+     * per query, counts[b] = number of qualifying rows below the threshold */
+    int32_t range_mode;
+    const double *thr;
+    int64_t *out_count;
     int64_t next;              /* next query to take (guarded by mu) */
     pthread_mutex_t mu;
     int failed;
@@ -459,6 +464,43 @@ static int one_query(job_t *J, int32_t b)
     return 0;
 }
 
+/* Threshold selection for query b: the qualifying rows i, ascending, whose
+ * FP64 distance is below thr[b]; the first out_stride of them are written,
+ * the rest of the row is padded with (-1, +inf); out_count[b] counts all. */
+static int one_query_range(job_t *J, int32_t b)
+{
+    const table_t *T = J->T;
+    const float *q = J->q + (int64_t)b * T->d;
+    const int32_t nt = J->nterms[b];
+    const int32_t *cols = J->cols + (int64_t)b * J->nterms_max;
+    const int64_t *lo = J->lo + (int64_t)b * J->nterms_max;
+    const int64_t *hi = J->hi + (int64_t)b * J->nterms_max;
+    int64_t *oi = J->out_idx + (int64_t)b * J->out_stride;
+    float *od = J->out_dist + (int64_t)b * J->out_stride;
+    double *od64 = J->out_dist64 ? J->out_dist64 + (int64_t)b * J->out_stride : NULL;
+    int64_t c = 0;
+    for (int64_t i = 0; i < T->n; i++) {
+        if (!qualifies(J->attr, T->n, i, nt, cols, lo, hi))
+            continue;
+        double dv = dist64(T, q, i, J->metric);
+        if (!(dv < J->thr[b]))
+            continue;
+        if (c < J->out_stride) {
+            oi[c] = i;
+            od[c] = (float)dv;
+            if (od64) od64[c] = dv;
+        }
+        c++;
+    }
+    for (int64_t r = c; r < J->out_stride; r++) {
+        oi[r] = -1;
+        od[r] = INFINITY;
+        if (od64) od64[r] = INFINITY;
+    }
+    J->out_count[b] = c;
+    return 0;
+}
+
 static void *worker(void *arg)
 {
     job_t *J = (job_t *)arg;
@@ -468,13 +510,35 @@ static void *worker(void *arg)
         pthread_mutex_unlock(&J->mu);
         if (b >= J->B)
             break;
-        if (one_query(J, (int32_t)b) != 0) {
+        if ((J->range_mode ? one_query_range(J, (int32_t)b) : one_query(J, (int32_t)b)) != 0) {
             pthread_mutex_lock(&J->mu);
             J->failed = 1;
             pthread_mutex_unlock(&J->mu);
         }
     }
     return NULL;
+}
+
+/* Run J's queries on nthreads threads (the caller's thread included). */
+static int run_job(job_t *J, int32_t nthreads)
+{
+    pthread_mutex_init(&J->mu, NULL);
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > J->B)
+        nthreads = J->B > 0 ? J->B : 1;
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+    char *ok = (char *)calloc((size_t)nthreads, 1);
+    for (int t = 1; t < nthreads; t++)
+        ok[t] = pthread_create(&th[t], NULL, worker, J) == 0;
+    worker(J); /* the calling thread takes part too */
+    for (int t = 1; t < nthreads; t++)
+        if (ok[t])
+            pthread_join(th[t], NULL);
+    free(ok);
+    free(th);
+    pthread_mutex_destroy(&J->mu);
+    return J->failed ? -1 : 0;
 }
 
 /*
@@ -513,21 +577,49 @@ int oracle_scan_topk(int32_t dtype, int64_t n, int32_t d, const void *rows, cons
     J.out_dist = out_dist;
     J.out_dist64 = out_dist64;
     J.out_nvalid = out_nvalid;
-    pthread_mutex_init(&J.mu, NULL);
-    if (nthreads < 1)
-        nthreads = 1;
-    if (nthreads > B)
-        nthreads = B > 0 ? B : 1;
-    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
-    char *ok = (char *)calloc((size_t)nthreads, 1);
-    for (int t = 1; t < nthreads; t++)
-        ok[t] = pthread_create(&th[t], NULL, worker, &J) == 0;
-    worker(&J); /* the calling thread takes part too */
-    for (int t = 1; t < nthreads; t++)
-        if (ok[t])
-            pthread_join(th[t], NULL);
-    free(ok);
-    free(th);
-    pthread_mutex_destroy(&J.mu);
-    return J.failed ? -1 : 0;
+    return run_job(&J, nthreads);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Threshold selection (eq. 1 and eq. 3 with eps = "distance below a         */
+/* threshold"; the evaluation's similarity predicate is a cosine-similarity  */
+/* threshold, Section 5 "Dataset": on normalised rows and a normalised query */
+/* cosine similarity > t is IP distance < -t)                                */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * For B queries, each with its own predicate and threshold thr[b]: the
+ * qualifying rows whose FP64 distance is below thr[b], ascending by row id.
+ *   outputs : [B][cap] ids (int64), float32 and FP64 distances (the first
+ *             cap rows; the rest padded with -1 / +inf), counts[b] = number
+ *             of rows selected (may exceed cap).
+ * Returns 0.
+ */
+int oracle_scan_range(int32_t dtype, int64_t n, int32_t d, const void *rows, const float *scale,
+                      const int32_t *attr, const float *q, int32_t B, int32_t nterms_max,
+                      const int32_t *nterms, const int32_t *cols, const int64_t *lo, const int64_t *hi,
+                      const double *thr, int32_t cap, int32_t metric, int32_t nthreads,
+                      int64_t *out_idx, float *out_dist, double *out_dist64, int64_t *out_count)
+{
+    table_t T = {dtype, d, n, (const float *)rows, (const uint16_t *)rows, (const uint8_t *)rows, scale};
+    job_t J;
+    memset(&J, 0, sizeof J);
+    J.T = &T;
+    J.attr = attr;
+    J.q = q;
+    J.B = B;
+    J.nterms_max = nterms_max;
+    J.nterms = nterms;
+    J.cols = cols;
+    J.lo = lo;
+    J.hi = hi;
+    J.out_stride = cap;
+    J.metric = metric;
+    J.out_idx = out_idx;
+    J.out_dist = out_dist;
+    J.out_dist64 = out_dist64;
+    J.range_mode = 1;
+    J.thr = thr;
+    J.out_count = out_count;
+    return run_job(&J, nthreads);
 }
