@@ -255,3 +255,22 @@ def scan_range(table: Table, q, preds, thr, cap, metric, nthreads=None):
                             _p(th), cap, int(metric), int(nthreads), _p(idx), _p(dist), _p(dist64),
                             _p(count))
     return idx[:, :cap], dist[:, :cap], dist64[:, :cap], count
+
+
+def stored_as_f32(table: Table) -> np.ndarray:
+    """The stored vectors as float32 rows: float32 and bfloat16 values are
+    exact; an FP8 value (scale * code) is rounded to the nearest float32."""
+    if table.dtype == F32:
+        return table.rows.copy()
+    if table.dtype == BF16:
+        return bf16_values(table.rows).reshape(table.n, table.d).astype(np.float32)
+    vals = e4m3_values(table.rows).reshape(table.n, table.d)
+    return (vals * table.scale.astype(np.float64)[:, None]).astype(np.float32)
+
+
+def join_topk(r_table: Table, s_table: Table, preds, k, metric, nthreads=None):
+    """Vector join: for every row of ``r_table`` (its stored vector as a
+    float32 query), the exact filtered top-k rows of ``s_table``.  Returns
+    what ``scan_topk`` returns, one row per row of ``r_table``."""
+    assert r_table.d == s_table.d
+    return scan_topk(s_table, stored_as_f32(r_table), preds, k, metric, nthreads=nthreads)
