@@ -274,3 +274,95 @@ def join_topk(r_table: Table, s_table: Table, preds, k, metric, nthreads=None):
     what ``scan_topk`` returns, one row per row of ``r_table``."""
     assert r_table.d == s_table.d
     return scan_topk(s_table, stored_as_f32(r_table), preds, k, metric, nthreads=nthreads)
+
+
+# ------------------------------------------------------------ probe path
+# A partition index over the vector column (the probe-based access path of
+# Section 4: data organised so that similar vectors sit together; here
+# k-means partitions, squared L2 on the stored vectors) and its filtered
+# probe with pre-filtering (Section 4.1: the relational predicate decides
+# which rows may enter the result, not which partitions are visited).
+
+def _nearest_centroid(x32, cent):
+    """Exact nearest centroid of every row by (FP64 squared L2, centroid id)."""
+    zr = np.zeros((1, x32.shape[0]), np.int32)
+    zc = np.zeros((1, cent.shape[0]), np.int32)
+    idx = join_topk(Table(F32, x32, zr), Table(F32, cent, zc), [], 1, L2SQ)[0]
+    return idx[:, 0].astype(np.int32)
+
+
+def _centroid_means(x32, assign, old):
+    """Mean of each partition's rows: FP64 running sum in ascending row
+    order, divided by the count, rounded to float32; an empty partition keeps
+    its previous centroid."""
+    cent = old.copy()
+    for c in range(old.shape[0]):
+        members = np.nonzero(assign == c)[0]
+        if members.size:
+            s = np.cumsum(x32[members].astype(np.float64), axis=0)[-1]
+            cent[c] = (s / float(members.size)).astype(np.float32)
+    return cent
+
+
+def ivf_build(table: Table, nlist: int, iters: int):
+    """k-means partition index: initial centroids are the stored rows at
+    positions floor(i n / nlist); each iteration assigns every row to its
+    exact nearest centroid and moves the centroids to their partitions'
+    means; the final assignment uses the final centroids.  Returns
+    (centroids float32 [nlist, d], assign int32 [n], list_off int64
+    [nlist + 1], list_ids int32 [n]) with every partition's rows ascending."""
+    x32 = stored_as_f32(table)
+    n = table.n
+    cent = x32[[(i * n) // nlist for i in range(nlist)]].copy()
+    for _ in range(iters):
+        cent = _centroid_means(x32, _nearest_centroid(x32, cent), cent)
+    assign = _nearest_centroid(x32, cent)
+    order = np.argsort(assign, kind="stable").astype(np.int32)
+    counts = np.bincount(assign, minlength=nlist)
+    list_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    return cent, assign, list_off, order
+
+
+def ivf_probe(table: Table, cent, list_off, list_ids, q, preds, k, metric, nprobe, min_cand, cap_c):
+    """Filtered probe: each query visits the partitions of its nprobe nearest
+    centroids (exact, by FP64 squared L2 and centroid id) in that order; a
+    visited partition contributes its rows that satisfy the predicate.  The
+    walk stops once min_cand rows qualified, or before a partition would
+    take the rows visited past cap_c (the first partition is always taken).
+    The result is the exact top-k of the collected rows by (FP64 distance,
+    id).  Returns (idx int64 [B, k], dist float32 [B, k], lists taken int64
+    [B], candidates int64 [B])."""
+    q = _c(q, np.float32)
+    B = q.shape[0]
+    zc = np.zeros((1, cent.shape[0]), np.int32)
+    coarse = scan_topk(Table(F32, cent, zc), q, [], nprobe, L2SQ)[0]
+    _, nterms, cols, lo, hi = _terms(preds, B)
+    idx = np.full((B, k), -1, np.int64)
+    dist = np.full((B, k), np.inf, np.float32)
+    taken = np.zeros(B, np.int64)
+    ncand = np.zeros(B, np.int64)
+    for b in range(B):
+        cand, visited = [], 0
+        for lst in coarse[b]:
+            if lst < 0:
+                break
+            members = list_ids[list_off[lst]:list_off[lst + 1]]
+            if taken[b] >= 1 and visited + members.size > cap_c:
+                break
+            ok = np.ones(members.size, bool)
+            for t in range(nterms[b]):
+                v = table.attr[cols[b, t], members].astype(np.int64)
+                ok &= (lo[b, t] <= v) & (v < hi[b, t])
+            cand.extend(members[ok].tolist())
+            visited += members.size
+            taken[b] += 1
+            if len(cand) >= min_cand:
+                break
+        ncand[b] = len(cand)
+        if cand:
+            ids = np.array(cand, np.int64)
+            d64 = distances(table, q[b], ids, metric)
+            order = np.lexsort((ids, d64))[:k]
+            idx[b, :order.size] = ids[order]
+            dist[b, :order.size] = d64[order].astype(np.float32)
+    return idx, dist, taken, ncand
