@@ -428,9 +428,9 @@ def bench_batched(args):
            torch.empty(B, dtype=torch.int32, device=dev), torch.empty(B, dtype=torch.uint8, device=dev))
     ws = torch.empty(T.batched_workspace_bytes(B, kmax, vrs.IP), dtype=torch.uint8, device=dev)
     t0 = time.time()
-    best, cfg_ms, _ = T.batched_tune(qd, pd, kd, kmax, vrs.IP, ws=ws, out=out)
+    best, cfg_ms, _ = T.batched_tune(qd, pd, kd, kmax, vrs.IP, ws=ws, out=out, kprime_mult=args.kprime_mult)
     log(f"autotuned in {time.time() - t0:.1f}s: config {best}, ms {['%.2f' % m for m in cfg_ms]}")
-    G = T.batched_graph(qd, pd, kd, kmax, vrs.IP, tile=best, ws=ws, out=out)
+    G = T.batched_graph(qd, pd, kd, kmax, vrs.IP, tile=best, ws=ws, out=out, kprime_mult=args.kprime_mult)
     for _ in range(args.warmup):
         G.launch()
     torch.cuda.synchronize()
@@ -447,7 +447,7 @@ def bench_batched(args):
     vrs.stage_times()
     vrs.profile(True)
     for _ in range(3):
-        T.scan_topk_batched(qd, pd, kd, kmax, vrs.IP, tile=best, ws=ws, out=out)
+        T.scan_topk_batched(qd, pd, kd, kmax, vrs.IP, tile=best, ws=ws, out=out, kprime_mult=args.kprime_mult)
     torch.cuda.synchronize()
     vrs.profile(False)
     stages = vrs.stage_times()
@@ -461,11 +461,19 @@ def bench_batched(args):
             "kernel_ms": round(screen_ms / launches, 4), "launches_per_step": launches,
             "screen_ms_per_batch": round(screen_ms, 4), "alg_flops_per_batch": int(pair_flops),
             "note": "algorithmic work = 2 d per qualifying (query, row) pair, over the batch's screening time"}
-    rd = T.scan_topk_batched(qd, pd, kd, kmax, vrs.IP, tile=best, ws=ws, diag=True)
+    rd = T.scan_topk_batched(qd, pd, kd, kmax, vrs.IP, tile=best, ws=ws, diag=True, kprime_mult=args.kprime_mult)
     torch.cuda.synchronize()
+    cert_b = rd.certified.cpu().numpy()
+    sfrac = sel_rows / n
     diag = {"err_ratio_max": float(rd.err_ratio.max().item()),
-            "certified_frac": float(rd.certified.float().mean().item()),
-            "same_ids_as_graph": bool(torch.equal(rd.idx, out[0]))}
+            "certified_frac": float(cert_b.mean()),
+            "same_ids_as_graph": bool(torch.equal(rd.idx, out[0])),
+            "fallbacks_by_k": {int(kk): [int((bp.k == kk).sum()), int(((bp.k == kk) & (cert_b == 0)).sum())]
+                               for kk in np.unique(bp.k)},
+            "fallbacks_by_selectivity_decade": {
+                f"{lo:g}-{lo * 10:g}": [int(((sfrac >= lo) & (sfrac < lo * 10)).sum()),
+                                         int(((sfrac >= lo) & (sfrac < lo * 10) & (cert_b == 0)).sum())]
+                for lo in (1e-5, 1e-4, 1e-3, 1e-2, 1e-1)}}
 
     # the plain path, one launch per query (own predicate and k), on a sample
     m = min(B, args.per_query_sample)
@@ -619,12 +627,251 @@ def bench_precision(args):
     print(json.dumps(rec), flush=True)
 
 
+# ------------------------------------------------------- threshold selection
+def bench_range(args):
+    """Threshold selection on the 10M x 128 table: cosine similarity > t (IP
+    distance < -t on L2-normalised rows and queries), the evaluation's
+    similarity predicate of the paper (Section 5), with the two-term range
+    predicate of the requested selectivity."""
+    import torch
+
+    import oracle as O
+    from paper_2403_15807_amd import inputs, vrs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    n, d, B = args.n or 10_000_000, args.d or 128, args.batch or 1
+    t0 = time.time()
+    x = inputs.table(1, n, d, args.clusters)
+    attr = inputs.attributes(1, n, 2, ATTR)
+    q = inputs.queries(1, B, d, args.clusters, stream_offset=3)
+    q = (q / np.linalg.norm(q.astype(np.float64), axis=1, keepdims=True)).astype(np.float32)
+    log(f"generated {n}x{d} in {time.time() - t0:.1f}s")
+    T = vrs.Table(torch.from_numpy(x).to(dev), torch.from_numpy(attr).to(dev), normalize=True)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    qd = torch.from_numpy(q).to(dev)
+    thr = -args.cos
+    w = inputs.two_term_width(args.sel, ATTR)
+    pred = [(0, 0, w), (1, 0, w)]
+    n_sel = int(T.select(pred).numel())
+    cap = args.cap
+    ws = torch.empty(T.range_workspace_bytes(B, cap), dtype=torch.uint8, device=dev)
+    out = (torch.empty((B, cap), dtype=torch.int64, device=dev), torch.empty((B, cap), dtype=torch.float32, device=dev),
+           torch.empty(B, dtype=torch.int64, device=dev))
+    strategy = {"auto": vrs.STRATEGY_AUTO, "mask": vrs.STRATEGY_MASK, "gather": vrs.STRATEGY_GATHER}[args.strategy]
+
+    def step():
+        T.scan_range(qd, pred, thr, cap, vrs.IP, strategy=strategy, ws=ws, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    vrs.stage_times()
+    vrs.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    vrs.profile(False)
+    stages = vrs.stage_times()
+    gather = stages["select"][1] > 0
+    screen_ms = stages["screen"][0] / max(1, stages["screen"][1])
+    roof = roofline(n_sel, n, d, B, "f32", gather, 2, screen_ms)
+    roof["kernel"] = "range_screen"
+    roof["kernel_ms"] = round(screen_ms, 4)
+    roof["traffic"] = None
+    counts = out[2].cpu().numpy()
+    cpu = None
+    if not args.no_cpu:
+        cores = len(os.sched_getaffinity(0))
+        nq = min(B, args.cpu_queries or cores)
+        ot = O.Table.build(x, attr, O.F32, normalize=True)
+        reps = max(1, (args.cpu_queries or cores) // nq)
+        qs = np.ascontiguousarray(np.tile(q[:nq], (reps, 1)))
+        t0 = time.perf_counter()
+        ref = O.scan_range(ot, qs, pred, thr, cap, O.IP, nthreads=cores)
+        cpu_s = time.perf_counter() - t0
+        gi = out[0].cpu().numpy()
+        same = bool(np.array_equal(ref[0][:nq], gi[:nq]) and np.array_equal(ref[3][:nq], counts[:nq]))
+        cpu = {"value": round(qs.shape[0] / cpu_s, 3), "unit": "queries/s", "cores": min(cores, qs.shape[0]),
+               "kind": "oracle", "sample": f"{qs.shape[0]} queries of the same workload, FP64, {cpu_s:.1f}s wall",
+               "gpu_ids_match_oracle": same}
+        log(f"oracle {cpu_s:.1f}s, ids match {same}")
+    rec = {
+        "metric": "threshold selection queries/s (cosine > t, N=10M, d=128)",
+        "value": round(B * args.steps / el, 2), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(el * 1e3 / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"clustered-gaussian N={n} d={d} f32 normalised, cosine > {args.cos}, "
+                               f"2-term predicate selectivity {args.sel:g}", "batch": B, "cap": cap,
+                   "strategy": "gather" if gather else "mask", "selectivity": round(n_sel / n, 6)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "selected_rows_per_query": [int(c) for c in counts[:8]],
+        "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
+    }
+    print(json.dumps(rec), flush=True)
+
+
+# --------------------------------------------------------------- vector join
+def bench_join(args):
+    """kNN join: the first R rows of the 10M x 128 table, each as a query,
+    against the whole table (squared L2, top-k)."""
+    import torch
+
+    import oracle as O
+    from paper_2403_15807_amd import inputs, vrs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    n, d, nr, k = args.n or 10_000_000, args.d or 128, args.join_rows, args.k
+    x = inputs.table(1, n, d, args.clusters)
+    attr = inputs.attributes(1, n, 2, ATTR)
+    S = vrs.Table(torch.from_numpy(x).to(dev), torch.from_numpy(attr).to(dev))
+    R = S.view(nr)
+    torch.cuda.synchronize()
+    w = inputs.two_term_width(args.sel, ATTR)
+    pred = [(0, 0, w), (1, 0, w)]
+    n_sel = int(S.select(pred).numel())
+    ws = torch.empty(R.join_workspace_bytes(S, k), dtype=torch.uint8, device=dev)
+    r = R.join_topk(S, pred, k, vrs.L2SQ, ws=ws)
+    torch.cuda.synchronize()
+    vrs.stage_times()
+    vrs.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = R.join_topk(S, pred, k, vrs.L2SQ, ws=ws)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    vrs.profile(False)
+    stages = vrs.stage_times()
+    screen_ms = stages["screen"][0] / max(1, stages["screen"][1])
+    launches = max(1, round(stages["screen"][1] / args.steps))
+    batches = (nr + 8191) // 8192
+    flops = 2.0 * nr * n_sel * d
+    tf = flops / (stages["screen"][0] / args.steps * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": round(tf, 2), "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / MFMA_F32_PEAK_TFLOPS, 4), "traffic": None, "kernel": "screen_mfma_f32",
+            "kernel_ms": round(screen_ms, 4), "launches_per_step": launches,
+            "note": "2 d flops per (R row, qualifying S row), over the step's screening time"}
+    cpu = None
+    if not args.no_cpu:
+        cores = len(os.sched_getaffinity(0))
+        nq = args.cpu_queries or cores
+        ot = O.Table(O.F32, x, attr)
+        rows = np.linspace(0, nr - 1, nq).astype(int)
+        t0 = time.perf_counter()
+        ref = O.scan_topk(ot, x[rows], pred, k, O.L2SQ, nthreads=cores)
+        cpu_s = time.perf_counter() - t0
+        same = bool(np.array_equal(ref[0], r.idx.cpu().numpy()[rows]))
+        cpu = {"value": round(nq / cpu_s, 3), "unit": "R rows/s", "cores": min(cores, nq), "kind": "oracle",
+               "sample": f"{nq} rows of R against the full table, FP64, {cpu_s:.1f}s wall",
+               "gpu_ids_match_oracle": same}
+        log(f"oracle {cpu_s:.1f}s, ids match {same}")
+    rec = {
+        "metric": "vector join R rows/s (kNN join against N=10M, d=128)",
+        "value": round(nr * args.steps / el, 2), "unit": "R rows/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": round(el * 1e3 / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"first {nr} rows of a clustered-gaussian N={n} d={d} f32 table joined with the "
+                               f"whole table, squared L2, top-{k}, 2-term predicate selectivity {args.sel:g}",
+                   "batches_of_R": batches},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "stages_ms_per_step": {kk: round(v[0] / args.steps, 4) for kk, v in stages.items()},
+    }
+    print(json.dumps(rec), flush=True)
+
+
+# ----------------------------------------------------------- probe vs scan
+def bench_probe(args):
+    """Scan vs probe (Section 5.3's question, Figs. 7-8): a 1M-row table, a
+    one-column range predicate of selectivity 1e-4..1, top-k; the exact scan
+    (the planner's mask or gather) against the filtered probe of a k-means
+    partition index (nprobe nearest partitions, walk extended until k rows
+    qualify), at one query and at a batch; recall of the probe against the
+    scan's exact answer."""
+    import torch
+
+    from paper_2403_15807_amd import inputs, vrs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    n, d, k = args.n or 1_000_000, args.d or 128, args.k
+    nlist, nprobe = args.nlist, args.nprobe
+    x = inputs.table(10, n, d, args.clusters)
+    attr = inputs.attributes(10, n, 1, ATTR)
+    T = vrs.Table(torch.from_numpy(x).to(dev), torch.from_numpy(attr).to(dev))
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ix = vrs.Index(T, nlist, iters=args.iters)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    log(f"index: {nlist} partitions, {args.iters} iterations in {build_s:.2f}s, largest {ix.max_list}")
+    points = []
+    for B in (1, args.probe_batch):
+        q = torch.from_numpy(inputs.queries(10, B, d, args.clusters)).to(dev)
+        for sel in (1e-4, 1e-3, 1e-2, 0.1, 0.5, 1.0):
+            pred = [(0, 0, max(1, int(round(sel * ATTR))))]
+            ex = T.scan_topk(q, pred, k, vrs.L2SQ)
+            ws = torch.empty(ix.workspace_bytes(B, k, nprobe, args.cap_c), dtype=torch.uint8, device=dev)
+            pr = ix.probe_topk(q, pred, k, vrs.L2SQ, nprobe, k, args.cap_c, ws=ws)
+            torch.cuda.synchronize()
+
+            def timed(fn, reps):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                for _ in range(reps):
+                    fn()
+                torch.cuda.synchronize()
+                return (time.perf_counter() - t1) / reps * 1e3
+
+            o = vrs.vrs_opts()
+            sws = T.workspace(B, k, o)
+            scan_ms = timed(lambda: T.scan_topk(q, pred, k, vrs.L2SQ, ws=sws), args.steps)
+            probe_ms = timed(lambda: ix.probe_topk(q, pred, k, vrs.L2SQ, nprobe, k, args.cap_c, ws=ws,
+                                                   out=pr), args.steps)
+            ei, pi = ex.idx.cpu().numpy(), pr[0].cpu().numpy()
+            rec = float(np.mean([len(set(pi[b][pi[b] >= 0]) & set(ei[b][ei[b] >= 0])) /
+                                 max(1, int((ei[b] >= 0).sum())) for b in range(B)]))
+            points.append({"batch": B, "sel": sel, "scan_ms": round(scan_ms, 4), "probe_ms": round(probe_ms, 4),
+                           "probe_recall": round(rec, 4),
+                           "partitions_visited_mean": round(float(pr[2].float().mean().item()), 2),
+                           "faster": "probe" if probe_ms < scan_ms else "scan"})
+            log(json.dumps(points[-1]))
+    head = [p for p in points if p["batch"] == 1 and p["sel"] == 1.0][0]
+    rec = {
+        "metric": "filtered top-k queries/s, probe path (k-means partitions) vs exact scan (N=1M)",
+        "value": round(1e3 / head["probe_ms"], 2), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": head["probe_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"clustered-gaussian N={n} d={d} f32, one-column range predicate, squared L2, "
+                               f"top-{k}; index {nlist} partitions ({args.iters} k-means iterations), probe "
+                               f"{nprobe} partitions extended until k rows qualify, cap {args.cap_c}",
+                   "index_build_s": round(build_s, 3), "largest_partition": ix.max_list},
+        "points": points,
+        "note": "value = probe queries/s at one query, selectivity 1; the scan is exact, the probe approximate",
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["scan", "batched", "precision"], default="scan")
+    ap.add_argument("--workload", choices=["scan", "batched", "precision", "range", "join", "probe"],
+                    default="scan")
+    ap.add_argument("--nlist", type=int, default=1024, help="probe workload: partitions")
+    ap.add_argument("--nprobe", type=int, default=16, help="probe workload: partitions probed")
+    ap.add_argument("--iters", type=int, default=8, help="probe workload: k-means iterations")
+    ap.add_argument("--cap-c", type=int, default=1 << 16, help="probe workload: visited-row budget")
+    ap.add_argument("--probe-batch", type=int, default=256, help="probe workload: the batched point")
+    ap.add_argument("--cos", type=float, default=0.9, help="range workload: cosine-similarity threshold")
+    ap.add_argument("--cap", type=int, default=65536, help="range workload: result slots per query")
+    ap.add_argument("--join-rows", type=int, default=16384, help="join workload: rows of R")
     ap.add_argument("--n", type=int, default=0, help="rows (default 10M scan, 2M batched)")
     ap.add_argument("--d", type=int, default=0, help="dimension (default 128 scan, 1536 batched)")
     ap.add_argument("--clusters", type=int, default=1000)
@@ -647,6 +894,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", dest="sweep", action="store_false",
                     help="skip the batch x selectivity x strategy sweep")
+    ap.add_argument("--kprime-mult", type=int, default=0,
+                    help="batched workload: k' = this times k for every query (0 = the library's rule)")
     ap.add_argument("--per-query-sample", type=int, default=256,
                     help="batched workload: queries timed through per-query launches")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -662,6 +911,12 @@ def main():
         bench_batched(args)
     elif args.workload == "precision":
         bench_precision(args)
+    elif args.workload == "range":
+        bench_range(args)
+    elif args.workload == "join":
+        bench_join(args)
+    elif args.workload == "probe":
+        bench_probe(args)
     else:
         bench_scan(args)
 

@@ -36,6 +36,7 @@ extern "C" {
 #endif
 
 typedef struct vrs_table_s *vrs_table; /* opaque, library-owned */
+typedef struct vrs_index_s *vrs_index; /* opaque, library-owned */
 
 typedef enum {
     VRS_OK = 0,
@@ -167,6 +168,109 @@ vrs_status vrs_select(vrs_table t, const vrs_pred *pred /* host */, int32_t *ids
 vrs_status vrs_scan_topk(vrs_table t, const float *q, int32_t B, const vrs_pred *pred, int32_t k,
                          vrs_metric metric, int64_t *out_idx, float *out_dist, void *ws,
                          size_t ws_bytes, const vrs_opts *opts, void *stream);
+
+/* Threshold selection: for each query b, every row i that satisfies the
+ * relational predicate and whose exact FP64 distance (the distance of this
+ * header) is below thr[b], ascending by row id.  This is the selection with
+ * a query vector and a similarity predicate of Section 3 (eq. 1), with the
+ * relational predicate pushed down as in eq. 3; the paper's evaluation uses
+ * a cosine-similarity threshold (Section 5, "Dataset"): on a table built
+ * with normalize=1 and a unit-norm query, cosine similarity > t is
+ * VRS_IP distance < -t.
+ *   q:         [B][d] float32 (device), finite.
+ *   pred:      host pointer, one conjunction for the whole batch.
+ *   thr:       [B] float64 (device); +inf selects every qualifying row,
+ *              -inf and NaN select none.
+ *   cap:       result slots per query (>= 1).
+ *   out_idx:   [B][cap] int64: the first min(count, cap) selected row ids,
+ *              ascending, then -1.
+ *   out_dist:  [B][cap] float32: their exact distances rounded to float32,
+ *              then +inf.
+ *   out_count: [B] int64: the number of selected rows (may exceed cap; then
+ *              out_idx holds the cap lowest ids).
+ *   ws:        >= vrs_range_workspace_bytes(t, B, cap) bytes, 256-aligned.
+ *   opts:      may be NULL; only opts->strategy is used (AUTO, MASK or
+ *              GATHER; results do not depend on it).
+ * The FP32 screening admits every row whose screening distance is below
+ * thr[b] plus a bound on its error; every admitted row is then decided by
+ * its exact FP64 distance, so the set is exact.  A query with more admitted
+ * rows than its candidate slots is decided by an exact pass over every
+ * qualifying row. */
+vrs_status vrs_range_workspace_bytes(vrs_table t, int32_t B, int32_t cap, size_t *bytes);
+vrs_status vrs_scan_range(vrs_table t, const float *q, int32_t B, const vrs_pred *pred,
+                          vrs_metric metric, const double *thr, int32_t cap, int64_t *out_idx,
+                          float *out_dist, int64_t *out_count, void *ws, size_t ws_bytes,
+                          const vrs_opts *opts, void *stream);
+
+/* Vector join: for every row r of R, taken as its stored vector (float32
+ * and bfloat16 values exactly, an FP8 value scale * code rounded to the
+ * nearest float32), the exact top-k rows of S satisfying pred, as
+ * vrs_scan_topk returns them for that query.  This is the N:N strategy of
+ * Section 3.1 with a whole relation as the query batch (the paper names
+ * joins as the large-batch use of the tensor form, Section 5.2).  R and S
+ * may be the same table (then every row finds itself at distance 0 when
+ * L2SQ is used and no lower-id duplicate exists).
+ *   pred:     host pointer, a conjunction over S's attributes.
+ *   out_idx:  [R.n][k] int64, out_dist: [R.n][k] float32 (device).
+ *   ws:       >= vrs_join_workspace_bytes(R, S, k, opts) bytes, 256-aligned.
+ *   opts:     as for vrs_scan_topk; n_valid, certified and err_ratio, when
+ *             given, hold R.n entries.
+ * R.d must equal S.d; L2SQ needs a float32 table S. */
+vrs_status vrs_join_workspace_bytes(vrs_table R, vrs_table S, int32_t k, const vrs_opts *opts,
+                                    size_t *bytes);
+vrs_status vrs_join_topk(vrs_table R, vrs_table S, const vrs_pred *pred, int32_t k, vrs_metric metric,
+                         int64_t *out_idx, float *out_dist, void *ws, size_t ws_bytes,
+                         const vrs_opts *opts, void *stream);
+
+/* Probe-based access path (Section 4): a partition index over a table's
+ * vector column and its filtered probe with pre-filtering (Section 4.1: the
+ * relational predicate decides which rows may enter the result, not which
+ * partitions are visited).  The result is approximate: the exact top-k of
+ * the rows the probe collects.  (The paper's index is HNSW; this one is
+ * k-means partitions, which turn a probe into a few short scans.)
+ *
+ * vrs_index_build: k-means with nlist partitions (1 <= nlist <= min(16384,
+ * n)) and iters Lloyd iterations (0..100) on the stored vectors, squared
+ * L2: the initial centroids are the stored rows floor(i n / nlist); every
+ * assignment is the row's exact nearest centroid (by FP64 distance, then
+ * centroid id); a centroid moves to its partition's mean (an FP64 running
+ * sum over the partition's rows in ascending order, divided by the count,
+ * rounded to float32; an empty partition keeps its centroid).  The table
+ * must outlive the index.  Allocates and synchronises `stream`. */
+vrs_status vrs_index_build(vrs_table t, int32_t nlist, int32_t iters, void *stream, vrs_index *out);
+vrs_status vrs_index_destroy(vrs_index ix);
+/* nlist and the largest partition (host pointers, may be NULL). */
+vrs_status vrs_index_info(vrs_index ix, int32_t *nlist, int64_t *max_list);
+/* Device copies: centroids [nlist][d] float32, partition offsets [nlist+1]
+ * int64, the rows of every partition ascending [n] int32 (any may be NULL). */
+vrs_status vrs_index_export(vrs_index ix, float *centroids, int64_t *list_off, int32_t *list_ids,
+                            void *stream);
+/* Scan or probe (the access-path choice of Section 5.3): estimated times
+ * (ms, host pointers, may be NULL) of the exact scan and of the probe for B
+ * queries with this predicate (selectivity from the table's column
+ * histograms) and k, from a bytes-moved cost model: the scan reads the
+ * predicate columns and either every row or the qualifying ones, once for
+ * the batch; a probe reads, per query, the partitions its walk visits until
+ * k rows qualify (between one and nprobe partitions, at most cap_c rows).
+ * use_probe = 1 when the probe is estimated faster.  The probe's results are
+ * approximate: a caller that needs the exact answer scans. */
+vrs_status vrs_plan_access(vrs_index ix, int32_t B, const vrs_pred *pred, int32_t k, int32_t nprobe,
+                           int64_t cap_c, double *scan_ms, double *probe_ms, int32_t *use_probe);
+/* Filtered probe of B queries sharing one predicate.  Each query takes its
+ * nprobe nearest centroids (exact, squared L2, ties by centroid id; 1 <=
+ * nprobe <= min(256, nlist)) and visits their partitions in that order; a
+ * visited partition contributes its rows that satisfy the predicate.  The
+ * walk stops once min_cand rows qualified, or before a partition that would
+ * take the rows visited past cap_c (the first partition is always visited).
+ * The result is the exact top-k of the collected rows by (FP64 distance,
+ * id), padded with (-1, +inf); out_taken [B] (or NULL) receives the number
+ * of partitions visited.  ws >= vrs_probe_workspace_bytes(...). */
+vrs_status vrs_probe_workspace_bytes(vrs_index ix, int32_t B, int32_t k, int32_t nprobe, int64_t cap_c,
+                                     size_t *bytes);
+vrs_status vrs_probe_topk(vrs_index ix, const float *q, int32_t B, const vrs_pred *pred, int32_t k,
+                          vrs_metric metric, int32_t nprobe, int64_t min_cand, int64_t cap_c,
+                          int64_t *out_idx, float *out_dist, int32_t *out_taken, void *ws,
+                          size_t ws_bytes, void *stream);
 
 /* Filtered exact top-k for B queries, each with its own predicate and k:
  * the selection of Section 3 (brute-force search with a relational

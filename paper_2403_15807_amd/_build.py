@@ -17,9 +17,9 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libvrs.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.cpp", "planner.cpp", "batched.cpp", "k_build.hip", "k_select.hip",
+SOURCES = ["api.cpp", "planner.cpp", "batched.cpp", "range.cpp", "join.cpp", "probe.cpp", "k_build.hip", "k_select.hip",
            "k_stream.hip", "k_mfma.hip", "k_mfma_bf16.hip", "k_finish.hip", "k_batched.hip",
-           "k_mlp.hip"]
+           "k_mlp.hip", "k_range.hip", "k_probe.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = ["-x", "hip", "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",

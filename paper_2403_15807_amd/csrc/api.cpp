@@ -92,6 +92,9 @@ vrs_status fold_pred(const vrs_pred *p, int n_attr, PredDev *out) {
 
 namespace vrs {
 
+// Status and message of a failed call, for entry points in other files.
+vrs_status set_error(vrs_status st, const char *msg) { return fail(st, "%s", msg); }
+
 int elem_bytes(vrs_dtype t) { return t == VRS_F32 ? 4 : (t == VRS_BF16 ? 2 : 1); }
 
 // Rows are zero-padded so that a row is a whole number of 128-byte blocks.
@@ -412,6 +415,170 @@ vrs_status vrs_scan_topk(vrs_table t, const float *q, int32_t B, const vrs_pred 
                          size_t ws_bytes, const vrs_opts *opts, void *stream) {
     return scan_common(t, q, B, pred, nullptr, nullptr, k, metric, out_idx, out_dist, ws, ws_bytes,
                        opts, stream);
+}
+
+vrs_status vrs_range_workspace_bytes(vrs_table t, int32_t B, int32_t cap, size_t *bytes) {
+    if (!t || !bytes) return fail(VRS_E_ARG, "NULL argument");
+    if (B < 1 || B > VRS_MAX_BATCH) return fail(VRS_E_ARG, "B=%d outside [1, %d]", B, VRS_MAX_BATCH);
+    if (cap < 1) return fail(VRS_E_ARG, "cap=%d < 1", cap);
+    *bytes = range_workspace(t, B, cap);
+    return ok();
+}
+
+vrs_status vrs_scan_range(vrs_table t, const float *q, int32_t B, const vrs_pred *pred,
+                          vrs_metric metric, const double *thr, int32_t cap, int64_t *out_idx,
+                          float *out_dist, int64_t *out_count, void *ws, size_t ws_bytes,
+                          const vrs_opts *opts, void *stream) {
+    if (!t) return fail(VRS_E_ARG, "table is NULL");
+    if (!q || !thr) return fail(VRS_E_ARG, "queries or thresholds are NULL");
+    if (!out_idx || !out_dist || !out_count) return fail(VRS_E_ARG, "outputs are NULL");
+    if (B < 1 || B > VRS_MAX_BATCH) return fail(VRS_E_ARG, "B=%d outside [1, %d]", B, VRS_MAX_BATCH);
+    if (cap < 1) return fail(VRS_E_ARG, "cap=%d < 1", cap);
+    if (metric != VRS_L2SQ && metric != VRS_IP) return fail(VRS_E_ARG, "unknown metric %d", (int)metric);
+    if (metric == VRS_L2SQ && t->store != VRS_F32)
+        return fail(VRS_E_UNSUPPORTED, "L2SQ needs a float32 table (bfloat16/FP8 tables support IP)");
+    if (opts && (opts->strategy < 0 || opts->strategy > 2))
+        return fail(VRS_E_ARG, "opts.strategy=%d outside [0, 2]", opts->strategy);
+    PredDev p;
+    vrs_status st = fold_pred(pred, t->n_attr, &p);
+    if (st != VRS_OK) return st;
+    const size_t need = range_workspace(t, B, cap);
+    if (!ws || ws_bytes < need) return fail(VRS_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    if (((uintptr_t)ws & 255) != 0) return fail(VRS_E_WORKSPACE, "workspace not 256-byte aligned");
+    hipError_t e = run_range(t, q, B, p, metric, thr, cap, out_idx, out_dist, out_count, ws, opts,
+                             (hipStream_t)stream);
+    if (e != hipSuccess) return fail(VRS_E_HIP, "range launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+vrs_status vrs_join_workspace_bytes(vrs_table R, vrs_table S, int32_t k, const vrs_opts *opts,
+                                    size_t *bytes) {
+    if (!R || !S || !bytes) return fail(VRS_E_ARG, "NULL argument");
+    if (k < 1 || k > 256) return fail(VRS_E_ARG, "k=%d outside [1, 256]", k);
+    if (R->d != S->d) return fail(VRS_E_ARG, "R has d=%d, S has d=%d", R->d, S->d);
+    *bytes = join_workspace(R, S, k, opts);
+    return ok();
+}
+
+vrs_status vrs_join_topk(vrs_table R, vrs_table S, const vrs_pred *pred, int32_t k, vrs_metric metric,
+                         int64_t *out_idx, float *out_dist, void *ws, size_t ws_bytes,
+                         const vrs_opts *opts, void *stream) {
+    if (!R || !S) return fail(VRS_E_ARG, "table is NULL");
+    if (!out_idx || !out_dist) return fail(VRS_E_ARG, "outputs are NULL");
+    if (R->d != S->d) return fail(VRS_E_ARG, "R has d=%d, S has d=%d", R->d, S->d);
+    if (k < 1 || k > 256) return fail(VRS_E_ARG, "k=%d outside [1, 256]", k);
+    if (metric != VRS_L2SQ && metric != VRS_IP) return fail(VRS_E_ARG, "unknown metric %d", (int)metric);
+    if (metric == VRS_L2SQ && S->store != VRS_F32)
+        return fail(VRS_E_UNSUPPORTED, "L2SQ needs a float32 table S (bfloat16/FP8 tables support IP)");
+    if (opts && (opts->strategy < 0 || opts->strategy > 2))
+        return fail(VRS_E_ARG, "opts.strategy=%d outside [0, 2]", opts->strategy);
+    if (opts && (opts->tile < -1 || opts->tile >= planner_num_tiles()))
+        return fail(VRS_E_ARG, "opts.tile=%d outside [-1, %d)", opts->tile, planner_num_tiles());
+    if (opts && (opts->kprime_mult < 0 || opts->kprime_mult > 64))
+        return fail(VRS_E_ARG, "opts.kprime_mult=%d outside [0, 64]", opts->kprime_mult);
+    PredDev p;
+    vrs_status st = fold_pred(pred, S->n_attr, &p);
+    if (st != VRS_OK) return st;
+    const size_t need = join_workspace(R, S, k, opts);
+    if (!ws || ws_bytes < need) return fail(VRS_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    if (((uintptr_t)ws & 255) != 0) return fail(VRS_E_WORKSPACE, "workspace not 256-byte aligned");
+    hipError_t e = run_join(R, S, p, k, metric, out_idx, out_dist, ws, opts, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(VRS_E_HIP, "join launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+vrs_status vrs_index_build(vrs_table t, int32_t nlist, int32_t iters, void *stream, vrs_index *out) {
+    if (!t || !out) return fail(VRS_E_ARG, "NULL argument");
+    if (nlist < 1 || nlist > 16384 || nlist > t->n)
+        return fail(VRS_E_ARG, "nlist=%d outside [1, min(16384, n)]", nlist);
+    if (iters < 0 || iters > 100) return fail(VRS_E_ARG, "iters=%d outside [0, 100]", iters);
+    std::string err;
+    vrs_index_s *ix = nullptr;
+    hipError_t e = index_build(t, nlist, iters, (hipStream_t)stream, &ix, &err);
+    if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? VRS_E_NOMEM : VRS_E_HIP, "index build: %s", err.c_str());
+    *out = ix;
+    return ok();
+}
+
+vrs_status vrs_index_destroy(vrs_index ix) {
+    if (!ix) return fail(VRS_E_ARG, "index is NULL");
+    index_free(ix);
+    return ok();
+}
+
+vrs_status vrs_index_info(vrs_index ix, int32_t *nlist, int64_t *max_list) {
+    if (!ix) return fail(VRS_E_ARG, "index is NULL");
+    if (nlist) *nlist = ix->nlist;
+    if (max_list) *max_list = ix->max_list;
+    return ok();
+}
+
+vrs_status vrs_index_export(vrs_index ix, float *centroids, int64_t *list_off, int32_t *list_ids,
+                            void *stream) {
+    if (!ix) return fail(VRS_E_ARG, "index is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (centroids)
+        HIP_TRY(hipMemcpyAsync(centroids, ix->cent, (size_t)ix->nlist * ix->d * 4, hipMemcpyDeviceToDevice, s));
+    if (list_off)
+        HIP_TRY(hipMemcpyAsync(list_off, ix->list_off, (size_t)(ix->nlist + 1) * 8, hipMemcpyDeviceToDevice, s));
+    if (list_ids)
+        HIP_TRY(hipMemcpyAsync(list_ids, ix->ids, (size_t)ix->table->n * 4, hipMemcpyDeviceToDevice, s));
+    return ok();
+}
+
+vrs_status vrs_plan_access(vrs_index ix, int32_t B, const vrs_pred *pred, int32_t k, int32_t nprobe,
+                           int64_t cap_c, double *scan_ms, double *probe_ms, int32_t *use_probe) {
+    if (!ix) return fail(VRS_E_ARG, "index is NULL");
+    if (B < 1 || B > VRS_MAX_BATCH) return fail(VRS_E_ARG, "B=%d outside [1, %d]", B, VRS_MAX_BATCH);
+    if (k < 1 || k > 256) return fail(VRS_E_ARG, "k=%d outside [1, 256]", k);
+    if (nprobe < 1 || nprobe > std::min(256, ix->nlist))
+        return fail(VRS_E_ARG, "nprobe=%d outside [1, min(256, nlist)]", nprobe);
+    PredDev p;
+    vrs_status st = fold_pred(pred, ix->table->n_attr, &p);
+    if (st != VRS_OK) return st;
+    double sc = 0.0, pr = 0.0;
+    access_costs(ix, B, p, k, nprobe, std::max<int64_t>(cap_c, 1), &sc, &pr);
+    if (scan_ms) *scan_ms = sc;
+    if (probe_ms) *probe_ms = pr;
+    if (use_probe) *use_probe = pr < sc;
+    return ok();
+}
+
+vrs_status vrs_probe_workspace_bytes(vrs_index ix, int32_t B, int32_t k, int32_t nprobe, int64_t cap_c,
+                                     size_t *bytes) {
+    if (!ix || !bytes) return fail(VRS_E_ARG, "NULL argument");
+    if (B < 1 || B > VRS_MAX_BATCH) return fail(VRS_E_ARG, "B=%d outside [1, %d]", B, VRS_MAX_BATCH);
+    if (k < 1 || k > 256) return fail(VRS_E_ARG, "k=%d outside [1, 256]", k);
+    if (nprobe < 1 || nprobe > std::min(256, ix->nlist))
+        return fail(VRS_E_ARG, "nprobe=%d outside [1, min(256, nlist)]", nprobe);
+    if (cap_c < 1) return fail(VRS_E_ARG, "cap_c=%lld < 1", (long long)cap_c);
+    *bytes = probe_workspace(ix, B, k, nprobe, cap_c);
+    return ok();
+}
+
+vrs_status vrs_probe_topk(vrs_index ix, const float *q, int32_t B, const vrs_pred *pred, int32_t k,
+                          vrs_metric metric, int32_t nprobe, int64_t min_cand, int64_t cap_c,
+                          int64_t *out_idx, float *out_dist, int32_t *out_taken, void *ws,
+                          size_t ws_bytes, void *stream) {
+    if (!ix) return fail(VRS_E_ARG, "index is NULL");
+    if (!q) return fail(VRS_E_ARG, "queries are NULL");
+    if (!out_idx || !out_dist) return fail(VRS_E_ARG, "outputs are NULL");
+    size_t need = 0;
+    vrs_status st = vrs_probe_workspace_bytes(ix, B, k, nprobe, cap_c, &need);
+    if (st != VRS_OK) return st;
+    if (min_cand < 1) return fail(VRS_E_ARG, "min_cand=%lld < 1", (long long)min_cand);
+    if (metric != VRS_L2SQ && metric != VRS_IP) return fail(VRS_E_ARG, "unknown metric %d", (int)metric);
+    if (metric == VRS_L2SQ && ix->table->store != VRS_F32)
+        return fail(VRS_E_UNSUPPORTED, "L2SQ needs a float32 table (bfloat16/FP8 tables support IP)");
+    PredDev p;
+    st = fold_pred(pred, ix->table->n_attr, &p);
+    if (st != VRS_OK) return st;
+    if (!ws || ws_bytes < need) return fail(VRS_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    if (((uintptr_t)ws & 255) != 0) return fail(VRS_E_WORKSPACE, "workspace not 256-byte aligned");
+    hipError_t e = run_probe(ix, q, B, p, k, metric, nprobe, min_cand, cap_c, out_idx, out_dist, out_taken, ws,
+                             (hipStream_t)stream);
+    if (e != hipSuccess) return fail(VRS_E_HIP, "probe launch failed: %s", hipGetErrorString(e));
+    return ok();
 }
 
 static size_t batched_bytes(vrs_table t, int32_t B, int32_t k_max, vrs_metric metric,

@@ -170,6 +170,11 @@ hipError_t run_batched(const vrs_table_s *t, const float *q, int B, const vrs_pr
     ba.n_attr = t->n_attr;
     ba.kmult = opts ? opts->kprime_mult : 0;
     ba.f32_rule = t->store == VRS_F32;
+    // every query's list holds up to P.kprime + 1 keys (sized for k_max):
+    // under the default rule a query with a small k reranks at least
+    // min(128, P.kprime) of them, which keeps its certificate clear of the
+    // near-ties of dense clusters at little cost
+    ba.kfloor = std::min(128, P.kprime);
     ba.attr = t->attr;
     ba.n = t->n;
     ba.an = t->attr_stride;

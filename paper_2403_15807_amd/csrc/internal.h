@@ -32,6 +32,17 @@ struct vrs_table_s {
     void *stats_alloc = nullptr;  // the allocation holding dstats (owner only)
 };
 
+// A partition index over a table's vector column (probe.cpp).
+struct vrs_index_s {
+    const vrs_table_s *table = nullptr;  // the indexed table (the caller keeps it alive)
+    vrs_table_s *cent_tab = nullptr;     // centroids as a float32 table (coarse scans)
+    float *cent = nullptr;               // [nlist][d]
+    int64_t *list_off = nullptr;         // [nlist + 1]
+    int32_t *ids = nullptr;              // [n] rows of every partition, ascending
+    int32_t nlist = 0, d = 0;
+    int64_t max_list = 0;                // largest partition
+};
+
 namespace vrs {
 
 constexpr int HIST_BINS = 256;
@@ -41,6 +52,8 @@ constexpr int HIST_BINS = 256;
 void ensure_dyn_lds(const void *kernel, size_t bytes);
 
 int elem_bytes(vrs_dtype t);
+// Record a failed call's status and message for vrs_last_error().
+vrs_status set_error(vrs_status st, const char *msg);
 int pad_dim(int d, vrs_dtype t);
 
 // ---- build kernels (k_build.hip)
@@ -49,6 +62,9 @@ hipError_t launch_build_rows(const float *vec, int64_t n, int32_t d, int32_t dp,
                              unsigned long long *max_norm_bits, int *bad_flag, hipStream_t s);
 hipError_t launch_attr_stats(const int32_t *attr, int64_t n, int32_t n_attr, int32_t *amin,
                              int32_t *amax, uint32_t *hist, hipStream_t s);
+// Rows [i0, i0 + count) as float32 vectors [count][d] (FP8: scale * code,
+// rounded to float32).
+hipError_t launch_rows_to_f32(const vrs_table_s *t, int64_t i0, int64_t count, float *out, hipStream_t s);
 
 // ---- predicate pass (k_select.hip)
 constexpr int SEL_BLOCK_ROWS = 8192;
@@ -238,9 +254,11 @@ __device__ inline QRange range_form(int b, const PredDev &o) {
     return r;
 }
 
-// k' of one query (the host rule of the planner).
-__device__ inline int kprime_dev(int k, int kmult, int f32_rule) {
-    int kp = kmult > 0 ? k * kmult : (f32_rule ? max(2 * k, k + 32) : max(4 * k, k + 32));
+// k' of one query (the host rule of the planner).  kfloor: the batched
+// form's lists are sized for k_max, so a query with a smaller k keeps (and
+// reranks) at least kfloor of them under the default rule.
+__device__ inline int kprime_dev(int k, int kmult, int f32_rule, int kfloor = 0) {
+    int kp = kmult > 0 ? k * kmult : max(f32_rule ? max(2 * k, k + 32) : max(4 * k, k + 32), kfloor);
     return min(max(kp, k), 1024);
 }
 
@@ -250,6 +268,7 @@ struct BatchArgs {
     const vrs_pred *preds;         // [B] caller's predicates
     const int32_t *ks;             // [B] caller's k
     int32_t B, kmax, n_attr, kmult, f32_rule;
+    int32_t kfloor;                // k' floor of the default rule (see kprime_dev)
     const int32_t *attr;
     int64_t n, an;
     const void *dstats;            // device column statistics (table)
@@ -337,6 +356,89 @@ hipError_t launch_merge(const FinishArgs &a, hipStream_t s);
 hipError_t launch_set_bound(const FinishArgs &a, uint64_t *gthr, int32_t *zero8, hipStream_t s);
 hipError_t launch_rerank(const FinishArgs &a, hipStream_t s);
 hipError_t launch_fallback(const FinishArgs &a, hipStream_t s);
+
+// ---- threshold selection (k_range.hip): for each query, the qualifying
+// rows whose exact FP64 distance is below its threshold, ascending by id.
+constexpr int RANGE_BLOCK_ROWS = 8192;   // rows per block of the output compaction
+struct RangeArgs {
+    const void *rows;
+    const float *scale;
+    int64_t n;
+    int32_t d, dp;
+    vrs_dtype store;
+    const int32_t *attr;
+    int64_t an;                    // attribute column stride
+    PredDev pred;
+    const int32_t *sel_ids;        // gather: qualifying rows, ascending
+    const int64_t *sel_count;
+    int gather;
+    const float *q;                // original queries [B][d]
+    const float *qp;               // [B][dp] padded
+    const double *qnorm;           // [B] FP64 query norms (rounded up)
+    int32_t B;
+    int metric;
+    const double *thr;             // [B] thresholds (caller's)
+    float *tf;                     // [B] screening admission bound (>= thr + error bound)
+    double rel, abs_ip, abs_l2, max_norm;  // screening error model
+    int32_t n_chunks;              // row chunks of the screening grid
+    int32_t cap_c;                 // candidate slots per query
+    uint32_t *cnt;                 // [B] candidates found (may exceed cap_c)
+    int32_t *cand;                 // [B][cap_c] candidate rows
+    int32_t *ovf_list;             // [B] queries whose candidates overflowed
+    int32_t *ovf_count;            // [1]
+    int32_t fb_chunks;             // row chunks of the exact pass for overflowed queries
+    uint32_t *bitmap;              // [B][words] selected rows
+    int64_t words;                 // 32-bit words per query bitmap (a multiple of 2)
+    uint32_t *blkcnt;              // [B][nblk] selected rows per block of RANGE_BLOCK_ROWS
+    int32_t nblk;
+    int32_t cap;                   // output slots per query
+    int64_t *out_idx;              // [B][cap]
+    float *out_dist;               // [B][cap]
+    int64_t *out_count;            // [B]
+};
+// Steps of a call, in order on one stream: 0 prep (admission bounds, empty
+// bitmaps), 1 screening (qt queries per workgroup: 1, 2, 4 or 8), 2 exact
+// distances of the candidates (and of every row for overflowed queries),
+// 3 output (compaction, exact distances of the written ids, padding).
+hipError_t launch_range(const RangeArgs &a, int qt, int step, hipStream_t s);
+
+// ---- probe path (k_probe.hip): partition index build and filtered probe
+constexpr int PROBE_LIST_BLOCK = 4096;  // rows placed by one thread
+constexpr int PROBE_CHUNK = 2048;       // candidates scored by one workgroup
+struct ProbeArgs {
+    const void *rows;
+    const float *scale;
+    int32_t d, dp;
+    vrs_dtype store;
+    int metric;
+    const int32_t *attr;
+    int64_t an;
+    PredDev pred;
+    const float *q;                // [B][d]
+    int32_t B, k;
+    const int64_t *coarse;         // [B][nprobe] partitions in centroid order (-1 pads)
+    int32_t nprobe;
+    int64_t min_cand, cap_c;       // stopping rules of the walk
+    const int64_t *list_off;       // [nlist + 1]
+    const int32_t *ids;            // rows of every partition, ascending
+    int32_t *cand;                 // [B][cand_cap] collected rows
+    int64_t cand_cap;
+    int32_t *ncand;                // [B]
+    int32_t *taken;                // [B] partitions visited, or null
+    int32_t nchunk;                // candidate chunks per query
+    uint64_t *part;                // [B][nchunk][k][2] per-chunk exact keys
+    int64_t *out_idx;              // [B][k]
+    float *out_dist;               // [B][k]
+};
+// assign [n] partition of every row -> partition offsets [nlist + 1] and the
+// rows of every partition ascending; cnt: [ceil(n / PROBE_LIST_BLOCK)][nlist]
+// scratch, size: [nlist] scratch.
+hipError_t launch_index_lists(const int64_t *assign, int64_t n, int nlist, uint32_t *cnt, int64_t *size,
+                              int64_t *off, int32_t *ids, hipStream_t s);
+hipError_t launch_centroid_init(const float *x32, int64_t n, int nlist, int d, float *cent, hipStream_t s);
+hipError_t launch_centroid_mean(const float *x32, int nlist, int d, const int64_t *off, const int32_t *ids,
+                                float *cent, hipStream_t s);
+hipError_t launch_probe(const ProbeArgs &a, hipStream_t s);
 
 // ---- chooser network (k_mlp.hip)
 hipError_t launch_mlp_forward(const float *p, const float *x, int nb, float *y, float *act,

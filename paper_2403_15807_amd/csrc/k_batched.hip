@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void batch_prepare_kernel(BatchArgs a) {
     int k = a.ks[b];
     k = k < 1 ? 1 : (k > a.kmax ? a.kmax : k);
     a.kc_o[b] = k;
-    a.kps_o[b] = kprime_dev(k, a.kmult, a.f32_rule);
+    a.kps_o[b] = kprime_dev(k, a.kmult, a.f32_rule, a.kfloor);
     const QRange r = range_form(b, o);
     a.qr[b] = r;
     bool cand = false;

@@ -191,4 +191,37 @@ hipError_t launch_attr_stats(const int32_t *attr, int64_t n, int32_t n_attr, int
     return hipGetLastError();
 }
 
+// ------------------------------------------------- stored rows as queries
+// Rows [i0, i0 + count) of a table as float32 vectors [count][d]: float32
+// and bfloat16 values exactly, an FP8 value (row scale times the code's
+// value) rounded to the nearest float32 (one float multiply of two exact
+// operands).  The queries of a vector join.
+__global__ __launch_bounds__(256) void rows_to_f32_kernel(const void *__restrict__ rows,
+                                                          const float *__restrict__ scale,
+                                                          int store, int d, int dp, int64_t i0,
+                                                          int64_t count, float *__restrict__ out) {
+    const int64_t total = count * d;
+    for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t r = e / d, j = e - r * d, row = i0 + r;
+        float v;
+        if (store == VRS_F32) {
+            v = ((const float *)rows)[row * dp + j];
+        } else if (store == VRS_BF16) {
+            v = __uint_as_float((uint32_t)((const uint16_t *)rows)[row * dp + j] << 16);
+        } else {
+            const uint32_t c = ((const uint8_t *)rows)[row * dp + j];
+            const float mag = __uint_as_float((c & 0x7fu) << 20) * 0x1p120f;  // exact (see the rerank)
+            v = scale[row] * __uint_as_float(__float_as_uint(mag) | ((c & 0x80u) << 24));
+        }
+        out[e] = v;
+    }
+}
+
+hipError_t launch_rows_to_f32(const vrs_table_s *t, int64_t i0, int64_t count, float *out, hipStream_t s) {
+    const int64_t total = count * t->d;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
+    rows_to_f32_kernel<<<grid, 256, 0, s>>>(t->rows, t->scale, (int)t->store, t->d, t->dp, i0, count, out);
+    return hipGetLastError();
+}
+
 }  // namespace vrs

@@ -9,7 +9,7 @@
 //             multiply-add each), order by (distance, id), certificate;
 //   fallback: for the queries whose certificate failed, an exact FP64 scan
 //             of every qualifying row with (distance, id) keys.
-#include "internal.h"
+#include "exact64.h"
 
 namespace vrs {
 
@@ -75,78 +75,6 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, 
         qnorm[b] = sqrt(red[0]) * (1.0 + 0x1p-40);
         qn2[b] = (float)red[0];
     }
-}
-
-// Exact distance of the definition: coordinates in ascending order, one
-// fused multiply-add each, accumulator from +0.0; IP applies the FP8 row
-// scale to the finished sum; zero is returned as +0.0.  The row is read in
-// 16-byte blocks up to the padded width dp; `qrow` holds the query padded
-// with zeros to dp, and a padded coordinate adds an exact zero (+0 + +0 or
-// acc + 0), so the value equals the sum over the first d coordinates.
-template <int STORE>
-__device__ __forceinline__ void decode16(const uint4 &w, float *x);
-template <>
-__device__ __forceinline__ void decode16<VRS_F32>(const uint4 &w, float *x) {
-    x[0] = __uint_as_float(w.x);
-    x[1] = __uint_as_float(w.y);
-    x[2] = __uint_as_float(w.z);
-    x[3] = __uint_as_float(w.w);
-}
-template <>
-__device__ __forceinline__ void decode16<VRS_BF16>(const uint4 &w, float *x) {
-    const uint32_t v[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        x[2 * i] = __uint_as_float(v[i] << 16);
-        x[2 * i + 1] = __uint_as_float(v[i] & 0xffff0000u);
-    }
-}
-// An e4m3fn code's 7 magnitude bits, placed as the top of an f32 exponent
-// and mantissa field (a normal or subnormal f32), times 2^(127-7) give its
-// value exactly: normal codes stay normal, subnormal codes m * 2^-9 come
-// from subnormal f32 inputs, which these kernels keep (FP32 denormals are
-// not flushed).  Four instructions instead of a branch on the exponent.
-__device__ __forceinline__ float e4m3_value(uint32_t c) {
-    const float mag = __uint_as_float((c & 0x7fu) << 20) * 0x1p120f;
-    return __uint_as_float(__float_as_uint(mag) | ((c & 0x80u) << 24));
-}
-template <>
-__device__ __forceinline__ void decode16<VRS_FP8E4M3>(const uint4 &w, float *x) {
-    const uint32_t v[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) x[4 * i + j] = e4m3_value((v[i] >> (8 * j)) & 0xffu);
-}
-
-template <int STORE, int METRIC>
-__device__ double exact_dist(const void *rows, const float *scale, int64_t row, int dp,
-                             const float *qrow /* dp floats, zero padded */) {
-    constexpr int V = STORE == VRS_F32 ? 4 : (STORE == VRS_BF16 ? 8 : 16);
-    constexpr int EB = 16 / V;
-    const uint4 *p = (const uint4 *)((const char *)rows + row * (int64_t)dp * EB);
-    const int nb = dp / V;
-    const double sc = (STORE == VRS_FP8E4M3) ? (double)scale[row] : 1.0;
-    double acc = 0.0;
-    for (int c = 0; c < nb; c += 2) {
-        uint4 w0 = p[c];
-        uint4 w1 = (c + 1 < nb) ? p[c + 1] : make_uint4(0, 0, 0, 0);
-        float x[2 * V];
-        decode16<STORE>(w0, x);
-        decode16<STORE>(w1, x + V);
-        const int jn = min(2 * V, dp - c * V);
-        for (int j = 0; j < jn; ++j) {
-            const double qj = (double)qrow[c * V + j];
-            if (METRIC == VRS_L2SQ) {
-                double t = qj - sc * (double)x[j];
-                acc = fma(t, t, acc);
-            } else {
-                acc = fma(qj, (double)x[j], acc);
-            }
-        }
-    }
-    if (METRIC == VRS_IP) acc = -(sc * acc);
-    return acc == 0.0 ? 0.0 : acc;
 }
 
 __device__ __forceinline__ int k_of(const FinishArgs &a, int b) { return a.ks ? a.ks[b] : a.k; }
@@ -374,12 +302,9 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
 // certificate and writes the result.
 constexpr int RR_THREADS = 512;
 constexpr int RR_WAVES = RR_THREADS / 64;
-constexpr int RR_CHUNK = 128;                  // bytes of a row staged per step
-constexpr int RR_STRIDE = RR_CHUNK / 16 + 1;   // 16-byte slots per staged row (one pad slot)
-constexpr size_t RR_STAGE_BYTES = (size_t)RR_WAVES * 64 * RR_STRIDE * 16;
+constexpr size_t RR_STAGE_BYTES = (size_t)RR_WAVES * X64_WAVE_LDS;
 // k' <= 1024 = 2 RR_THREADS: the candidate sort holds at most two keys per thread
 static_assert(2 * RR_THREADS >= 1024, "rerank sort width");
-typedef unsigned int rr_u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bool k128_less(uint64_t ah, uint32_t al, uint64_t bh, uint32_t bl) {
     return ah < bh || (ah == bh && al < bl);
@@ -483,11 +408,7 @@ __host__ __device__ inline size_t rr_lds_bytes(int dp, int K) {
 
 template <int STORE, int METRIC>
 __global__ __launch_bounds__(RR_THREADS) void rerank_kernel(FinishArgs a) {
-    constexpr int V = STORE == VRS_F32 ? 4 : (STORE == VRS_BF16 ? 8 : 16);  // elements per 16 B
-    constexpr int EB = 16 / V;
     constexpr int T = RR_THREADS;
-    constexpr int SLOTS = RR_CHUNK / 16;      // 16-byte slots per staged row chunk
-    constexpr int CE = RR_CHUNK / EB;         // coordinates per chunk
     const int s = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int kpb = kp_of(a, b);
     // the k' survivors, and with error diagnostics also the (k'+1)-th key
@@ -500,7 +421,7 @@ __global__ __launch_bounds__(RR_THREADS) void rerank_kernel(FinishArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     double *qd = (double *)smem;                                  // [dp]
     unsigned char *area = smem + (size_t)a.dp * 8;
-    rr_u32x4 *stage = (rr_u32x4 *)area + (size_t)wave * 64 * RR_STRIDE;  // this wave's rows
+    x64_u32x4 *stage = (x64_u32x4 *)(area + (size_t)wave * X64_WAVE_LDS);  // this wave's rows
     uint64_t *xh = (uint64_t *)area;                              // [2T]   (final phase)
     uint32_t *xl = (uint32_t *)(xh + 2 * T);                      // [2T]
     Key128 *cand = (Key128 *)(xl + 2 * T);                        // [round8(K)]
@@ -513,8 +434,6 @@ __global__ __launch_bounds__(RR_THREADS) void rerank_kernel(FinishArgs a) {
     }
     __syncthreads();
     const uint64_t *lst = a.merged + (int64_t)b * a.K;
-    const int nch = a.dp * EB / RR_CHUNK;  // whole chunks: a row is whole 128-byte blocks
-    const int64_t row_bytes = (int64_t)a.dp * EB;
     double *dist = a.rr_dist + (int64_t)b * a.K;
     for (int t = s + S * wave; t < ntask; t += S * RR_WAVES) {
         const int ci = t * 64 + lane;
@@ -522,60 +441,8 @@ __global__ __launch_bounds__(RR_THREADS) void rerank_kernel(FinishArgs a) {
         const bool has = key != KEY_INF;
         // a lane without a candidate stages row 0 and drops its value
         const int row = has ? (int)(uint32_t)key : 0;
-        const double sc = (STORE == VRS_FP8E4M3 && has) ? (double)a.scale[row] : 1.0;
-        // the rows this lane stages: i * 8 + lane / 8, 16-byte slot lane % 8
-        const char *src[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int r = __shfl(row, i * 8 + (lane >> 3));
-            src[i] = (const char *)a.rows + (int64_t)r * row_bytes + (lane & 7) * 16;
-        }
-        rr_u32x4 *dst = stage + (lane >> 3) * RR_STRIDE + (lane & 7);
-        const rr_u32x4 *mine = stage + lane * RR_STRIDE;
-        rr_u32x4 wa[8], wb[8];
-        auto load = [&](rr_u32x4(&w)[8], int c) {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) w[i] = *(const rr_u32x4 *)(src[i] + (int64_t)c * RR_CHUNK);
-        };
-        auto put = [&](const rr_u32x4(&w)[8]) {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) dst[i * 8 * RR_STRIDE] = w[i];
-        };
-        double acc = 0.0;
-        auto chain = [&](int c) {
-#pragma unroll
-            for (int u = 0; u < SLOTS; ++u) {
-                const rr_u32x4 w = mine[u];
-                float x[V];
-                decode16<STORE>(make_uint4(w.x, w.y, w.z, w.w), x);
-                const double *qq = qd + c * CE + u * V;
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    if (METRIC == VRS_L2SQ) {
-                        const double tv = qq[v] - sc * (double)x[v];
-                        acc = fma(tv, tv, acc);
-                    } else {
-                        acc = fma(qq[v], (double)x[v], acc);
-                    }
-                }
-            }
-        };
-        // two chunks in flight: wa holds the even chunks, wb the odd ones.
-        // The LDS area is the wave's own and a wave's LDS accesses complete
-        // in program order, so a chunk is written only after every lane has
-        // read the one before it.
-        load(wa, 0);
-        if (nch > 1) load(wb, 1);
-        for (int c = 0; c < nch; c += 2) {
-            put(wa);
-            if (c + 2 < nch) load(wa, c + 2);
-            chain(c);
-            if (c + 1 >= nch) break;
-            put(wb);
-            if (c + 3 < nch) load(wb, c + 3);
-            chain(c + 1);
-        }
-        if (ci < nc && has) dist[ci] = METRIC == VRS_IP ? -(sc * acc) : acc;
+        const double dv = exact64_wave<STORE, METRIC>(a.rows, a.scale, row, has, qd, a.dp, stage);
+        if (ci < nc && has) dist[ci] = dv;
     }
     // arrival: the last workgroup of query b finishes it (a single workgroup
     // needs no counter and no device-scope fences)
@@ -659,17 +526,19 @@ constexpr int FB_GRID = 1024;
 
 template <int STORE, int METRIC>
 __global__ __launch_bounds__(256) void fallback_scan_kernel(FinishArgs a) {
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6;
     const int nf = *a.fail_count;
     const int64_t tasks = (int64_t)nf * a.fb_chunks;
     extern __shared__ __align__(16) unsigned char smem[];
     const int Kp = next_pow2(a.kmax);
     const int M = next_pow2(Kp + 256);
     const int CB = M - Kp;
-    Key128 *keys = (Key128 *)smem;
+    // the waves' row staging, the FP64 query, then the top-k list
+    x64_u32x4 *stage = (x64_u32x4 *)(smem + (size_t)wave * X64_WAVE_LDS);
+    double *qd = (double *)(smem + 4 * X64_WAVE_LDS);
+    Key128 *keys = (Key128 *)(qd + a.dp);
     Key128 *thr = keys + M;
     int *cnt = (int *)(thr + 1);
-    float *qrow = (float *)(cnt + 4);
     for (int64_t w = blockIdx.x; w < tasks; w += gridDim.x) {
         const int f = (int)(w / a.fb_chunks), c = (int)(w - (int64_t)f * a.fb_chunks);
         const int b = a.fail_list[f];
@@ -677,16 +546,19 @@ __global__ __launch_bounds__(256) void fallback_scan_kernel(FinishArgs a) {
         const int kb = k_of(a, b);
         const PredDev p = a.preds ? a.preds[b] : a.pred;
         __syncthreads();  // previous task done with LDS
-        for (int j = tid; j < a.dp; j += 256) qrow[j] = j < a.d ? a.q[(int64_t)ob * a.d + j] : 0.0f;
+        for (int j = tid; j < a.dp; j += 256) qd[j] = j < a.d ? (double)a.q[(int64_t)ob * a.d + j] : 0.0;
         TopkLds<Key128> tk{keys, cnt, thr, 1, kb, Kp, CB};
         tk.init(tid, 256);
         const int64_t r0 = (int64_t)c * a.fb_rows_per_chunk;
         const int64_t r1 = min(a.n, r0 + a.fb_rows_per_chunk);
+        // wave w takes rows t0 + 64 w .. + 63, one per lane, staged together
         for (int64_t t0 = r0; t0 < r1; t0 += 256) {
-            int64_t row = t0 + tid;
-            if (row < r1 && pred_eval(p, a.attr, a.an, row)) {
-                double dv = exact_dist<STORE, METRIC>(a.rows, a.scale, row, a.dp, qrow);
-                tk.push(0, Key128{ord64(dv), (uint64_t)row});
+            const int64_t row = t0 + tid;
+            const bool has = row < r1 && pred_eval(p, a.attr, a.an, row);
+            if (__ballot(has) != 0) {  // (wave-uniform)
+                const double dv =
+                    exact64_wave<STORE, METRIC>(a.rows, a.scale, has ? (int)row : 0, has, qd, a.dp, stage);
+                if (has) tk.push(0, Key128{ord64(dv), (uint64_t)row});
             }
             __syncthreads();
             if (tk.need_flush(256)) tk.flush(tid, 256);
@@ -873,6 +745,7 @@ hipError_t launch_rerank(const FinishArgs &a, hipStream_t s) {
 template <int STORE, int METRIC>
 static void fallback_t(const FinishArgs &a, hipStream_t s, size_t lds_scan, size_t lds_merge,
                        int grid) {
+    ensure_dyn_lds((const void *)fallback_scan_kernel<STORE, METRIC>, lds_scan);
     fallback_scan_kernel<STORE, METRIC><<<grid, 256, lds_scan, s>>>(a);
     fallback_merge_kernel<<<std::min(grid, a.B), 256, lds_merge, s>>>(a);
 }
@@ -880,7 +753,7 @@ static void fallback_t(const FinishArgs &a, hipStream_t s, size_t lds_scan, size
 hipError_t launch_fallback(const FinishArgs &a, hipStream_t s) {
     const int Kp = next_pow2(a.kmax), M = next_pow2(Kp + 256);
     const size_t lds_merge = (size_t)M * sizeof(Key128) + sizeof(Key128) + 16;
-    const size_t lds_scan = lds_merge + (size_t)a.dp * 4 + 16;
+    const size_t lds_scan = 4 * X64_WAVE_LDS + (size_t)a.dp * 8 + lds_merge;
     const int grid = FB_GRID;
     if (a.metric == VRS_L2SQ) {
         switch (a.store) {

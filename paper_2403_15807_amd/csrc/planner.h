@@ -68,6 +68,29 @@ bool chooser_ready();
 // predicted time among the allowed arms, or -1.
 int chooser_pick(const float feats[6], const bool *allowed, int n_arms);
 
+// ---- threshold selection (range.cpp)
+size_t range_workspace(const vrs_table_s *t, int B, int cap);
+hipError_t run_range(const vrs_table_s *t, const float *q, int B, const PredDev &p, vrs_metric metric,
+                     const double *thr, int cap, int64_t *out_idx, float *out_dist, int64_t *out_count,
+                     void *ws, const vrs_opts *opts, hipStream_t s);
+
+// ---- vector join (join.cpp)
+size_t join_workspace(const vrs_table_s *R, const vrs_table_s *S, int k, const vrs_opts *opts);
+hipError_t run_join(const vrs_table_s *R, const vrs_table_s *S, const PredDev &p, int k,
+                    vrs_metric metric, int64_t *out_idx, float *out_dist, void *ws,
+                    const vrs_opts *opts, hipStream_t s);
+
+// ---- probe path (probe.cpp)
+hipError_t index_build(const vrs_table_s *t, int nlist, int iters, hipStream_t s, vrs_index_s **out,
+                       std::string *err);
+void index_free(vrs_index_s *ix);
+void access_costs(const vrs_index_s *ix, int B, const PredDev &p, int k, int nprobe, int64_t cap_c,
+                  double *scan_ms, double *probe_ms);
+size_t probe_workspace(const vrs_index_s *ix, int B, int k, int nprobe, int64_t cap_c);
+hipError_t run_probe(const vrs_index_s *ix, const float *q, int B, const PredDev &p, int k, vrs_metric metric,
+                     int nprobe, int64_t min_cand, int64_t cap_c, int64_t *out_idx, float *out_dist,
+                     int32_t *out_taken, void *ws, hipStream_t s);
+
 // ---- batched uneven form (batched.cpp)
 // A configuration of the batched launch: queries qualifying at most
 // cap_frac * n rows go to the sparse gather kernel, the dense kernel aims at

@@ -34,6 +34,9 @@ EXPORTS = [
     "vrs_chooser_set", "vrs_chooser_clear", "vrs_plan", "vrs_table_view",
     "vrs_batched_workspace_bytes", "vrs_batched_num_configs", "vrs_batched_tune",
     "vrs_batched_graph_create", "vrs_graph_launch", "vrs_graph_config", "vrs_graph_destroy",
+    "vrs_range_workspace_bytes", "vrs_scan_range", "vrs_join_workspace_bytes", "vrs_join_topk",
+    "vrs_index_build", "vrs_index_destroy", "vrs_index_info", "vrs_index_export", "vrs_probe_workspace_bytes",
+    "vrs_probe_topk", "vrs_plan_access",
 ]
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 6, 64, 16, 5648
 NUM_STAGES = 6
@@ -93,6 +96,17 @@ def lib() -> C.CDLL:
             "vrs_chooser_clear": [],
             "vrs_plan": [P, I32, P, I32, I32, P, P, P, P],
             "vrs_table_view": [P, I64, P],
+            "vrs_range_workspace_bytes": [P, I32, I32, P],
+            "vrs_join_workspace_bytes": [P, P, I32, P, P],
+            "vrs_index_build": [P, I32, I32, P, P],
+            "vrs_index_destroy": [P],
+            "vrs_index_info": [P, P, P],
+            "vrs_index_export": [P, P, P, P, P],
+            "vrs_probe_workspace_bytes": [P, I32, I32, I32, I64, P],
+            "vrs_plan_access": [P, I32, P, I32, I32, I64, P, P, P],
+            "vrs_probe_topk": [P, P, I32, P, I32, I32, I32, I64, I64, P, P, P, P, S, P],
+            "vrs_join_topk": [P, P, P, I32, I32, P, P, P, S, P, P],
+            "vrs_scan_range": [P, P, I32, P, I32, P, I32, P, P, P, P, S, P, P],
             "vrs_batched_workspace_bytes": [P, I32, I32, I32, P, P],
             "vrs_batched_num_configs": [],
             "vrs_batched_tune": [P, P, I32, P, P, I32, I32, P, P, P, S, P, P, P, P],
@@ -156,6 +170,13 @@ class ScanResult:
     n_valid: torch.Tensor
     certified: torch.Tensor
     err_ratio: torch.Tensor | None = None
+
+
+@dataclass
+class RangeResult:
+    idx: torch.Tensor
+    dist: torch.Tensor
+    count: torch.Tensor
 
 
 class Table:
@@ -283,6 +304,60 @@ class Table:
                                    _ptr(ws), ws.numel(), C.byref(o), _stream(stream)))
         return ScanResult(idx, dist, nv, cert, er)
 
+    def range_workspace_bytes(self, B: int, cap: int) -> int:
+        out = C.c_size_t()
+        _check(lib().vrs_range_workspace_bytes(self._h, B, cap, C.byref(out)))
+        return out.value
+
+    def scan_range(self, q: torch.Tensor, terms, thr, cap: int, metric: int = IP,
+                   strategy: int = STRATEGY_AUTO, ws: torch.Tensor | None = None, out: tuple | None = None,
+                   stream=None) -> RangeResult:
+        """Threshold selection: per query, the qualifying rows whose exact
+        distance is below ``thr`` (a float, or one per query), ascending by
+        id, at most ``cap`` of them; ``count`` counts them all."""
+        q = q.contiguous()
+        B = q.shape[0]
+        th = torch.as_tensor(thr, dtype=torch.float64).reshape(-1).expand(B).contiguous().to("cuda")
+        if out is None:
+            idx = torch.empty((B, cap), dtype=torch.int64, device="cuda")
+            dist = torch.empty((B, cap), dtype=torch.float32, device="cuda")
+            cnt = torch.empty(B, dtype=torch.int64, device="cuda")
+        else:
+            idx, dist, cnt = out
+        if ws is None:
+            ws = torch.empty(max(self.range_workspace_bytes(B, cap), 256), dtype=torch.uint8, device="cuda")
+        o = vrs_opts()
+        o.strategy = strategy
+        p = make_pred(terms)
+        _check(lib().vrs_scan_range(self._h, _ptr(q), B, C.byref(p), metric, _ptr(th), cap, _ptr(idx),
+                                    _ptr(dist), _ptr(cnt), _ptr(ws), ws.numel(), C.byref(o), _stream(stream)))
+        return RangeResult(idx, dist, cnt)
+
+    def join_workspace_bytes(self, S: "Table", k: int) -> int:
+        nb = C.c_size_t()
+        _check(lib().vrs_join_workspace_bytes(self._h, S.handle, k, None, C.byref(nb)))
+        return nb.value
+
+    def join_topk(self, S: "Table", terms, k: int, metric: int = L2SQ, strategy: int = STRATEGY_AUTO,
+                  tile: int = -1, diag: bool = False, ws: torch.Tensor | None = None, stream=None) -> ScanResult:
+        """Vector join: every row of this table (its stored vector) as a
+        query against ``S``; one result row per row of this table."""
+        n = self.n
+        idx = torch.empty((n, k), dtype=torch.int64, device="cuda")
+        dist = torch.empty((n, k), dtype=torch.float32, device="cuda")
+        nv = torch.empty(n, dtype=torch.int32, device="cuda")
+        cert = torch.empty(n, dtype=torch.uint8, device="cuda")
+        er = torch.empty(n, dtype=torch.float32, device="cuda") if diag else None
+        o = self._opts(n, strategy, tile, CHOOSER_LEARNED, 0, nv, cert, 0, er)
+        if ws is None:
+            nb = C.c_size_t()
+            _check(lib().vrs_join_workspace_bytes(self._h, S.handle, k, C.byref(o), C.byref(nb)))
+            ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device="cuda")
+        p = make_pred(terms)
+        _check(lib().vrs_join_topk(self._h, S.handle, C.byref(p), k, metric, _ptr(idx), _ptr(dist), _ptr(ws),
+                                   ws.numel(), C.byref(o), _stream(stream)))
+        return ScanResult(idx, dist, nv, cert, er)
+
     def batched_workspace_bytes(self, B: int, k_max: int, metric: int = IP, opts: vrs_opts | None = None) -> int:
         out = C.c_size_t()
         _check(lib().vrs_batched_workspace_bytes(self._h, B, k_max, metric,
@@ -343,6 +418,70 @@ class Table:
                                               _ptr(idx), _ptr(dist), _ptr(ws), ws.numel(), C.byref(o),
                                               _stream(stream), C.byref(h)))
         return BatchedGraph(h, (q, preds, ks, ws, self), ScanResult(idx, dist, nv, cert))
+
+
+class Index:
+    """A partition index over a table's vector column (``vrs_index_build``);
+    keep the table alive while the index is used."""
+
+    def __init__(self, table: "Table", nlist: int, iters: int = 10, stream=None):
+        h = C.c_void_p()
+        _check(lib().vrs_index_build(table.handle, int(nlist), int(iters), _stream(stream), C.byref(h)))
+        self._h, self.table = h, table
+        nl, ml = C.c_int32(), C.c_int64()
+        _check(lib().vrs_index_info(h, C.byref(nl), C.byref(ml)))
+        self.nlist, self.max_list = nl.value, ml.value
+
+    def export(self, stream=None):
+        cent = torch.empty((self.nlist, self.table.d), dtype=torch.float32, device="cuda")
+        off = torch.empty(self.nlist + 1, dtype=torch.int64, device="cuda")
+        ids = torch.empty(self.table.n, dtype=torch.int32, device="cuda")
+        _check(lib().vrs_index_export(self._h, _ptr(cent), _ptr(off), _ptr(ids), _stream(stream)))
+        return cent, off, ids
+
+    def workspace_bytes(self, B: int, k: int, nprobe: int, cap_c: int) -> int:
+        nb = C.c_size_t()
+        _check(lib().vrs_probe_workspace_bytes(self._h, B, k, nprobe, cap_c, C.byref(nb)))
+        return nb.value
+
+    def probe_topk(self, q: torch.Tensor, terms, k: int, metric: int = L2SQ, nprobe: int = 16,
+                   min_cand: int | None = None, cap_c: int = 1 << 16, ws: torch.Tensor | None = None,
+                   out: tuple | None = None, stream=None):
+        """Filtered probe: (idx [B, k], dist [B, k], partitions visited [B])."""
+        q = q.contiguous()
+        B = q.shape[0]
+        if out is None:
+            out = (torch.empty((B, k), dtype=torch.int64, device="cuda"),
+                   torch.empty((B, k), dtype=torch.float32, device="cuda"),
+                   torch.empty(B, dtype=torch.int32, device="cuda"))
+        idx, dist, taken = out
+        if ws is None:
+            ws = torch.empty(max(self.workspace_bytes(B, k, nprobe, cap_c), 256), dtype=torch.uint8, device="cuda")
+        p = make_pred(terms)
+        _check(lib().vrs_probe_topk(self._h, _ptr(q), B, C.byref(p), k, metric, nprobe,
+                                    int(min_cand if min_cand is not None else k), int(cap_c), _ptr(idx),
+                                    _ptr(dist), _ptr(taken), _ptr(ws), ws.numel(), _stream(stream)))
+        return idx, dist, taken
+
+    def plan_access(self, B: int, terms, k: int, nprobe: int = 16, cap_c: int = 1 << 16):
+        """(estimated scan ms, estimated probe ms, probe faster?)"""
+        sc, pr, up = C.c_double(), C.c_double(), C.c_int32()
+        p = make_pred(terms)
+        _check(lib().vrs_plan_access(self._h, B, C.byref(p), k, nprobe, cap_c, C.byref(sc), C.byref(pr),
+                                     C.byref(up)))
+        return sc.value, pr.value, bool(up.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().vrs_index_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().vrs_index_destroy(self._h)
+        except Exception:
+            pass
 
 
 class BatchedGraph:

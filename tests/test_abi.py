@@ -38,8 +38,9 @@ def test_exports_every_declared_symbol(L):
 def test_header_struct_layout_matches_binding():
     assert C.sizeof(vrs.vrs_range) == 24
     assert C.sizeof(vrs.vrs_pred) == 8 + 24 * vrs.MAX_TERMS
-    assert C.sizeof(vrs.vrs_opts) == 40  # 4 int32, 2 pointers, 1 int32 + tail padding
+    assert C.sizeof(vrs.vrs_opts) == 48  # 4 int32, 2 pointers, 2 int32, 1 pointer
     assert vrs.vrs_opts.passes.offset == 32
+    assert vrs.vrs_opts.err_ratio.offset == 40
 
 
 def test_host_side_argument_errors(L):
@@ -57,4 +58,7 @@ def test_host_side_argument_errors(L):
     nb = C.c_size_t()
     assert L.vrs_scan_workspace_bytes(None, 1, 1, None, C.byref(nb)) == vrs.VRS_E_ARG
     assert L.vrs_chooser_load(b"/nonexistent/chooser.bin") == vrs.VRS_E_ARG
+    assert L.vrs_range_workspace_bytes(None, 1, 1, C.byref(nb)) == vrs.VRS_E_ARG
+    assert L.vrs_scan_range(None, None, 1, None, 1, None, 1, None, None, None, None, 0, None,
+                            None) == vrs.VRS_E_ARG
     assert L.vrs_num_tiles() >= 4
