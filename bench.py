@@ -51,6 +51,7 @@ KERNEL_SOURCES = {
     "screen_stream": ["k_stream.hip"],
     "screen_mfma_f32": ["k_mfma.hip", "wave_topk.h"],
     "screen_mfma_bf16": ["k_mfma_bf16.hip", "wave_topk.h"],
+    "range_screen": ["k_range.hip", "exact64.h"],
 }
 
 
@@ -681,7 +682,9 @@ def bench_range(args):
     roof = roofline(n_sel, n, d, B, "f32", gather, 2, screen_ms)
     roof["kernel"] = "range_screen"
     roof["kernel_ms"] = round(screen_ms, 4)
-    roof["traffic"] = None
+    wkey = f"range-{n}x{d}-f32-ip-b{B}-s{args.sel:g}-cos{args.cos:g}-{'gather' if gather else 'mask'}"
+    roof["traffic"] = traffic_from_profiles("range_screen", wkey)
+    roof["traffic_key"] = wkey
     counts = out[2].cpu().numpy()
     cpu = None
     if not args.no_cpu:
