@@ -169,6 +169,21 @@ vrs_status vrs_scan_topk(vrs_table t, const float *q, int32_t B, const vrs_pred 
                          vrs_metric metric, int64_t *out_idx, float *out_dist, void *ws,
                          size_t ws_bytes, const vrs_opts *opts, void *stream);
 
+/* vrs_scan_topk without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and errors as
+ * vrs_scan_topk; the workspace is a static device array of
+ * VRS_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends.  A call whose scan needs more workspace than that
+ * (vrs_scan_workspace_bytes) returns VRS_E_WORKSPACE and launches nothing;
+ * nothing is allocated.  Every call on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (two streams, two threads) race, so the caller
+ * serialises them. */
+#define VRS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+vrs_status vrs_scan_topk_noalloc(vrs_table t, const float *q, int32_t B, const vrs_pred *pred,
+                                 int32_t k, vrs_metric metric, int64_t *out_idx, float *out_dist,
+                                 const vrs_opts *opts, void *stream);
+
 /* Threshold selection: for each query b, every row i that satisfies the
  * relational predicate and whose exact FP64 distance (the distance of this
  * header) is below thr[b], ascending by row id.  This is the selection with

@@ -19,7 +19,8 @@ BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.cpp", "planner.cpp", "batched.cpp", "range.cpp", "join.cpp", "probe.cpp", "k_build.hip", "k_select.hip",
            "k_stream.hip", "k_mfma.hip", "k_mfma_bf16.hip", "k_finish.hip", "k_batched.hip",
-           "k_mlp.hip", "k_range.hip", "k_probe.hip"]
+           "k_mlp.hip", "k_range.hip", "k_probe.hip",
+           "noalloc.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = ["-x", "hip", "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",

@@ -25,6 +25,7 @@ STRATEGY_AUTO, STRATEGY_MASK, STRATEGY_GATHER = 0, 1, 2
 CHOOSER_LEARNED, CHOOSER_HEURISTIC = 0, 1
 MAX_TERMS = 4
 MAX_BATCH = 65535  # largest B of one call (VRS_MAX_BATCH)
+NOALLOC_SCRATCH_BYTES = 64 << 20  # static workspace of vrs_scan_topk_noalloc (VRS_NOALLOC_SCRATCH_BYTES)
 
 EXPORTS = [
     "vrs_build_table", "vrs_destroy_table", "vrs_table_info", "vrs_table_export",
@@ -36,7 +37,7 @@ EXPORTS = [
     "vrs_batched_graph_create", "vrs_graph_launch", "vrs_graph_config", "vrs_graph_destroy",
     "vrs_range_workspace_bytes", "vrs_scan_range", "vrs_join_workspace_bytes", "vrs_join_topk",
     "vrs_index_build", "vrs_index_destroy", "vrs_index_info", "vrs_index_export", "vrs_probe_workspace_bytes",
-    "vrs_probe_topk", "vrs_plan_access",
+    "vrs_probe_topk", "vrs_plan_access", "vrs_scan_topk_noalloc",
 ]
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 6, 64, 16, 5648
 NUM_STAGES = 6
@@ -104,6 +105,7 @@ def lib() -> C.CDLL:
             "vrs_index_export": [P, P, P, P, P],
             "vrs_probe_workspace_bytes": [P, I32, I32, I32, I64, P],
             "vrs_plan_access": [P, I32, P, I32, I32, I64, P, P, P],
+            "vrs_scan_topk_noalloc": [P, P, I32, P, I32, I32, P, P, P, P],
             "vrs_probe_topk": [P, P, I32, P, I32, I32, I32, I64, I64, P, P, P, P, S, P],
             "vrs_join_topk": [P, P, P, I32, I32, P, P, P, S, P, P],
             "vrs_scan_range": [P, P, I32, P, I32, P, I32, P, P, P, P, S, P, P],
