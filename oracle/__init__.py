@@ -324,18 +324,22 @@ def ivf_build(table: Table, nlist: int, iters: int):
 
 
 def ivf_probe(table: Table, cent, list_off, list_ids, q, preds, k, metric, nprobe, min_cand, cap_c):
-    """Filtered probe: each query visits the partitions of its nprobe nearest
-    centroids (exact, by FP64 squared L2 and centroid id) in that order; a
-    visited partition contributes its rows that satisfy the predicate.  The
-    walk stops once min_cand rows qualified, or before a partition would
-    take the rows visited past cap_c (the first partition is always taken).
-    The result is the exact top-k of the collected rows by (FP64 distance,
-    id).  Returns (idx int64 [B, k], dist float32 [B, k], lists taken int64
+    """Filtered probe: each query walks the partitions in the order of their
+    centroids' distance to it (exact, by FP64 squared L2 and centroid id; at
+    most min(nlist, 256) of them); a visited partition contributes its rows
+    that satisfy the predicate.  The first nprobe partitions are visited;
+    past them the walk continues only while fewer than min_cand rows
+    qualified (pre-filtering: a selective predicate makes the probe visit
+    more of the index).  A partition that would take the rows visited past
+    cap_c ends the walk (the first partition is always visited).  The result
+    is the exact top-k of the collected rows by (FP64 distance, id).
+    Returns (idx int64 [B, k], dist float32 [B, k], partitions visited int64
     [B], candidates int64 [B])."""
     q = _c(q, np.float32)
     B = q.shape[0]
     zc = np.zeros((1, cent.shape[0]), np.int32)
-    coarse = scan_topk(Table(F32, cent, zc), q, [], nprobe, L2SQ)[0]
+    walk = min(cent.shape[0], 256)
+    coarse = scan_topk(Table(F32, cent, zc), q, [], walk, L2SQ)[0]
     _, nterms, cols, lo, hi = _terms(preds, B)
     idx = np.full((B, k), -1, np.int64)
     dist = np.full((B, k), np.inf, np.float32)
@@ -345,6 +349,8 @@ def ivf_probe(table: Table, cent, list_off, list_ids, q, preds, k, metric, nprob
         cand, visited = [], 0
         for lst in coarse[b]:
             if lst < 0:
+                break
+            if taken[b] >= nprobe and len(cand) >= min_cand:
                 break
             members = list_ids[list_off[lst]:list_off[lst + 1]]
             if taken[b] >= 1 and visited + members.size > cap_c:
@@ -356,8 +362,6 @@ def ivf_probe(table: Table, cent, list_off, list_ids, q, preds, k, metric, nprob
             cand.extend(members[ok].tolist())
             visited += members.size
             taken[b] += 1
-            if len(cand) >= min_cand:
-                break
         ncand[b] = len(cand)
         if cand:
             ids = np.array(cand, np.int64)

@@ -74,7 +74,7 @@ def test_probing_every_partition_is_the_scan(data):
     cent, assign, off, ids = O.ivf_build(t, 16, 3)
     q = x[[5, 700, 2999]] + np.float32(0.25)
     for pred in ([], [(0, 3, 9)]):
-        got = O.ivf_probe(t, cent, off, ids, q, pred, 10, O.L2SQ, 16, x.shape[0], x.shape[0])
+        got = O.ivf_probe(t, cent, off, ids, q, pred, 10, O.L2SQ, 16, 1, x.shape[0])
         ref = O.scan_topk(t, q, pred, 10, O.L2SQ)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
         assert (got[2] == 16).all()
@@ -88,17 +88,19 @@ def test_probe_candidates_nest_and_stopping_rules(data):
     exact = O.scan_topk(t, q, pred, 10, O.L2SQ)[0]
     prev_rec = -1.0
     for nprobe in (1, 2, 4, 8, 16):
-        got = O.ivf_probe(t, cent, off, ids, q, pred, 10, O.L2SQ, nprobe, x.shape[0], x.shape[0])
+        got = O.ivf_probe(t, cent, off, ids, q, pred, 10, O.L2SQ, nprobe, 1, x.shape[0])
         assert (got[2] == nprobe).all()
         rec = np.mean([len(set(got[0][b]) & set(exact[b])) / 10 for b in range(2)])
         assert rec >= prev_rec
         prev_rec = rec
     assert prev_rec == 1.0
-    # min_cand: the walk stops at the first partition that brings the
-    # qualifying count to it
-    got = O.ivf_probe(t, cent, off, ids, q, pred, 10, O.L2SQ, 16, 1, x.shape[0])
-    assert (got[2] == 1).all()
+    # past nprobe the walk goes on only while fewer than min_cand rows
+    # qualified: a selective predicate makes it visit more partitions
+    sel = [(0, 0, 1)]
+    few = O.ivf_probe(t, cent, off, ids, q, sel, 10, O.L2SQ, 1, 1, x.shape[0])
+    more = O.ivf_probe(t, cent, off, ids, q, sel, 10, O.L2SQ, 1, 60, x.shape[0])
+    assert (few[2] == 1).all() and (more[2] > 1).all() and (more[3] >= 60).all()
     # cap_c: a partition that would take the visited rows past the cap is not
     # visited (the first one always is)
-    got = O.ivf_probe(t, cent, off, ids, q, pred, 10, O.L2SQ, 16, x.shape[0], 1)
+    got = O.ivf_probe(t, cent, off, ids, q, pred, 10, O.L2SQ, 16, 1, 1)
     assert (got[2] == 1).all()
