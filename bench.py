@@ -60,8 +60,10 @@ def log(msg):
 
 
 def source_hash(kernel):
+    """Hash of the kernel's source file and the device headers it uses (host
+    structures elsewhere may change without changing the kernel)."""
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES[kernel] + ["common.h", "internal.h"]:
+    for f in KERNEL_SOURCES[kernel] + ["common.h"]:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -790,8 +792,9 @@ def bench_join(args):
 
 # ----------------------------------------------------------- probe vs scan
 def bench_probe(args):
-    """Scan vs probe (Section 5.3's question, Figs. 7-8): a 1M-row table, a
-    one-column range predicate of selectivity 1e-4..1, top-k; the exact scan
+    """Scan vs probe (Section 5.3's question, Figs. 7-8): the 10M x 128 table
+    with one attribute, a one-column range predicate of selectivity 1e-4..1,
+    top-k; the exact scan
     (the planner's mask or gather) against the filtered probe of a k-means
     partition index (nprobe nearest partitions, walk extended until k rows
     qualify), at one query and at a batch; recall of the probe against the
@@ -802,7 +805,7 @@ def bench_probe(args):
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    n, d, k = args.n or 1_000_000, args.d or 128, args.k
+    n, d, k = args.n or 10_000_000, args.d or 128, args.k
     nlist, nprobe = args.nlist, args.nprobe
     x = inputs.table(10, n, d, args.clusters)
     attr = inputs.attributes(10, n, 1, ATTR)
@@ -839,22 +842,28 @@ def bench_probe(args):
             ei, pi = ex.idx.cpu().numpy(), pr[0].cpu().numpy()
             rec = float(np.mean([len(set(pi[b][pi[b] >= 0]) & set(ei[b][ei[b] >= 0])) /
                                  max(1, int((ei[b] >= 0).sum())) for b in range(B)]))
+            est_scan, est_probe, use_probe = ix.plan_access(B, pred, k, nprobe, args.cap_c)
+            chosen = probe_ms if use_probe else scan_ms
             points.append({"batch": B, "sel": sel, "scan_ms": round(scan_ms, 4), "probe_ms": round(probe_ms, 4),
                            "probe_recall": round(rec, 4),
                            "partitions_visited_mean": round(float(pr[2].float().mean().item()), 2),
-                           "faster": "probe" if probe_ms < scan_ms else "scan"})
+                           "faster": "probe" if probe_ms < scan_ms else "scan",
+                           "model_scan_ms": round(est_scan, 4), "model_probe_ms": round(est_probe, 4),
+                           "model_pick": "probe" if use_probe else "scan",
+                           "model_regret": round(chosen / min(scan_ms, probe_ms) - 1.0, 4)})
             log(json.dumps(points[-1]))
     head = [p for p in points if p["batch"] == 1 and p["sel"] == 1.0][0]
     rec = {
-        "metric": "filtered top-k queries/s, probe path (k-means partitions) vs exact scan (N=1M)",
+        "metric": f"filtered top-k queries/s, probe path (k-means partitions) vs exact scan (N={n})",
         "value": round(1e3 / head["probe_ms"], 2), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
         "warmup": 1, "ms_per_step": head["probe_ms"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"clustered-gaussian N={n} d={d} f32, one-column range predicate, squared L2, "
                                f"top-{k}; index {nlist} partitions ({args.iters} k-means iterations), probe "
-                               f"{nprobe} partitions extended until k rows qualify, cap {args.cap_c}",
+                               f"{nprobe} partitions, more until k rows qualify, at most {args.cap_c} rows",
                    "index_build_s": round(build_s, 3), "largest_partition": ix.max_list},
         "points": points,
+        "model_picks_faster": f"{sum(p['model_pick'] == p['faster'] for p in points)}/{len(points)}",
         "note": "value = probe queries/s at one query, selectivity 1; the scan is exact, the probe approximate",
     }
     print(json.dumps(rec), flush=True)
@@ -870,7 +879,7 @@ def main():
     ap.add_argument("--nlist", type=int, default=1024, help="probe workload: partitions")
     ap.add_argument("--nprobe", type=int, default=16, help="probe workload: partitions probed")
     ap.add_argument("--iters", type=int, default=8, help="probe workload: k-means iterations")
-    ap.add_argument("--cap-c", type=int, default=1 << 16, help="probe workload: visited-row budget")
+    ap.add_argument("--cap-c", type=int, default=1 << 20, help="probe workload: visited-row budget")
     ap.add_argument("--probe-batch", type=int, default=256, help="probe workload: the batched point")
     ap.add_argument("--cos", type=float, default=0.9, help="range workload: cosine-similarity threshold")
     ap.add_argument("--cap", type=int, default=65536, help="range workload: result slots per query")
