@@ -265,21 +265,24 @@ vrs_status vrs_index_export(vrs_index ix, float *centroids, int64_t *list_off, i
  * queries with this predicate (selectivity from the table's column
  * histograms) and k, from a bytes-moved cost model: the scan reads the
  * predicate columns and either every row or the qualifying ones, once for
- * the batch; a probe reads, per query, the partitions its walk visits until
- * k rows qualify (between one and nprobe partitions, at most cap_c rows).
+ * the batch; a probe reads, per query, the partitions its walk visits (at
+ * least nprobe, more until k rows qualify, at most cap_c rows).
  * use_probe = 1 when the probe is estimated faster.  The probe's results are
  * approximate: a caller that needs the exact answer scans. */
 vrs_status vrs_plan_access(vrs_index ix, int32_t B, const vrs_pred *pred, int32_t k, int32_t nprobe,
                            int64_t cap_c, double *scan_ms, double *probe_ms, int32_t *use_probe);
-/* Filtered probe of B queries sharing one predicate.  Each query takes its
- * nprobe nearest centroids (exact, squared L2, ties by centroid id; 1 <=
- * nprobe <= min(256, nlist)) and visits their partitions in that order; a
+/* Filtered probe of B queries sharing one predicate.  Each query walks the
+ * partitions in the order of their centroids' distance to it (exact,
+ * squared L2, ties by centroid id; at most min(nlist, 256) partitions); a
  * visited partition contributes its rows that satisfy the predicate.  The
- * walk stops once min_cand rows qualified, or before a partition that would
- * take the rows visited past cap_c (the first partition is always visited).
- * The result is the exact top-k of the collected rows by (FP64 distance,
- * id), padded with (-1, +inf); out_taken [B] (or NULL) receives the number
- * of partitions visited.  ws >= vrs_probe_workspace_bytes(...). */
+ * first nprobe partitions (1 <= nprobe <= min(256, nlist)) are visited;
+ * past them the walk continues only while fewer than min_cand rows
+ * qualified (with pre-filtering a selective predicate makes the probe visit
+ * more of the index).  A partition that would take the rows visited past
+ * cap_c ends the walk (the first partition is always visited).  The result
+ * is the exact top-k of the collected rows by (FP64 distance, id), padded
+ * with (-1, +inf); out_taken [B] (or NULL) receives the number of
+ * partitions visited.  ws >= vrs_probe_workspace_bytes(...). */
 vrs_status vrs_probe_workspace_bytes(vrs_index ix, int32_t B, int32_t k, int32_t nprobe, int64_t cap_c,
                                      size_t *bytes);
 vrs_status vrs_probe_topk(vrs_index ix, const float *q, int32_t B, const vrs_pred *pred, int32_t k,
@@ -392,6 +395,13 @@ vrs_status vrs_mlp_adam(float *params, const float *grad, float *m, float *v, in
  * planner to the selectivity-threshold heuristic. */
 vrs_status vrs_chooser_set(const float *params, const float *feat_mean, const float *feat_std);
 vrs_status vrs_chooser_clear(void);
+
+/* The installed network's pick among the allowed arms (host inference, the
+ * same computation the planner runs per call): feats [6] as vrs_plan returns
+ * them, allowed [2 * vrs_num_tiles()] uint8 (arm = (strategy - 1) *
+ * vrs_num_tiles() + tile), *arm (host) = the allowed arm with the lowest
+ * predicted time, or -1 when no network is installed or nothing is allowed. */
+vrs_status vrs_chooser_pick(const float *feats, const uint8_t *allowed, int32_t *arm);
 
 /* Load chooser weights from a file written by the training tool (magic
  * "VRSCHOOS", version 1, then the params, mean and std as little-endian

@@ -190,70 +190,197 @@ def save(path, params, mean, std):
         f.write(np.asarray(std, "<f4").tobytes())
 
 
-def evaluate(workloads, F, Y, C, params, mean, std, tables):
-    """Regret of the learned and heuristic picks against the best timed arm."""
-    nt = vrs.num_tiles()
-    res = {"learned": [], "heuristic": []}
-    for j, w in enumerate(workloads):
-        y = Y[j]
+MFMA_TILES = range(4, 8)   # tile ids of the MFMA kernels (the rest stream), as the planner's table
+STREAM_QT = [1, 2, 4, 8]   # queries per workgroup of the streaming tiles
+
+
+def allowed_arms(f, y, nt):
+    """The arms the planner offers the network for a workload, from its
+    recorded features and timings: the arms available for the table and k
+    (timed or censored), no gather arm when the estimated selectivity is at
+    least 0.9, and no streaming tile that would re-read the table 8 or more
+    times when an MFMA tile is available (the rules of the planner)."""
+    valid = np.isfinite(y)
+    B = int(round(math.exp(f[2])))
+    est_sel = math.exp(f[3])
+    any_mfma = bool(valid[[s * nt + t for s in (0, 1) for t in MFMA_TILES]].any())
+    allowed = valid.copy()
+    if est_sel >= 0.9:
+        allowed[nt:] = False
+    for t, qt in enumerate(STREAM_QT):
+        if any_mfma and (B + qt - 1) // qt >= 8:
+            allowed[t] = allowed[nt + t] = False
+    return allowed
+
+
+def heuristic_arm(f, y, nt):
+    """The selectivity-threshold heuristic's arm: gather below an estimated
+    selectivity of 0.5; MFMA tile 4 from 8 queries, else the streaming tile
+    for the batch size."""
+    valid = np.isfinite(y)
+    B = int(round(math.exp(f[2])))
+    est_sel = math.exp(f[3])
+    if B >= 8 and valid[4]:
+        tile = 4
+    else:
+        tile = 0 if B <= 1 else (1 if B <= 2 else (2 if B <= 4 else 3))
+    return (1 if est_sel < 0.5 else 0) * nt + tile
+
+
+def evaluate_recorded(F, Y, params, mean, std):
+    """Regret (t_pick / t_best - 1) of the learned and heuristic picks on
+    recorded timings (a censored arm counts at its cost-model bound, at least
+    8 times the best).  Deterministic: the learned pick is the library's own
+    host inference (vrs_chooser_pick)."""
+    nt = Y.shape[1] // 2
+    vrs.chooser_set(params, mean, std)
+    rows = []
+    for f, y in zip(F, Y):
         if not np.isfinite(y).any():
             continue
         tbest = math.exp(np.nanmin(y))
-        T = tables.get(w.d, w.dtype, w.n)
-        width = inputs.two_term_width(w.sel, ATTR_RANGE)
-        pred = [(0, 0, width), (1, 0, width)]
-        vrs.chooser_set(params, mean, std)
-        _, s_l, t_l = T.plan(w.b, pred, w.k, vrs.IP, chooser=vrs.CHOOSER_LEARNED)
-        vrs.chooser_clear()
-        _, s_h, t_h = T.plan(w.b, pred, w.k, vrs.IP, chooser=vrs.CHOOSER_HEURISTIC)
-        for name, s, t in (("learned", s_l, t_l), ("heuristic", s_h, t_h)):
-            a = (s - 1) * nt + t
-            tp = math.exp(y[a]) if np.isfinite(y[a]) else tbest * 100.0
-            res[name].append(tp / tbest - 1.0)
+        al = allowed_arms(f, y, nt)
+        a_l = vrs.chooser_pick(f, al)
+        a_h = heuristic_arm(f, y, nt)
+        r = []
+        for a in (a_l, a_h):
+            tp = math.exp(y[a]) if a >= 0 and np.isfinite(y[a]) else tbest * 100.0
+            r.append(tp / tbest - 1.0)
+        rows.append((r[0], r[1], a_l, a_h, int(np.nanargmin(y))))
+    vrs.chooser_clear()
+    return rows
+
+
+def summarize(rows):
     out = {}
-    for name, r in res.items():
-        r = np.array(r)
+    for j, name in ((0, "learned"), (1, "heuristic")):
+        r = np.array([x[j] for x in rows])
         out[name] = {"mean_regret": float(r.mean()), "p95_regret": float(np.percentile(r, 95)),
                      "median_regret": float(np.median(r)), "frac_best": float((r < 1e-9).mean()),
                      "n": int(r.size)}
     return out
 
 
+def tail_analysis(F, Y, rows, top=12):
+    """Where the learned pick's regret concentrates: by dtype, dimension,
+    batch and selectivity buckets, and the worst workloads."""
+    keep = [i for i in range(len(F)) if np.isfinite(Y[i]).any()]
+    Fk = F[keep]
+    reg = np.array([x[0] for x in rows])
+    groups = {}
+    def add(key, mask):
+        if mask.any():
+            groups[key] = {"n": int(mask.sum()), "mean": round(float(reg[mask].mean()), 4),
+                           "p95": round(float(np.percentile(reg[mask], 95)), 4)}
+    for dt, nm in ((0, "f32"), (1, "bf16"), (2, "fp8")):
+        add(f"dtype={nm}", np.isclose(Fk[:, 5], dt))
+    for d in (64, 128, 768, 1536):
+        add(f"d={d}", np.isclose(np.exp(Fk[:, 1]), d, rtol=1e-3))
+    B = np.exp(Fk[:, 2])
+    for lo, hi in ((1, 8), (8, 64), (64, 512), (512, 5000)):
+        add(f"B=[{lo},{hi})", (B >= lo - 1e-6) & (B < hi))
+    s = np.exp(Fk[:, 3])
+    for lo, hi in ((0, 1e-3), (1e-3, 1e-2), (1e-2, 0.1), (0.1, 0.5), (0.5, 1.01)):
+        add(f"sel=[{lo:g},{hi:g})", (s >= lo) & (s < hi))
+    worst = np.argsort(-reg)[:top]
+    w = [{"N": int(round(math.exp(Fk[i, 0]))), "d": int(round(math.exp(Fk[i, 1]))),
+          "B": int(round(math.exp(Fk[i, 2]))), "est_sel": float(math.exp(Fk[i, 3])),
+          "k": int(round(math.exp(Fk[i, 4]))), "dtype": int(Fk[i, 5]), "regret": round(float(reg[i]), 3),
+          "learned_arm": rows[i][2], "best_arm": rows[i][4]} for i in worst]
+    return {"groups": groups, "worst": w}
+
+
+def load_weights(path):
+    raw = open(path, "rb").read()
+    assert raw[:8] == b"VRSCHOOS"
+    n = struct.unpack("<ii", raw[8:16])[1]
+    arr = np.frombuffer(raw[16:], "<f4")
+    return arr[:n].copy(), arr[n:n + 6].copy(), arr[n + 6:n + 12].copy()
+
+
+HELDOUT = os.path.join(HERE, "chooser_heldout.npz")
+TRAINSET = os.path.join(HERE, "chooser_train.npz")
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train", type=int, default=1250)
+    ap.add_argument("--phase", choices=["train", "heldout", "report"], required=True,
+                    help="train: time the training workloads and fit the network (GPU); heldout: time the "
+                         "held-out workloads exhaustively (GPU); report: regret on the recorded held-out "
+                         "timings (host only)")
+    ap.add_argument("--train", type=int, default=1350)
     ap.add_argument("--heldout", type=int, default=2000)
     ap.add_argument("--epochs", type=int, default=4000)
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--report", default=REPORT)
     args = ap.parse_args()
-    tables = Tables()
-    wt = inputs.chooser_workloads(CFG_TRAIN, args.train)
-    wh = inputs.chooser_workloads(CFG_HELDOUT, args.heldout)
-    t0 = time.time()
-    Ft, Yt, Ct = collect(wt, tables, "train")
-    t_collect = time.time() - t0
-    log(f"training set: {len(wt)} workloads, {int(np.isfinite(Yt).sum())} timed arms "
-        f"({int(Ct.sum())} censored), {t_collect:.0f}s")
-    t0 = time.time()
-    params, mean, std, loss = train(Ft, Yt, epochs=args.epochs)
-    t_train = time.time() - t0
-    log(f"trained in {t_train:.1f}s, final masked MSE {loss:.4f}")
-    save(args.out, params, mean, std)
-    t0 = time.time()
-    Fh, Yh, Ch = collect(wh, tables, "heldout")
-    t_held = time.time() - t0
-    ev = evaluate(wh, Fh, Yh, Ch, params, mean, std, tables)
-    report = {"train_workloads": len(wt), "train_timed_arms": int(np.isfinite(Yt).sum()),
-              "train_censored_arms": int(Ct.sum()), "heldout_workloads": len(wh),
-              "heldout_timed_arms": int(np.isfinite(Yh).sum()), "final_train_mse_ln_ms": loss,
-              "collect_train_s": round(t_collect, 1), "train_s": round(t_train, 2),
-              "collect_heldout_s": round(t_held, 1), "regret": ev, "arms": vrs.num_tiles() * 2,
-              "workload_ranges": {"n": "logU[1e5, 1e7] (d<=128), [1e5, 4e6] (768), [1e5, 2e6] (1536)",
-                                  "d": list(inputs.CHOOSER_DIMS), "B": "logU-int[1, 4096]",
-                                  "selectivity": "logU[1e-4, 1] (3/4), U[0.3, 1] (1/4)",
-                                  "k": [1, 10, 100],
-                                  "dtype": ["f32", "bf16", "fp8"], "metric": "IP (normalised rows)"}}
+    if args.phase == "train":
+        tables = Tables()
+        wt = inputs.chooser_workloads(CFG_TRAIN, args.train)
+        t0 = time.time()
+        Ft, Yt, Ct = collect(wt, tables, "train")
+        t_collect = time.time() - t0
+        log(f"training set: {len(wt)} workloads, {int(np.isfinite(Yt).sum())} timed arms "
+            f"({int(Ct.sum())} censored), {t_collect:.0f}s")
+        t0 = time.time()
+        params, mean, std, loss = train(Ft, Yt, epochs=args.epochs)
+        t_train = time.time() - t0
+        log(f"trained in {t_train:.1f}s, final masked MSE {loss:.4f}")
+        save(args.out, params, mean, std)
+        np.savez_compressed(TRAINSET, F=Ft, Y=Yt, C=Ct, collect_s=t_collect, train_s=t_train, loss=loss)
+        return
+    if args.phase == "heldout":
+        tables = Tables()
+        wh = inputs.chooser_workloads(CFG_HELDOUT, args.heldout)
+        t0 = time.time()
+        Fh, Yh, Ch = collect(wh, tables, "heldout")
+        t_held = time.time() - t0
+        # inference latency of the network on the GPU (one workload, the
+        # library's forward kernel), HIP events
+        params, mean, std = load_weights(args.out)
+        dp = torch.from_numpy(params).cuda()
+        x = torch.from_numpy(((Fh[:1] - mean) / std).astype(np.float32)).cuda()
+        act = torch.empty((1, 2 * vrs.MLP_HIDDEN), dtype=torch.float32, device="cuda")
+        vrs.mlp_forward(dp, x, act)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(100):
+            vrs.mlp_forward(dp, x, act)
+        e1.record()
+        e1.synchronize()
+        hip_us = e0.elapsed_time(e1) * 10.0
+        np.savez_compressed(HELDOUT, F=Fh, Y=Yh, C=Ch, collect_s=t_held, hip_infer_us=hip_us)
+        log(f"held-out: {len(wh)} workloads in {t_held:.0f}s, HIP inference {hip_us:.1f} us")
+        return
+    # report (host only)
+    params, mean, std = load_weights(args.out)
+    H = np.load(HELDOUT)
+    Fh, Yh, Ch = H["F"], H["Y"], H["C"]
+    rows = evaluate_recorded(Fh, Yh, params, mean, std)
+    vrs.chooser_set(params, mean, std)
+    f0 = Fh[0].astype(np.float32)
+    al = np.ones(Yh.shape[1], np.uint8)
+    t0 = time.perf_counter()
+    for _ in range(10000):
+        vrs.chooser_pick(f0, al)
+    host_us = (time.perf_counter() - t0) / 10000 * 1e6
+    vrs.chooser_clear()
+    report = {"heldout_workloads": int(Fh.shape[0]), "heldout_timed_arms": int((np.isfinite(Yh) & ~Ch).sum()),
+              "heldout_censored_arms": int(Ch.sum()), "collect_heldout_s": round(float(H["collect_s"]), 1),
+              "regret": summarize(rows), "tail": tail_analysis(Fh, Yh, rows),
+              "inference_us": {"host_pick_incl_python_call": round(host_us, 2),
+                               "hip_forward_one_workload": round(float(H["hip_infer_us"]), 2)},
+              "arms": int(Yh.shape[1])}
+    if os.path.exists(TRAINSET):
+        T = np.load(TRAINSET)
+        report.update({"train_workloads": int(T["F"].shape[0]),
+                       "train_timed_arms": int((np.isfinite(T["Y"]) & ~T["C"]).sum()),
+                       "train_censored_arms": int(T["C"].sum()), "collect_train_s": round(float(T["collect_s"]), 1),
+                       "train_s": round(float(T["train_s"]), 2), "final_train_mse_ln_ms": float(T["loss"])})
+    report["workload_ranges"] = {"n": "logU[1e5, 1e7] (d<=128), [1e5, 4e6] (768), [1e5, 2e6] (1536)",
+                                 "d": list(inputs.CHOOSER_DIMS), "B": "logU-int[1, 4096]",
+                                 "selectivity": "logU[1e-4, 1] (3/4), U[0.3, 1] (1/4)", "k": [1, 10, 100],
+                                 "dtype": ["f32", "bf16", "fp8"], "metric": "IP (normalised rows)"}
     with open(args.report, "w") as f:
         json.dump(report, f, indent=1)
     print(json.dumps(report["regret"]), flush=True)

@@ -308,6 +308,15 @@ vrs_status vrs_chooser_set(const float *params, const float *feat_mean, const fl
     return ok();
 }
 
+vrs_status vrs_chooser_pick(const float *feats, const uint8_t *allowed, int32_t *arm) {
+    if (!feats || !allowed || !arm) return fail(VRS_E_ARG, "NULL argument");
+    const int n = 2 * planner_num_tiles();
+    bool al[64];
+    for (int i = 0; i < n; ++i) al[i] = allowed[i] != 0;
+    *arm = chooser_pick(feats, al, n);
+    return ok();
+}
+
 vrs_status vrs_chooser_clear(void) {
     chooser_clear();
     return ok();

@@ -180,17 +180,39 @@ __global__ __launch_bounds__(256, 3) void batch_count_kernel(BatchArgs a) {
 
 // Per candidate: total count, and the sub-block counts turned into
 // exclusive prefix sums (each sub-block's first slot in the query's list).
-__global__ __launch_bounds__(256) void batch_total_kernel(BatchArgs a) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= a.B || !a.cand[b]) return;
+// Workgroup = 64 consecutive queries (one per lane, so every access is a
+// coalesced row of the [sub-block][query] array) x 16 waves, wave w taking
+// the w-th sixteenth of the sub-blocks: a pass of sums, a prefix across the
+// waves in LDS, then a pass writing the prefixes.
+constexpr int TOT_WAVES = 16;
+__global__ __launch_bounds__(64 * TOT_WAVES) void batch_total_kernel(BatchArgs a) {
+    __shared__ uint32_t part[TOT_WAVES][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int b = blockIdx.x * 64 + lane;
+    const bool act = b < a.B && a.cand[b];
+    const int per = (a.nsub + TOT_WAVES - 1) / TOT_WAVES;
+    const int s0 = wave * per, s1 = min(a.nsub, s0 + per);
+    uint32_t sum = 0;
+    if (act)
+        for (int sub = s0; sub < s1; ++sub) sum += a.subcnt[(int64_t)sub * a.B + b];
+    part[wave][lane] = sum;
+    __syncthreads();
     uint32_t run = 0;
-    for (int sub = 0; sub < a.nsub; ++sub) {
-        uint32_t *p = a.subcnt + (int64_t)sub * a.B + b;
-        const uint32_t c = *p;
-        *p = run;
-        run += c;
+    for (int w = 0; w < wave; ++w) run += part[w][lane];
+    if (act) {
+        constexpr int G = 16;  // reads issued before the writes that follow them
+        for (int sub = s0; sub < s1; sub += G) {
+            uint32_t c[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) c[g] = sub + g < s1 ? a.subcnt[(int64_t)(sub + g) * a.B + b] : 0u;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if (sub + g < s1) a.subcnt[(int64_t)(sub + g) * a.B + b] = run;
+                run += c[g];
+            }
+        }
+        if (wave == TOT_WAVES - 1) a.tot[b] = (int32_t)run;
     }
-    a.tot[b] = (int32_t)run;
 }
 
 // Exclusive prefix sum over the 1024 threads of the block; returns the total.
@@ -469,7 +491,7 @@ hipError_t launch_batch_classify(const BatchArgs &b, hipStream_t s) {
     batch_prepare_kernel<<<(b.B + 255) / 256, 256, 0, s>>>(b);
     if (b.rows_cap > 0) {
         batch_count_kernel<<<(b.nsub * QSPLIT + 3) / 4, 256, 0, s>>>(b);
-        batch_total_kernel<<<(b.B + 255) / 256, 256, 0, s>>>(b);
+        batch_total_kernel<<<(b.B + 63) / 64, 64 * TOT_WAVES, 0, s>>>(b);
     }
     batch_order_kernel<<<1, 1024, 0, s>>>(b);
     return hipGetLastError();

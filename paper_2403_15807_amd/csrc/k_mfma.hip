@@ -164,67 +164,72 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
         for (int p = 0; p < PASSES; ++p) *(float4 *)(xs + (p * RP + sr) * LDX + 4 * sc) = w[p];
         if (!__syncthreads_or(mine)) continue;
 
-        // ---- Q X^T for the wave's QW queries x 64 rows
-        f4v acc[MB][4];
+        // A wave whose queries all lie past the batch (a partial query
+        // tile) skips the product and the epilogue; it still stages rows
+        // and meets every barrier.
+        if (q0 + wave * QW < Bq) {
+            // ---- Q X^T for the wave's QW queries x 64 rows
+            f4v acc[MB][4];
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
+            for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = (f4v){0.f, 0.f, 0.f, 0.f};
+                for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = (f4v){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int t = 0; t < NT4; ++t) {
-            float4 bv[4];
+            for (int t = 0; t < NT4; ++t) {
+                float4 bv[4];
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb)
-                bv[nb] = *(const float4 *)(xs + (nb * 16 + (lane & 15)) * LDX + 16 * t + 4 * (lane >> 4));
-            // independent accumulators back to back: no MFMA waits on the
-            // result of the previous one
+                for (int nb = 0; nb < 4; ++nb)
+                    bv[nb] = *(const float4 *)(xs + (nb * 16 + (lane & 15)) * LDX + 16 * t + 4 * (lane >> 4));
+                // independent accumulators back to back: no MFMA waits on the
+                // result of the previous one
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
+                for (int c = 0; c < 4; ++c)
 #pragma unroll
-                for (int mb = 0; mb < MB; ++mb)
+                    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                    for (int nb = 0; nb < 4; ++nb)
-                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb][t][c], bv[nb][c], acc[mb][nb], 0, 0, 0);
-        }
+                        for (int nb = 0; nb < 4; ++nb)
+                            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb][t][c], bv[nb][c], acc[mb][nb], 0, 0, 0);
+            }
 
-        // ---- epilogue: lane holds queries QW*w + 16mb + 4(lane/16) + i, rows 16nb + lane%16
-        if ((((t0 - c0) / BR) & 15) == 15) {
-            for (int i = lane; i < QW; i += 64) {
-                const int qa = q0 + wave * QW + i;
-                if (qa < Bq) {
-                    const uint64_t g = __atomic_load_n((const unsigned long long *)(a.gthr + qa), __ATOMIC_RELAXED);
-                    if (g < thr[wave * QW + i]) thr[wave * QW + i] = g;
+            // ---- epilogue: lane holds queries QW*w + 16mb + 4(lane/16) + i, rows 16nb + lane%16
+            if ((((t0 - c0) / BR) & 15) == 15) {
+                for (int i = lane; i < QW; i += 64) {
+                    const int qa = q0 + wave * QW + i;
+                    if (qa < Bq) {
+                        const uint64_t g = __atomic_load_n((const unsigned long long *)(a.gthr + qa), __ATOMIC_RELAXED);
+                        if (g < thr[wave * QW + i]) thr[wave * QW + i] = g;
+                    }
                 }
             }
-        }
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            const int qb = wave * QW + mb * 16 + 4 * (lane >> 4);
-            uint64_t th[4];
-            float qn[4], thf[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                th[i] = thr[qb + i];
-                thf[i] = key_dist(th[i]);
-                qn[i] = qn2[qb + i];
-            }
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb) {
-                const int r = nb * 16 + (lane & 15);
-                if (!rq[r]) continue;
-                const int row = rid[r];
+            for (int mb = 0; mb < MB; ++mb) {
+                const int qb = wave * QW + mb * 16 + 4 * (lane >> 4);
+                uint64_t th[4];
+                float qn[4], thf[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int q = qb + i;
-                    const int qa = q0 + q;
-                    if (qa >= Bq) continue;
-                    if (BATCHED && !pred_eval(qpred[q], a.attr, a.an, row)) continue;
-                    const float dist = METRIC == VRS_L2SQ ? fmaf(-2.0f, acc[mb][nb][i], qn[i] + xn2[r]) : -acc[mb][nb][i];
-                    if (!(dist <= thf[i])) continue;
-                    const uint64_t key = make_key(dist, (uint32_t)row);
-                    if (key < th[i]) {
-                        const int slot = atomicAdd(&cnt[q], 1);
-                        a.cbuf[((int64_t)qa * nchunks + chunk) * CBq + slot] = key;
+                    th[i] = thr[qb + i];
+                    thf[i] = key_dist(th[i]);
+                    qn[i] = qn2[qb + i];
+                }
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb) {
+                    const int r = nb * 16 + (lane & 15);
+                    if (!rq[r]) continue;
+                    const int row = rid[r];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int q = qb + i;
+                        const int qa = q0 + q;
+                        if (qa >= Bq) continue;
+                        if (BATCHED && !pred_eval(qpred[q], a.attr, a.an, row)) continue;
+                        const float dist = METRIC == VRS_L2SQ ? fmaf(-2.0f, acc[mb][nb][i], qn[i] + xn2[r]) : -acc[mb][nb][i];
+                        if (!(dist <= thf[i])) continue;
+                        const uint64_t key = make_key(dist, (uint32_t)row);
+                        if (key < th[i]) {
+                            const int slot = atomicAdd(&cnt[q], 1);
+                            a.cbuf[((int64_t)qa * nchunks + chunk) * CBq + slot] = key;
+                        }
                     }
                 }
             }

@@ -37,7 +37,7 @@ EXPORTS = [
     "vrs_batched_graph_create", "vrs_graph_launch", "vrs_graph_config", "vrs_graph_destroy",
     "vrs_range_workspace_bytes", "vrs_scan_range", "vrs_join_workspace_bytes", "vrs_join_topk",
     "vrs_index_build", "vrs_index_destroy", "vrs_index_info", "vrs_index_export", "vrs_probe_workspace_bytes",
-    "vrs_probe_topk", "vrs_plan_access", "vrs_scan_topk_noalloc",
+    "vrs_probe_topk", "vrs_plan_access", "vrs_scan_topk_noalloc", "vrs_chooser_pick",
 ]
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 6, 64, 16, 5648
 NUM_STAGES = 6
@@ -106,6 +106,7 @@ def lib() -> C.CDLL:
             "vrs_probe_workspace_bytes": [P, I32, I32, I32, I64, P],
             "vrs_plan_access": [P, I32, P, I32, I32, I64, P, P, P],
             "vrs_scan_topk_noalloc": [P, P, I32, P, I32, I32, P, P, P, P],
+            "vrs_chooser_pick": [P, P, P],
             "vrs_probe_topk": [P, P, I32, P, I32, I32, I32, I64, I64, P, P, P, P, S, P],
             "vrs_join_topk": [P, P, P, I32, I32, P, P, P, S, P, P],
             "vrs_scan_range": [P, P, I32, P, I32, P, I32, P, P, P, P, S, P, P],
@@ -565,6 +566,17 @@ def chooser_set(params, mean, std):
 
 def chooser_clear():
     _check(lib().vrs_chooser_clear())
+
+
+def chooser_pick(feats, allowed) -> int:
+    """The installed network's pick among the allowed arms (host inference,
+    as the planner runs it); -1 without a network."""
+    import numpy as np
+    f = np.ascontiguousarray(feats, dtype=np.float32)
+    al = np.ascontiguousarray(allowed, dtype=np.uint8)
+    arm = C.c_int32()
+    _check(lib().vrs_chooser_pick(f.ctypes.data, al.ctypes.data, C.byref(arm)))
+    return arm.value
 
 
 def num_tiles() -> int:

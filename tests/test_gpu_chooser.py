@@ -1,9 +1,9 @@
-"""The trained access-path chooser against the selectivity-threshold
-heuristic on held-out workloads of the chooser's distribution (kept small so
-the test runs in seconds): the learned picks must be faster in total, and
-every arm must return the same result."""
+"""The access-path chooser never changes results: on workloads of the
+chooser's distribution (float32, bfloat16 and FP8 tables), the learned pick,
+the heuristic pick and every other available arm return the same ids and
+distances.  (Its timing quality is judged on recorded held-out timings by
+tests/test_chooser_regret.py, deterministically.)"""
 
-import math
 import os
 
 import numpy as np
@@ -22,39 +22,30 @@ def test_shipped_weights_load():
     assert vrs.lib().vrs_chooser_load(vrs.CHOOSER_WEIGHTS.encode()) == vrs.VRS_OK
 
 
-def _time(T, q, pred, k, chooser, reps=3):
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    T.scan_topk(q, pred, k, vrs.IP, chooser=chooser)
-    best = math.inf
-    for _ in range(reps):
-        e0.record()
-        r = T.scan_topk(q, pred, k, vrs.IP, chooser=chooser)
-        e1.record()
-        e1.synchronize()
-        best = min(best, e0.elapsed_time(e1))
-    return best, r
-
-
-def test_learned_picks_beat_the_heuristic_and_never_change_results():
+@pytest.mark.parametrize("store,d", [(vrs.F32, 128), (vrs.BF16, 768), (vrs.FP8E4M3, 768)])
+def test_every_arm_returns_the_same_result(store, d):
     vrs.lib().vrs_chooser_load(vrs.CHOOSER_WEIGHTS.encode())
-    ws = [w for w in inputs.chooser_workloads(CH.CFG_HELDOUT + 7, 200)
-          if w.d <= 128 and w.n <= 3_000_000][:16]
-    assert len(ws) >= 8
-    src = {}
-    tl = th = 0.0
-    for w in ws:
-        if (w.d, w.dtype) not in src:
-            x = inputs.table(7, 3_000_000, w.d, 1000)
-            a = inputs.attributes(7, 3_000_000, 2, CH.ATTR_RANGE)
-            src[(w.d, w.dtype)] = vrs.Table(torch.from_numpy(x).cuda(), torch.from_numpy(a).cuda(),
-                                            store=w.dtype, normalize=True)
-        T = src[(w.d, w.dtype)].view(w.n)
-        q = torch.from_numpy(inputs.queries(7, w.b, w.d, 1000, stream_offset=w.seed % 1000)).cuda()
-        width = inputs.two_term_width(w.sel, CH.ATTR_RANGE)
+    n = 400_000
+    x = inputs.table(7, n, d, 1000)
+    a = inputs.attributes(7, n, 2, CH.ATTR_RANGE)
+    T = vrs.Table(torch.from_numpy(x).cuda(), torch.from_numpy(a).cuda(), store=store, normalize=True)
+    nt = vrs.num_tiles()
+    for B, sel, k in ((1, 0.3, 10), (24, 0.01, 100), (300, 0.9, 1)):
+        q = torch.from_numpy(inputs.queries(7, B, d, 1000, stream_offset=B)).cuda()
+        width = inputs.two_term_width(sel, CH.ATTR_RANGE)
         pred = [(0, 0, width), (1, 0, width)]
-        t_l, r_l = _time(T, q, pred, w.k, vrs.CHOOSER_LEARNED)
-        t_h, r_h = _time(T, q, pred, w.k, vrs.CHOOSER_HEURISTIC)
-        assert torch.equal(r_l.idx, r_h.idx) and torch.equal(r_l.dist, r_h.dist)
-        tl += t_l
-        th += t_h
-    assert tl <= 1.05 * th, (tl, th)
+        ref = T.scan_topk(q, pred, k, vrs.IP, chooser=vrs.CHOOSER_LEARNED)
+        outs = [T.scan_topk(q, pred, k, vrs.IP, chooser=vrs.CHOOSER_HEURISTIC)]
+        for s in (vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER):
+            for t in range(nt):
+                _, su, tu = T.plan(B, pred, k, vrs.IP, strategy=s, tile=t, chooser=vrs.CHOOSER_HEURISTIC)
+                if su != s or tu != t:
+                    continue  # arm not available for this table and k
+                if t < 4 and (B + [1, 2, 4, 8][t] - 1) // [1, 2, 4, 8][t] > 64:
+                    continue  # a streaming tile that would re-read the table too often to run here
+                outs.append(T.scan_topk(q, pred, k, vrs.IP, strategy=s, tile=t))
+        torch.cuda.synchronize()
+        for r in outs:
+            assert torch.equal(r.idx, ref.idx), (store, B, sel, k)
+            assert torch.equal(r.dist.view(torch.int32), ref.dist.view(torch.int32)), (store, B, sel, k)
+    T.close()
