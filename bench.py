@@ -806,7 +806,8 @@ def bench_probe(args):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     n, d, k = args.n or 10_000_000, args.d or 128, args.k
-    nlist, nprobe = args.nlist, args.nprobe
+    nlist = args.nlist
+    nprobes = [int(v) for v in str(args.nprobe).split(",")]
     x = inputs.table(10, n, d, args.clusters)
     attr = inputs.attributes(10, n, 1, ATTR)
     T = vrs.Table(torch.from_numpy(x).to(dev), torch.from_numpy(attr).to(dev))
@@ -816,43 +817,57 @@ def bench_probe(args):
     torch.cuda.synchronize()
     build_s = time.time() - t0
     log(f"index: {nlist} partitions, {args.iters} iterations in {build_s:.2f}s, largest {ix.max_list}")
+    cent, off, _ = [t.cpu().numpy() for t in ix.export()]
+    sizes = np.diff(off)
+    size_biased = float((sizes.astype(np.float64) ** 2).sum() / n)
+
+    def visited_rows(qh, taken):
+        # rows in the partitions each query visited (its nearest centroids, FP64)
+        dd = ((qh.astype(np.float64)[:, None, :] - cent.astype(np.float64)[None]) ** 2).sum(-1)
+        order = np.argsort(dd, axis=1, kind="stable")
+        return float(np.mean([sizes[order[b, :taken[b]]].sum() for b in range(qh.shape[0])]))
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) / reps * 1e3
+
     points = []
-    for B in (1, args.probe_batch):
-        q = torch.from_numpy(inputs.queries(10, B, d, args.clusters)).to(dev)
+    for B in (1, 16, args.probe_batch):
+        qh = inputs.queries(10, B, d, args.clusters)
+        q = torch.from_numpy(qh).to(dev)
         for sel in (1e-4, 1e-3, 1e-2, 0.1, 0.5, 1.0):
             pred = [(0, 0, max(1, int(round(sel * ATTR))))]
             ex = T.scan_topk(q, pred, k, vrs.L2SQ)
-            ws = torch.empty(ix.workspace_bytes(B, k, nprobe, args.cap_c), dtype=torch.uint8, device=dev)
-            pr = ix.probe_topk(q, pred, k, vrs.L2SQ, nprobe, k, args.cap_c, ws=ws)
-            torch.cuda.synchronize()
-
-            def timed(fn, reps):
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                for _ in range(reps):
-                    fn()
-                torch.cuda.synchronize()
-                return (time.perf_counter() - t1) / reps * 1e3
-
             o = vrs.vrs_opts()
             sws = T.workspace(B, k, o)
             scan_ms = timed(lambda: T.scan_topk(q, pred, k, vrs.L2SQ, ws=sws), args.steps)
-            probe_ms = timed(lambda: ix.probe_topk(q, pred, k, vrs.L2SQ, nprobe, k, args.cap_c, ws=ws,
-                                                   out=pr), args.steps)
-            ei, pi = ex.idx.cpu().numpy(), pr[0].cpu().numpy()
-            rec = float(np.mean([len(set(pi[b][pi[b] >= 0]) & set(ei[b][ei[b] >= 0])) /
-                                 max(1, int((ei[b] >= 0).sum())) for b in range(B)]))
-            est_scan, est_probe, use_probe = ix.plan_access(B, pred, k, nprobe, args.cap_c)
-            chosen = probe_ms if use_probe else scan_ms
-            points.append({"batch": B, "sel": sel, "scan_ms": round(scan_ms, 4), "probe_ms": round(probe_ms, 4),
-                           "probe_recall": round(rec, 4),
-                           "partitions_visited_mean": round(float(pr[2].float().mean().item()), 2),
-                           "faster": "probe" if probe_ms < scan_ms else "scan",
-                           "model_scan_ms": round(est_scan, 4), "model_probe_ms": round(est_probe, 4),
-                           "model_pick": "probe" if use_probe else "scan",
-                           "model_regret": round(chosen / min(scan_ms, probe_ms) - 1.0, 4)})
-            log(json.dumps(points[-1]))
-    head = [p for p in points if p["batch"] == 1 and p["sel"] == 1.0][0]
+            ei = ex.idx.cpu().numpy()
+            for nprobe in nprobes:
+                ws = torch.empty(ix.workspace_bytes(B, k, nprobe, args.cap_c), dtype=torch.uint8, device=dev)
+                pr = ix.probe_topk(q, pred, k, vrs.L2SQ, nprobe, k, args.cap_c, ws=ws)
+                torch.cuda.synchronize()
+                probe_ms = timed(lambda: ix.probe_topk(q, pred, k, vrs.L2SQ, nprobe, k, args.cap_c, ws=ws,
+                                                       out=pr), args.steps)
+                pi = pr[0].cpu().numpy()
+                taken = pr[2].cpu().numpy()
+                rec = float(np.mean([len(set(pi[b][pi[b] >= 0]) & set(ei[b][ei[b] >= 0])) /
+                                     max(1, int((ei[b] >= 0).sum())) for b in range(B)]))
+                est_scan, est_probe, use_probe = ix.plan_access(B, pred, k, nprobe, args.cap_c)
+                chosen = probe_ms if use_probe else scan_ms
+                points.append({"batch": B, "sel": sel, "nprobe": nprobe, "scan_ms": round(scan_ms, 4),
+                               "probe_ms": round(probe_ms, 4), "probe_recall": round(rec, 4),
+                               "partitions_visited_mean": round(float(taken.mean()), 2),
+                               "rows_visited_mean": round(visited_rows(qh, taken)),
+                               "faster": "probe" if probe_ms < scan_ms else "scan",
+                               "model_scan_ms": round(est_scan, 4), "model_probe_ms": round(est_probe, 4),
+                               "model_pick": "probe" if use_probe else "scan",
+                               "model_regret": round(chosen / min(scan_ms, probe_ms) - 1.0, 4)})
+                log(json.dumps(points[-1]))
+    head = [p for p in points if p["batch"] == 1 and p["sel"] == 1.0 and p["nprobe"] == nprobes[0]][0]
     rec = {
         "metric": f"filtered top-k queries/s, probe path (k-means partitions) vs exact scan (N={n})",
         "value": round(1e3 / head["probe_ms"], 2), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
@@ -860,8 +875,9 @@ def bench_probe(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"clustered-gaussian N={n} d={d} f32, one-column range predicate, squared L2, "
                                f"top-{k}; index {nlist} partitions ({args.iters} k-means iterations), probe "
-                               f"{nprobe} partitions, more until k rows qualify, at most {args.cap_c} rows",
-                   "index_build_s": round(build_s, 3), "largest_partition": ix.max_list},
+                               f"{nprobes} partitions, more until k rows qualify, at most {args.cap_c} rows",
+                   "index_build_s": round(build_s, 3), "largest_partition": ix.max_list,
+                   "size_biased_partition": round(size_biased)},
         "points": points,
         "model_picks_faster": f"{sum(p['model_pick'] == p['faster'] for p in points)}/{len(points)}",
         "note": "value = probe queries/s at one query, selectivity 1; the scan is exact, the probe approximate",
@@ -877,7 +893,7 @@ def main():
     ap.add_argument("--workload", choices=["scan", "batched", "precision", "range", "join", "probe"],
                     default="scan")
     ap.add_argument("--nlist", type=int, default=1024, help="probe workload: partitions")
-    ap.add_argument("--nprobe", type=int, default=16, help="probe workload: partitions probed")
+    ap.add_argument("--nprobe", default="4,16", help="probe workload: partitions probed (comma list)")
     ap.add_argument("--iters", type=int, default=8, help="probe workload: k-means iterations")
     ap.add_argument("--cap-c", type=int, default=1 << 20, help="probe workload: visited-row budget")
     ap.add_argument("--probe-batch", type=int, default=256, help="probe workload: the batched point")

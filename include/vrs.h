@@ -250,8 +250,11 @@ vrs_status vrs_join_topk(vrs_table R, vrs_table S, const vrs_pred *pred, int32_t
  * assignment is the row's exact nearest centroid (by FP64 distance, then
  * centroid id); a centroid moves to its partition's mean (an FP64 running
  * sum over the partition's rows in ascending order, divided by the count,
- * rounded to float32; an empty partition keeps its centroid).  The table
- * must outlive the index.  Allocates and synchronises `stream`. */
+ * rounded to float32; an empty partition keeps its centroid).  The index
+ * keeps its own copy of the stored rows (and FP8 scales) and of the
+ * predicate columns in partition order, so that a probe reads every
+ * partition contiguously: about the table's size again in device memory.
+ * The table must outlive the index.  Allocates and synchronises `stream`. */
 vrs_status vrs_index_build(vrs_table t, int32_t nlist, int32_t iters, void *stream, vrs_index *out);
 vrs_status vrs_index_destroy(vrs_index ix);
 /* nlist and the largest partition (host pointers, may be NULL). */
@@ -262,11 +265,14 @@ vrs_status vrs_index_export(vrs_index ix, float *centroids, int64_t *list_off, i
                             void *stream);
 /* Scan or probe (the access-path choice of Section 5.3): estimated times
  * (ms, host pointers, may be NULL) of the exact scan and of the probe for B
- * queries with this predicate (selectivity from the table's column
- * histograms) and k, from a bytes-moved cost model: the scan reads the
- * predicate columns and either every row or the qualifying ones, once for
- * the batch; a probe reads, per query, the partitions its walk visits (at
- * least nprobe, more until k rows qualify, at most cap_c rows).
+ * queries with this predicate (selectivity s from the table's column
+ * histograms) and k.  The scan: the installed chooser network's predicted
+ * time of the arm it would pick, else a bytes-moved model (the predicate
+ * columns and either every row or the qualifying ones, once for the batch).
+ * The probe: per query the rows its walk visits (at least nprobe
+ * partitions of the size-biased mean partition size, more until k rows
+ * qualify, at most cap_c rows), then a linear time model of the predicate
+ * columns and qualifying rows the batch reads, fitted to measured probes.
  * use_probe = 1 when the probe is estimated faster.  The probe's results are
  * approximate: a caller that needs the exact answer scans. */
 vrs_status vrs_plan_access(vrs_index ix, int32_t B, const vrs_pred *pred, int32_t k, int32_t nprobe,

@@ -313,6 +313,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=4000)
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--report", default=REPORT)
+    ap.add_argument("--trainset", default=TRAINSET, help="recorded training timings (.npz)")
+    ap.add_argument("--heldout-file", default=HELDOUT, help="recorded held-out timings (.npz)")
     args = ap.parse_args()
     if args.phase == "train":
         tables = Tables()
@@ -327,7 +329,7 @@ def main():
         t_train = time.time() - t0
         log(f"trained in {t_train:.1f}s, final masked MSE {loss:.4f}")
         save(args.out, params, mean, std)
-        np.savez_compressed(TRAINSET, F=Ft, Y=Yt, C=Ct, collect_s=t_collect, train_s=t_train, loss=loss)
+        np.savez_compressed(args.trainset, F=Ft, Y=Yt, C=Ct, collect_s=t_collect, train_s=t_train, loss=loss)
         return
     if args.phase == "heldout":
         tables = Tables()
@@ -349,12 +351,12 @@ def main():
         e1.record()
         e1.synchronize()
         hip_us = e0.elapsed_time(e1) * 10.0
-        np.savez_compressed(HELDOUT, F=Fh, Y=Yh, C=Ch, collect_s=t_held, hip_infer_us=hip_us)
+        np.savez_compressed(args.heldout_file, F=Fh, Y=Yh, C=Ch, collect_s=t_held, hip_infer_us=hip_us)
         log(f"held-out: {len(wh)} workloads in {t_held:.0f}s, HIP inference {hip_us:.1f} us")
         return
     # report (host only)
     params, mean, std = load_weights(args.out)
-    H = np.load(HELDOUT)
+    H = np.load(args.heldout_file)
     Fh, Yh, Ch = H["F"], H["Y"], H["C"]
     rows = evaluate_recorded(Fh, Yh, params, mean, std)
     vrs.chooser_set(params, mean, std)
@@ -371,8 +373,8 @@ def main():
               "inference_us": {"host_pick_incl_python_call": round(host_us, 2),
                                "hip_forward_one_workload": round(float(H["hip_infer_us"]), 2)},
               "arms": int(Yh.shape[1])}
-    if os.path.exists(TRAINSET):
-        T = np.load(TRAINSET)
+    if os.path.exists(args.trainset):
+        T = np.load(args.trainset)
         report.update({"train_workloads": int(T["F"].shape[0]),
                        "train_timed_arms": int((np.isfinite(T["Y"]) & ~T["C"]).sum()),
                        "train_censored_arms": int(T["C"].sum()), "collect_train_s": round(float(T["collect_s"]), 1),

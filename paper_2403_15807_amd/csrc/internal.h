@@ -39,8 +39,15 @@ struct vrs_index_s {
     float *cent = nullptr;               // [nlist][d]
     int64_t *list_off = nullptr;         // [nlist + 1]
     int32_t *ids = nullptr;              // [n] rows of every partition, ascending
+    // The table's stored rows, FP8 scales and predicate columns copied into
+    // the same partition order (position m holds row ids[m]), so that a
+    // probe reads a partition's data contiguously.
+    void *rows_p = nullptr;              // [n][dp] as stored
+    float *scale_p = nullptr;            // [n] (FP8 tables)
+    int32_t *attr_p = nullptr;           // [n_attr][n]
     int32_t nlist = 0, d = 0;
     int64_t max_list = 0;                // largest partition
+    double size_biased = 0.0;            // mean size of a row's partition: sum of size^2 / n
 };
 
 namespace vrs {
@@ -404,29 +411,40 @@ hipError_t launch_range(const RangeArgs &a, int qt, int step, hipStream_t s);
 
 // ---- probe path (k_probe.hip): partition index build and filtered probe
 constexpr int PROBE_LIST_BLOCK = 4096;  // rows placed by one thread
-constexpr int PROBE_CHUNK = 2048;       // candidates scored by one workgroup
+constexpr int PROBE_MAX_WALK = 256;     // partitions ordered per query
+constexpr int PROBE_SORT_MAX = 4096;    // centroids sorted at once by the coarse scan
+constexpr int PROBE_COUNT_R = 8;        // rows per thread in one counting step
+constexpr int PROBE_FAN = 16;           // partial lists merged by one workgroup
+constexpr int PROBE_MAX_GS = 512;       // scoring workgroups per query at most
 struct ProbeArgs {
-    const void *rows;
-    const float *scale;
+    const void *rows;              // partition-ordered rows [n][dp]
+    const float *scale;            // partition-ordered FP8 scales, or null
     int32_t d, dp;
     vrs_dtype store;
     int metric;
-    const int32_t *attr;
+    const int32_t *attr;           // partition-ordered predicate columns [n_attr][an]
     int64_t an;
     PredDev pred;
     const float *q;                // [B][d]
     int32_t B, k;
-    const int64_t *coarse;         // [B][nprobe] partitions in centroid order (-1 pads)
-    int32_t nprobe;
+    const void *cent_rows;         // centroid table rows [nlist][cdp] float32
+    int32_t cdp, nlist;
+    int64_t *coarse_out;           // [B][walk] partitions in centroid order (-1 pads)
+    const int64_t *coarse;         // (the same array, read by the walk)
+    int32_t walk;                  // partitions ordered per query: min(nlist, 256)
+    int32_t nprobe;                // partitions always visited
     int64_t min_cand, cap_c;       // stopping rules of the walk
     const int64_t *list_off;       // [nlist + 1]
     const int32_t *ids;            // rows of every partition, ascending
-    int32_t *cand;                 // [B][cand_cap] collected rows
-    int64_t cand_cap;
-    int32_t *ncand;                // [B]
+    int64_t *pre;                  // [B][walk + 1] rows in the first i partitions of the walk
+    uint32_t *cnt;                 // [B][walk] qualifying rows of every counted partition
+    int64_t *state;                // [B][4] open, walk position, qualifying rows so far, limit
+    int32_t w0, w1;                // walk positions counted by this round
+    int32_t gc, gs;                // counting / scoring workgroups per query
+    int32_t srows;                 // rows per scoring step (256 per thread-row)
     int32_t *taken;                // [B] partitions visited, or null
-    int32_t nchunk;                // candidate chunks per query
-    uint64_t *part;                // [B][nchunk][k][2] per-chunk exact keys
+    uint64_t *part;                // [B][gs][k][2] exact keys of every scoring workgroup
+    uint64_t *part2;               // [B][ceil(gs / PROBE_FAN)][k][2] merged groups, or null
     int64_t *out_idx;              // [B][k]
     float *out_dist;               // [B][k]
 };
@@ -436,6 +454,11 @@ struct ProbeArgs {
 hipError_t launch_index_lists(const int64_t *assign, int64_t n, int nlist, uint32_t *cnt, int64_t *size,
                               int64_t *off, int32_t *ids, hipStream_t s);
 hipError_t launch_centroid_init(const float *x32, int64_t n, int nlist, int d, float *cent, hipStream_t s);
+// Copies of the rows (row_bytes each, a multiple of 16), FP8 scales (or
+// null) and n_attr predicate columns (stride an) in the order of ids [n].
+hipError_t launch_list_gather(const int32_t *ids, int64_t n, const void *rows, int64_t row_bytes,
+                              const float *scale, const int32_t *attr, int n_attr, int64_t an, void *rows_p,
+                              float *scale_p, int32_t *attr_p, hipStream_t s);
 hipError_t launch_centroid_mean(const float *x32, int nlist, int d, const int64_t *off, const int32_t *ids,
                                 float *cent, hipStream_t s);
 hipError_t launch_probe(const ProbeArgs &a, hipStream_t s);

@@ -255,6 +255,48 @@ void plan_features(const vrs_table_s *t, int B, double sel, int k, float f[6]) {
     f[5] = (float)t->store;
 }
 
+// The arms offered to the learned chooser for a call.
+static void chooser_arms(const vrs_table_s *t, int B, int k, int metric, bool batched, double est_sel,
+                         const vrs_opts *opts, bool *allowed) {
+    const int want_s = opts ? opts->strategy : VRS_STRATEGY_AUTO;
+    const int want_t = opts ? opts->tile : -1;
+    // A streaming tile re-reads the table once per query tile; when an MFMA
+    // tile exists, arms that would re-read it 8 or more times are not
+    // offered to the network (it has not seen every such shape).
+    bool any_mfma = false;
+    for (int tile = 0; tile < kNumTiles; ++tile)
+        if (kTiles[tile].kind == 1 && tile_ok(t, B, k, opts, tile, metric)) any_mfma = true;
+    // When the predicate keeps (almost) every row, the gathered scan can
+    // skip nothing and still pays the selection pass and the id reads: only
+    // masked arms are offered (the network has seen few such workloads and
+    // can misjudge the small margin).
+    const bool dense = est_sel >= 0.9;
+    for (int sidx = 0; sidx < 2; ++sidx)
+        for (int tile = 0; tile < kNumTiles; ++tile) {
+            const int st = sidx + 1;
+            bool ok = tile_ok(t, B, k, opts, tile, metric);
+            if (want_s != VRS_STRATEGY_AUTO && st != want_s) ok = false;
+            if (want_s == VRS_STRATEGY_AUTO && dense && st == VRS_STRATEGY_GATHER) ok = false;
+            if (batched && st != VRS_STRATEGY_MASK) ok = false;
+            if (want_t >= 0 && tile != want_t) ok = false;
+            if (want_t < 0 && any_mfma && kTiles[tile].kind == 0 && (B + kTiles[tile].qt - 1) / kTiles[tile].qt >= 8)
+                ok = false;
+            allowed[sidx * kNumTiles + tile] = ok;
+        }
+}
+
+double plan_predict_ms(const vrs_table_s *t, int B, const PredDev &p, int k, int metric) {
+    if (!chooser_ready()) return -1.0;
+    const double est_sel = estimate_selectivity(t, p);
+    float feats[6];
+    plan_features(t, B, est_sel, k, feats);
+    bool allowed[2 * kNumTiles];
+    chooser_arms(t, B, k, metric, false, est_sel, nullptr, allowed);
+    float y = 0.0f;
+    if (chooser_pick_value(feats, allowed, 2 * kNumTiles, &y) < 0) return -1.0;
+    return std::exp((double)y);
+}
+
 void plan_decide(const vrs_table_s *t, int B, const PredDev &p, bool batched, int k, int metric,
                  const vrs_opts *opts, float feats[6], int *strategy_out, int *tile_out) {
     const double est_sel = batched ? 1.0 : estimate_selectivity(t, p);
@@ -263,31 +305,8 @@ void plan_decide(const vrs_table_s *t, int B, const PredDev &p, bool batched, in
     const int want_t = opts ? opts->tile : -1;
     const bool learned = (!opts || opts->chooser == VRS_CHOOSER_LEARNED) && chooser_ready();
     if (learned && (want_s == VRS_STRATEGY_AUTO || want_t < 0)) {
-        // A streaming tile re-reads the table once per query tile; when an
-        // MFMA tile exists, arms that would re-read it 8 or more times are
-        // not offered to the network (it has not seen every such shape).
-        bool any_mfma = false;
-        for (int tile = 0; tile < kNumTiles; ++tile)
-            if (kTiles[tile].kind == 1 && tile_ok(t, B, k, opts, tile, metric)) any_mfma = true;
-        // When the predicate keeps (almost) every row, the gathered scan can
-        // skip nothing and still pays the selection pass and the id reads:
-        // only masked arms are offered (the network has seen few such
-        // workloads and can misjudge the small margin).
-        const bool dense = est_sel >= 0.9;
         bool allowed[2 * kNumTiles];
-        for (int sidx = 0; sidx < 2; ++sidx)
-            for (int tile = 0; tile < kNumTiles; ++tile) {
-                const int st = sidx + 1;
-                bool ok = tile_ok(t, B, k, opts, tile, metric);
-                if (want_s != VRS_STRATEGY_AUTO && st != want_s) ok = false;
-                if (want_s == VRS_STRATEGY_AUTO && dense && st == VRS_STRATEGY_GATHER) ok = false;
-                if (batched && st != VRS_STRATEGY_MASK) ok = false;
-                if (want_t >= 0 && tile != want_t) ok = false;
-                if (want_t < 0 && any_mfma && kTiles[tile].kind == 0 &&
-                    (B + kTiles[tile].qt - 1) / kTiles[tile].qt >= 8)
-                    ok = false;
-                allowed[sidx * kNumTiles + tile] = ok;
-            }
+        chooser_arms(t, B, k, metric, batched, est_sel, opts, allowed);
         const int arm = chooser_pick(feats, allowed, 2 * kNumTiles);
         if (arm >= 0) {
             *strategy_out = arm / kNumTiles + 1;
@@ -555,6 +574,11 @@ bool chooser_ready() {
 
 // Host inference of the chooser network (same layer formula as the kernels).
 int chooser_pick(const float feats[6], const bool *allowed, int n_arms) {
+    float y = 0.0f;
+    return chooser_pick_value(feats, allowed, n_arms, &y);
+}
+
+int chooser_pick_value(const float feats[6], const bool *allowed, int n_arms, float *value) {
     std::lock_guard<std::mutex> g(g_ch_mu);
     if (!g_ch_ready) return -1;
     const int NI = VRS_MLP_IN, NH = VRS_MLP_HIDDEN, NO = VRS_MLP_OUT;
@@ -581,6 +605,7 @@ int chooser_pick(const float feats[6], const bool *allowed, int n_arms) {
     int best = -1;
     for (int j = 0; j < std::min(n_arms, NO); ++j)
         if (allowed[j] && (best < 0 || y[j] < y[best])) best = j;
+    if (best >= 0) *value = y[best];
     return best;
 }
 

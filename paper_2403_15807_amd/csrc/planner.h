@@ -67,6 +67,11 @@ bool chooser_ready();
 // Returns the arm index (strategy * num_tiles + tile) with the lowest
 // predicted time among the allowed arms, or -1.
 int chooser_pick(const float feats[6], const bool *allowed, int n_arms);
+// The same, with the picked arm's predicted log(ms) in *value.
+int chooser_pick_value(const float feats[6], const bool *allowed, int n_arms, float *value);
+// The learned chooser's predicted time (ms) of its pick for a single-predicate
+// scan call, or -1 without a network.
+double plan_predict_ms(const vrs_table_s *t, int B, const PredDev &p, int k, int metric);
 
 // ---- threshold selection (range.cpp)
 size_t range_workspace(const vrs_table_s *t, int B, int cap);

@@ -3,7 +3,7 @@
 // assignment is the exact nearest centroid, a vector join against the
 // centroid table) and the filtered probe (vrs_probe_topk: the queries'
 // nearest centroids by an exact scan of the centroid table, then the
-// collection, exact scoring and merge kernels of k_probe.hip).
+// walk, exact scoring and merge kernels of k_probe.hip).
 #include <algorithm>
 #include <vector>
 
@@ -16,28 +16,41 @@ namespace vrs {
 namespace {
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Probe time model (ms): fixed, per query, per GB of predicate columns
+// visited, per GB of qualifying rows (see access_costs).
+constexpr double PROBE_FIT[4] = {0.175, 2.75e-3, 1.48, 0.438};
+
 struct ProbePlan {
-    int64_t cand_cap;
-    int nchunk;
-    size_t o_scan, o_cidx, o_cdist, o_cand, o_ncand, o_part, total;
+    int gc, gs, srows;  // counting / scoring workgroups per query, rows per scoring step
+    bool two_level;     // partial lists merged in groups of PROBE_FAN first
+    size_t o_cidx, o_pre, o_cnt, o_state, o_part, o_part2, total;
 };
 
+// Launch shape of the probe: small batches split a query's rows over many
+// workgroups in short steps (latency), large ones use fewer, longer steps.
 ProbePlan probe_plan(const vrs_index_s *ix, int B, int k, int nprobe, int64_t cap_c) {
+    (void)nprobe;
     ProbePlan P{};
-    P.cand_cap = std::max<int64_t>(std::min<int64_t>(cap_c, ix->table->n), ix->max_list);
-    P.nchunk = (int)((P.cand_cap + PROBE_CHUNK - 1) / PROBE_CHUNK);
+    const int walk = std::min(ix->nlist, PROBE_MAX_WALK);
+    // rows one query may visit: the first partition, or partitions within cap_c
+    const int64_t vis = std::max<int64_t>(std::min<int64_t>(cap_c, ix->table->n), ix->max_list);
+    P.srows = B <= 16 ? 256 * 2 : 256 * 16;
+    const int64_t nst = std::max<int64_t>(1, (vis + P.srows - 1) / P.srows);
+    P.gc = std::max(1, std::min(256, 8192 / B));
+    P.gs = (int)std::max<int64_t>(1, std::min<int64_t>({nst, 4096 / B, PROBE_MAX_GS}));
+    P.two_level = P.gs > 2 * PROBE_FAN;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t r = o;
         o += a256(bytes);
         return r;
     };
-    P.o_scan = take(plan_workspace(ix->cent_tab, B, nprobe, nullptr));
-    P.o_cidx = take((size_t)B * nprobe * 8);
-    P.o_cdist = take((size_t)B * nprobe * 4);
-    P.o_cand = take((size_t)B * P.cand_cap * 4);
-    P.o_ncand = take((size_t)B * 4);
-    P.o_part = take((size_t)B * P.nchunk * k * 16);
+    P.o_cidx = take((size_t)B * walk * 8);
+    P.o_pre = take((size_t)B * (walk + 1) * 8);
+    P.o_cnt = take((size_t)B * walk * 4);
+    P.o_state = take((size_t)B * 4 * 8);
+    P.o_part = take((size_t)B * P.gs * k * 16);
+    P.o_part2 = P.two_level ? take((size_t)B * ((P.gs + PROBE_FAN - 1) / PROBE_FAN) * k * 16) : 0;
     P.total = o;
     return P;
 }
@@ -58,6 +71,9 @@ void index_free(vrs_index_s *ix) {
     (void)hipFree(ix->cent);
     (void)hipFree(ix->list_off);
     (void)hipFree(ix->ids);
+    (void)hipFree(ix->rows_p);
+    (void)hipFree(ix->scale_p);
+    (void)hipFree(ix->attr_p);
     delete ix;
 }
 
@@ -135,11 +151,24 @@ hipError_t index_build(const vrs_table_s *t, int nlist, int iters, hipStream_t s
             ix->cent_tab = ct;        // the final centroids: the coarse scan's table
         }
     }
+    // the partition-ordered copies the probe reads
+    const int64_t row_bytes = (int64_t)t->dp * elem_bytes(t->store);
+    if ((e = hipMalloc(&ix->rows_p, std::max<size_t>((size_t)n * row_bytes, 16))) != hipSuccess)
+        return fail("allocation");
+    if (t->scale && (e = dalloc(&ix->scale_p, (size_t)n)) != hipSuccess) return fail("allocation");
+    if ((e = dalloc(&ix->attr_p, (size_t)std::max(1, t->n_attr) * n)) != hipSuccess) return fail("allocation");
+    if ((e = launch_list_gather(ix->ids, n, t->rows, row_bytes, t->scale, t->attr, t->n_attr, t->attr_stride,
+                                ix->rows_p, ix->scale_p, ix->attr_p, s)) != hipSuccess)
+        return fail("list copies");
     std::vector<int64_t> off(nlist + 1);
     e = hipMemcpyAsync(off.data(), ix->list_off, (nlist + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail("list sizes");
-    for (int c = 0; c < nlist; ++c) ix->max_list = std::max(ix->max_list, off[c + 1] - off[c]);
+    for (int c = 0; c < nlist; ++c) {
+        const int64_t sz = off[c + 1] - off[c];
+        ix->max_list = std::max(ix->max_list, sz);
+        ix->size_biased += (double)sz * (double)sz / (double)n;
+    }
     (void)hipFree(x32);
     (void)hipFree(jdist);
     (void)hipFree(assign);
@@ -157,70 +186,80 @@ hipError_t run_probe(const vrs_index_s *ix, const float *q, int B, const PredDev
     const ProbePlan P = probe_plan(ix, B, k, nprobe, cap_c);
     char *w = (char *)ws;
     int64_t *cidx = (int64_t *)(w + P.o_cidx);
-    PredDev none{};
-    none.nterms = 0;
-    prof_begin(2, s);
-    hipError_t e = run_scan(ix->cent_tab, q, B, none, nullptr, nullptr, nprobe, VRS_L2SQ, cidx,
-                            (float *)(w + P.o_cdist), w + P.o_scan, nullptr, s);
-    prof_end(2, s);
-    if (e != hipSuccess) return e;
     ProbeArgs a{};
-    a.rows = t->rows;
-    a.scale = t->scale;
+    a.rows = ix->rows_p;
+    a.scale = ix->scale_p;
     a.d = t->d;
     a.dp = t->dp;
     a.store = t->store;
     a.metric = metric;
-    a.attr = t->attr;
-    a.an = t->attr_stride;
+    a.attr = ix->attr_p;
+    a.an = t->n;
     a.pred = p;
     a.q = q;
     a.B = B;
     a.k = k;
+    a.cent_rows = ix->cent_tab->rows;
+    a.cdp = ix->cent_tab->dp;
+    a.nlist = ix->nlist;
+    a.coarse_out = cidx;
     a.coarse = cidx;
+    a.walk = std::min(ix->nlist, PROBE_MAX_WALK);
     a.nprobe = nprobe;
     a.min_cand = min_cand;
     a.cap_c = cap_c;
     a.list_off = ix->list_off;
     a.ids = ix->ids;
-    a.cand = (int32_t *)(w + P.o_cand);
-    a.cand_cap = P.cand_cap;
-    a.ncand = (int32_t *)(w + P.o_ncand);
+    a.pre = (int64_t *)(w + P.o_pre);
+    a.cnt = (uint32_t *)(w + P.o_cnt);
+    a.state = (int64_t *)(w + P.o_state);
+    a.gc = P.gc;
+    a.gs = P.gs;
+    a.srows = P.srows;
     a.taken = out_taken;
-    a.nchunk = P.nchunk;
     a.part = (uint64_t *)(w + P.o_part);
+    a.part2 = P.two_level ? (uint64_t *)(w + P.o_part2) : nullptr;
     a.out_idx = out_idx;
     a.out_dist = out_dist;
     prof_begin(4, s);
-    e = launch_probe(a, s);
+    hipError_t e = launch_probe(a, s);
     prof_end(4, s);
     return e;
 }
 
-// Scan-vs-probe cost model (bytes moved at the HBM rate plus a fixed launch
-// cost per call, and the batch's MFMA work for the scan), from the
-// estimated selectivity s of the predicate:
-//   scan:  min(mask: every row and its predicate columns once,
-//              gather: the predicate columns, then the s N qualifying rows
-//              and their ids), the table read once for the whole batch,
-//              plus 2 B s N d flops;
-//   probe: per query, the partitions visited until k rows qualify, at least
-//          one and at most nprobe (average partition n / nlist), capped at
-//          cap_c rows: their ids and predicate columns, and the qualifying
-//          rows among them; plus the coarse scan of the centroids.
+// Scan-vs-probe estimates (ms).  The scan: the learned chooser's predicted
+// time of the arm it would pick, when a network is installed (it is trained
+// on measured scan timings); otherwise a bytes-moved model (the predicate
+// columns and either every row or the qualifying ones, read once for the
+// batch, plus 2 B s N d flops).  The probe: the rows a query's walk visits,
+// from the size-biased mean partition size L (the partition of a random row
+// holds sum(size^2) / n rows on average, and queries fall where the rows
+// are):
+//   V = min(cap_c, walk L, max(nprobe L, k / s)),
+// then a linear model of the batch's bytes: the predicate columns of the
+// visited rows (read by the counting and the scoring passes) and the
+// qualifying rows.  Its coefficients are fitted to measured probe times of a
+// 10M x 128 float32 index with 1024 partitions at B = 1, 16 and 256.
 void access_costs(const vrs_index_s *ix, int B, const PredDev &p, int k, int nprobe, int64_t cap_c,
                   double *scan_ms, double *probe_ms) {
     const vrs_table_s *t = ix->table;
     const double s = std::max(estimate_selectivity(t, p), 1e-9);
     const double n = (double)t->n, terms = std::max(0, p.nterms);
     const double row = (double)t->dp * elem_bytes(t->store);
-    const double hbm = 5.0e12, mfma = 60e12, fixed_scan = 80e-6, fixed_probe = 60e-6;
-    const double mask = n * (row + 4.0 * terms), gather = 4.0 * terms * n + s * n * (row + 4.0);
-    *scan_ms = 1e3 * (fixed_scan + std::min(mask, gather) / hbm + 2.0 * B * s * n * t->d / mfma);
-    const double L = n / ix->nlist;
-    const double visited = std::min((double)cap_c, std::min(nprobe * L, std::max(L, k / s)));
-    const double per_q = visited * (4.0 + 4.0 * terms) + s * visited * row;
-    *probe_ms = 1e3 * (fixed_probe + (B * per_q + (double)ix->nlist * row) / hbm);
+    const double learned = plan_predict_ms(t, B, p, k, VRS_L2SQ);
+    if (learned > 0.0) {
+        *scan_ms = learned;
+    } else {
+        const double hbm = 5.0e12, mfma = 60e12, fixed_scan = 80e-6;
+        const double mask = n * (row + 4.0 * terms), gather = 4.0 * terms * n + s * n * (row + 4.0);
+        *scan_ms = 1e3 * (fixed_scan + std::min(mask, gather) / hbm + 2.0 * B * s * n * t->d / mfma);
+    }
+    const double L = std::max(1.0, ix->size_biased);
+    const double walk = std::min(ix->nlist, PROBE_MAX_WALK);
+    const double V = std::min({(double)cap_c, walk * L, std::max(nprobe * L, k / s)});
+    const double attr_gb = B * V * 4.0 * std::max(1.0, terms) / 1e9;
+    const double rows_gb = B * V * s * (row + 4.0) / 1e9;
+    *probe_ms = PROBE_FIT[0] + PROBE_FIT[1] * B + PROBE_FIT[2] * attr_gb + PROBE_FIT[3] * rows_gb;
 }
 
 }  // namespace vrs

@@ -52,8 +52,8 @@ def test_index_equals_the_oracle(built):
 def test_probe_equals_the_oracle(built, pred, B):
     x, a, T, ix, ot, (cent, assign, off, ids) = built
     q = inputs.queries(9, B, x.shape[1], 200)
-    for nprobe, min_cand, cap_c in ((1, 10, 1 << 16), (8, 10, 1 << 16), (8, 5000, 1 << 16), (32, 10 ** 6, 4000),
-                                    (128, 10 ** 6, 10 ** 6)):
+    for nprobe, min_cand, cap_c in ((1, 10, 1 << 16), (8, 10, 1 << 16), (1, 5000, 1 << 16), (32, 10 ** 6, 4000),
+                                    (128, 1, 10 ** 6), (4, 3000, 10 ** 6)):
         ref = O.ivf_probe(ot, cent, off, ids, q, pred, 10, O.L2SQ, nprobe, min_cand, cap_c)
         gi, gd, gt = ix.probe_topk(_dev(q), pred, 10, vrs.L2SQ, nprobe, min_cand, cap_c)
         torch.cuda.synchronize()
@@ -70,9 +70,50 @@ def test_probe_recall_grows_with_partitions(built):
     exact = T.scan_topk(q, pred, 10, vrs.L2SQ).idx.cpu().numpy()
     prev = -1.0
     for nprobe in (1, 4, 16, 128):
-        gi, _, _ = ix.probe_topk(q, pred, 10, vrs.L2SQ, nprobe, 10 ** 6, 10 ** 6)
+        gi, _, _ = ix.probe_topk(q, pred, 10, vrs.L2SQ, nprobe, 1, 10 ** 6)
         gi = gi.cpu().numpy()
         rec = np.mean([len(set(gi[b]) & set(exact[b])) / 10 for b in range(32)])
         assert rec >= prev
         prev = rec
     assert prev == 1.0  # every partition visited: the scan's answer
+
+
+@pytest.mark.parametrize("nprobe,min_cand,cap_c", [(4, 100, 1 << 14), (1, 4000, 10 ** 6)])
+def test_probe_many_queries_equals_the_oracle(built, nprobe, min_cand, cap_c):
+    # a batch large enough that every workgroup of the walk and of the
+    # scoring takes several chunks of rows
+    x, a, T, ix, ot, (cent, assign, off, ids) = built
+    q = inputs.queries(9, 300, x.shape[1], 200, stream_offset=2)
+    pred = [(0, 0, 30)]
+    ref = O.ivf_probe(ot, cent, off, ids, q, pred, 100, O.L2SQ, nprobe, min_cand, cap_c)
+    gi, gd, gt = ix.probe_topk(_dev(q), pred, 100, vrs.L2SQ, nprobe, min_cand, cap_c)
+    torch.cuda.synchronize()
+    assert np.array_equal(gt.cpu().numpy(), ref[2])
+    assert np.array_equal(gi.cpu().numpy(), ref[0])
+    assert np.array_equal(gd.cpu().numpy().view(np.uint32), ref[1].view(np.uint32))
+
+
+@pytest.mark.parametrize("store,ostore", [(vrs.BF16, O.BF16), (vrs.FP8E4M3, O.FP8)])
+def test_probe_low_precision_ip_equals_the_oracle(store, ostore):
+    # inner product on bfloat16 / FP8 tables (FP8 row scales, two predicate
+    # columns): the index's partition-ordered copies of rows, scales and
+    # predicate columns must score exactly as the table itself
+    n, d, nlist = 30000, 96, 64
+    x = inputs.table(11, n, d, 100)
+    a = inputs.attributes(11, n, 2, 100)
+    T = vrs.Table(_dev(x), _dev(a), store=store, normalize=True)
+    ix = vrs.Index(T, nlist, iters=3)
+    ot = O.Table.build(x, a, ostore, normalize=True)
+    cent, _, off, ids = O.ivf_build(ot, nlist, 3)
+    gc, go, gi = ix.export()
+    torch.cuda.synchronize()
+    assert np.array_equal(gi.cpu().numpy(), ids)
+    q = inputs.queries(11, 5, d, 100)
+    pred = [(0, 0, 60), (1, 10, 90)]
+    for nprobe, min_cand in ((2, 50), (1, 3000)):
+        ref = O.ivf_probe(ot, cent, off, ids, q, pred, 20, O.IP, nprobe, min_cand, 10 ** 6)
+        gi2, gd2, gt2 = ix.probe_topk(_dev(q), pred, 20, vrs.IP, nprobe, min_cand, 10 ** 6)
+        torch.cuda.synchronize()
+        assert np.array_equal(gt2.cpu().numpy(), ref[2])
+        assert np.array_equal(gi2.cpu().numpy(), ref[0])
+        assert np.array_equal(gd2.cpu().numpy().view(np.uint32), ref[1].view(np.uint32))
