@@ -46,7 +46,7 @@ struct BPlan {
     bool two_pass;  // dense side in two passes (prefix of every chunk, merged bound, all rows)
     size_t o_qp, o_qnorm, o_qn2, o_qhl, o_gthr, o_ctl, o_pred_o, o_pred_p, o_qr, o_cands, o_sq, o_kc_o, o_kps_o, o_kc_p,
         o_kps_p, o_cand, o_subcnt, o_tot, o_perm, o_spoff, o_spcnt, o_segpre, o_listoff, o_nlists,
-        o_pool, o_part, o_cbuf, o_merged, o_rrdist, o_rrcnt, o_fail, o_failcnt, o_fb, total;
+        o_pool, o_part, o_cbuf, o_merged, o_rrdist, o_fail, o_failcnt, o_fb, total;
 };
 
 BPlan make_bplan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int cfg) {
@@ -110,7 +110,6 @@ BPlan make_bplan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, in
     P.o_cbuf = take((size_t)P.dense_lists * P.CB * 8);
     P.o_merged = take((size_t)B * P.K * 8);
     P.o_rrdist = take((size_t)B * P.K * 8);
-    P.o_rrcnt = take((size_t)B * 4);
     P.o_fail = take((size_t)B * 4);
     P.o_failcnt = take(8);
     P.o_fb = take((size_t)B * P.fb_chunks * kmax * 16);
@@ -286,7 +285,6 @@ hipError_t run_batched(const vrs_table_s *t, const float *q, int B, const vrs_pr
     fa.merge_mid = nullptr;
     fa.merged = (uint64_t *)(w + P.o_merged);
     fa.rr_dist = (double *)(w + P.o_rrdist);
-    fa.rr_count = (int32_t *)(w + P.o_rrcnt);
     // Screening error: the larger of the two kernels' models (the sparse
     // kernel is the VALU form with IEEE round-to-nearest, unit roundoff
     // 2^-24; the dense one the MFMA form, whose internal rounding is only

@@ -340,7 +340,6 @@ struct FinishArgs {
     uint64_t *merged;              // [B][K]
     const int32_t *merge_limit;    // positions >= *merge_limit get an empty merged list (or null)
     double *rr_dist;               // [B][K] exact distances of the candidates
-    int32_t *rr_count;             // [B] rerank arrival counters (zeroed by the merge)
     double rel, abs_ip, abs_l2, max_norm;  // screening error model
     int32_t *fail_list;            // [B]
     int32_t *fail_count;           // [1]

@@ -103,12 +103,10 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
                                                               const int64_t *__restrict__ list_off,
                                                               const int32_t *__restrict__ nlists,
                                                               const uint64_t *__restrict__ heads,
-                                                              int32_t *__restrict__ rr_count,
                                                               const int32_t *__restrict__ limit,
                                                               const int32_t *__restrict__ fills) {
     constexpr int T = MERGE_THREADS;
     const int g = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
-    if (rr_count && tid == 0) rr_count[b] = 0;  // the rerank's arrival counter
     extern __shared__ __align__(16) unsigned char smem[];
     // query b's lists: n_lists of them at b * n_lists, or (batched uneven
     // form) nlists[b] of them at list_off[b]
@@ -296,10 +294,9 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
 // chunk at a time (coalesced 16-byte loads: eight lanes per row chunk, two
 // chunks in flight in registers), then every lane runs its chain over its
 // row's chunk.  Spreading one query's tasks over several workgroups (small
-// batches) puts several CUs' load queues on the scattered rows.  The last
-// workgroup of a query to finish (an arrival counter, zeroed by the final
-// merge level) ranks the candidates by exact distance, checks the
-// certificate and writes the result.
+// batches) puts several CUs' load queues on the scattered rows.  One
+// workgroup per query then ranks the candidates by exact distance, checks
+// the certificate and writes the result.
 constexpr int RR_THREADS = 512;
 constexpr int RR_WAVES = RR_THREADS / 64;
 constexpr size_t RR_STAGE_BYTES = (size_t)RR_WAVES * X64_WAVE_LDS;
@@ -406,7 +403,13 @@ __host__ __device__ inline size_t rr_lds_bytes(int dp, int K) {
     return (size_t)dp * 8 + (sb > RR_STAGE_BYTES ? sb : RR_STAGE_BYTES);
 }
 
-template <int STORE, int METRIC>
+// PHASE 0: one workgroup per query does both parts; PHASE 1: the exact
+// distances, split over the workgroups of a query; PHASE 2 (a later launch,
+// one workgroup per query): the ranking and the certificate.  The kernel
+// boundary between phases 1 and 2 orders the distances before their use, so
+// no device-scope fence is needed (on this GPU such a fence writes back the
+// XCD's L2).
+template <int STORE, int METRIC, int PHASE>
 __global__ __launch_bounds__(RR_THREADS) void rerank_kernel(FinishArgs a) {
     constexpr int T = RR_THREADS;
     const int s = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -426,36 +429,28 @@ __global__ __launch_bounds__(RR_THREADS) void rerank_kernel(FinishArgs a) {
     uint32_t *xl = (uint32_t *)(xh + 2 * T);                      // [2T]
     Key128 *cand = (Key128 *)(xl + 2 * T);                        // [round8(K)]
     Key128 *srt = cand + ((a.K + 7) & ~7);                        // [k] in exact order
-    __shared__ int last_s, n_cand_s, ratio_s;
-    for (int j = tid; j < a.dp; j += T) qd[j] = j < a.d ? (double)a.q[(int64_t)ob * a.d + j] : 0.0;
+    __shared__ int n_cand_s, ratio_s;
     if (tid == 0) {
         n_cand_s = 0;
         ratio_s = 0;
     }
-    __syncthreads();
     const uint64_t *lst = a.merged + (int64_t)b * a.K;
     double *dist = a.rr_dist + (int64_t)b * a.K;
-    for (int t = s + S * wave; t < ntask; t += S * RR_WAVES) {
-        const int ci = t * 64 + lane;
-        const uint64_t key = ci < nc ? lst[ci] : KEY_INF;
-        const bool has = key != KEY_INF;
-        // a lane without a candidate stages row 0 and drops its value
-        const int row = has ? (int)(uint32_t)key : 0;
-        const double dv = exact64_wave<STORE, METRIC>(a.rows, a.scale, row, has, qd, a.dp, stage);
-        if (ci < nc && has) dist[ci] = dv;
-    }
-    // arrival: the last workgroup of query b finishes it (a single workgroup
-    // needs no counter and no device-scope fences)
-    if (ns > 1) {
-        __threadfence();
+    if (PHASE != 2) {
+        for (int j = tid; j < a.dp; j += T) qd[j] = j < a.d ? (double)a.q[(int64_t)ob * a.d + j] : 0.0;
         __syncthreads();
-        if (tid == 0) last_s = atomicAdd(&a.rr_count[b], 1) == ns - 1;
-        __syncthreads();
-        if (!last_s) return;
-        __threadfence();
-    } else {
-        __syncthreads();  // every wave's distances written, the staging area free
+        for (int t = s + S * wave; t < ntask; t += S * RR_WAVES) {
+            const int ci = t * 64 + lane;
+            const uint64_t key = ci < nc ? lst[ci] : KEY_INF;
+            const bool has = key != KEY_INF;
+            // a lane without a candidate stages row 0 and drops its value
+            const int row = has ? (int)(uint32_t)key : 0;
+            const double dv = exact64_wave<STORE, METRIC>(a.rows, a.scale, row, has, qd, a.dp, stage);
+            if (ci < nc && has) dist[ci] = dv;
+        }
     }
+    if (PHASE == 1) return;
+    __syncthreads();  // every wave's distances written, the staging area free
 
     // the screening keys are sorted with empty slots last, so the candidates
     // are the first n_cand of them
@@ -698,17 +693,17 @@ hipError_t launch_merge(const FinishArgs &a, hipStream_t s) {
     if (a.n_chunks <= G) {
         merge_kernel<<<dim3(1, a.B), MERGE_THREADS, lds, s>>>(a.partials, a.n_chunks, G, a.K, Kp,
                                                              CB, a.merged, 1, a.list_off, a.nlists,
-                                                             a.heads, a.rr_count, a.merge_limit, a.fills);
+                                                             a.heads, a.merge_limit, a.fills);
         return hipGetLastError();
     }
     // two levels: groups of G lists, then the group results
     const int ng = (a.n_chunks + G - 1) / G;
     uint64_t *mid = a.merge_mid;
     merge_kernel<<<dim3(ng, a.B), MERGE_THREADS, lds, s>>>(a.partials, a.n_chunks, G, a.K, Kp, CB,
-                                                          mid, ng, a.list_off, a.nlists, a.heads, nullptr,
+                                                          mid, ng, a.list_off, a.nlists, a.heads,
                                                           a.merge_limit, a.fills);
     merge_kernel<<<dim3(1, a.B), MERGE_THREADS, lds, s>>>(mid, ng, ng, a.K, Kp, CB, a.merged, 1,
-                                                         nullptr, nullptr, nullptr, a.rr_count,
+                                                         nullptr, nullptr, nullptr,
                                                          a.merge_limit, nullptr);
     return hipGetLastError();
 }
@@ -716,13 +711,20 @@ hipError_t launch_merge(const FinishArgs &a, hipStream_t s) {
 template <int STORE, int METRIC>
 static hipError_t rerank_t(const FinishArgs &a, hipStream_t s, int kpmax) {
     const size_t lds = rr_lds_bytes(a.dp, a.K);
-    ensure_dyn_lds((const void *)rerank_kernel<STORE, METRIC>, lds);
-    // Several workgroups per query when the batch alone cannot fill the GPU
-    // (their rows come from many CUs at once); one per query, with no
-    // arrival counter or device-scope fence, from 256 queries on.
+    ensure_dyn_lds((const void *)rerank_kernel<STORE, METRIC, 0>, lds);
+    ensure_dyn_lds((const void *)rerank_kernel<STORE, METRIC, 1>, lds);
+    ensure_dyn_lds((const void *)rerank_kernel<STORE, METRIC, 2>, lds);
+    // Several workgroups per query for the distances when the batch alone
+    // cannot fill the GPU (their rows come from many CUs at once), then one
+    // per query for the ranking; one per query for both from 256 queries on.
     const int tasks = (kpmax + (a.err_ratio ? 1 : 0) + 63) / 64;
     const int S = std::max(1, std::min(tasks, (256 + a.B - 1) / a.B));
-    rerank_kernel<STORE, METRIC><<<dim3(S, a.B), RR_THREADS, lds, s>>>(a);
+    if (S == 1) {
+        rerank_kernel<STORE, METRIC, 0><<<dim3(1, a.B), RR_THREADS, lds, s>>>(a);
+    } else {
+        rerank_kernel<STORE, METRIC, 1><<<dim3(S, a.B), RR_THREADS, lds, s>>>(a);
+        rerank_kernel<STORE, METRIC, 2><<<dim3(1, a.B), RR_THREADS, lds, s>>>(a);
+    }
     return hipGetLastError();
 }
 

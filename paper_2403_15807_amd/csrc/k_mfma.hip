@@ -2,7 +2,9 @@
 // tensor formulation, Section 3.1: a batch of queries against a batch of
 // data vectors as one matrix product Q X^T), float32 tables.
 //
-// Workgroup = 4 waves = 64 queries (16 per wave) x one chunk of rows.
+// Workgroup = 4 waves = 64 queries (16 per wave) x one chunk of rows; for
+// batches of at most 16 queries, the four waves share the 16 queries and
+// split each tile's rows instead.
 //   - Each wave keeps its 16 queries as MFMA A-operands in registers for the
 //     whole row width (v_mfma_f32_16x16x4_f32; the coordinate order inside a
 //     lane is permuted identically for queries and rows, which leaves the
@@ -39,20 +41,29 @@ __device__ __forceinline__ float4 load_x(const float4 *p, int shared) {
 constexpr int BR = 64;  // rows per tile
 
 // MB = 16-query blocks per wave (a workgroup holds QM = 64 * MB queries); a
-// B-operand read from LDS feeds MB MFMAs.
+// B-operand read from LDS feeds MB MFMAs.  G = waves sharing one group of QW
+// queries (G > 1 only with MB = 1, for batches of at most 64 / G queries):
+// the group's waves split every 64-row tile between them, so that all four
+// SIMDs of the CU run MFMAs for a small batch; the group's candidates are
+// then merged by its first wave after a workgroup barrier.
 // One work item: queries [q0, q0 + QM) (of Bq) against row chunk `chunk` of
 // `nchunks`; its lists are (query, chunk) lists of the partials.
-template <int DP, int METRIC, bool GATHER, bool BATCHED, int E, int MB>
+template <int DP, int METRIC, bool GATHER, bool BATCHED, int E, int MB, int G = 1>
 __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, const int nchunks,
                                          const int q0, const int Bq, unsigned char *smem) {
-    constexpr int QM = 64 * MB;
-    constexpr int QW = 16 * MB;            // queries per wave
+    static_assert(G == 1 || MB == 1, "query groups shared by several waves hold 16 queries");
+    constexpr int QM = 64 * MB / G;
+    constexpr int QW = 16 * MB;            // queries per wave group
+    constexpr int NBW = 4 / G;             // 16-row blocks of a tile per wave
     constexpr int NT4 = DP / 16;           // float4 A-fragments per lane per block
     constexpr int LDX = DP + 4;            // padded LDS row stride (floats)
     constexpr int NV4 = DP / 4;            // float4 per row
     constexpr int RP = 256 / NV4;          // rows staged per pass
     constexpr int PASSES = BR / RP;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int qw0 = (wave / G) * QW;       // the wave's first query in the workgroup
+    const int nb0 = (wave % G) * NBW;      // the wave's first 16-row block of a tile
+    const bool owner = wave % G == 0;      // merges the group's candidates
 
     float *xs = (float *)smem;                                   // [BR][LDX]
     int *rid = (int *)(xs + BR * LDX);                           // [BR]
@@ -67,20 +78,20 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
     const int K = a.K, CBq = a.CB;
 
     // A fragments: lane (m = lane % 16, kq = lane / 16) of wave w holds, for
-    // block mb, query q0 + QW*w + 16*mb + m at coordinates 16t + 4kq + c.
+    // block mb, query q0 + qw0 + 16*mb + m at coordinates 16t + 4kq + c.
     float4 af[MB][NT4];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
-        const int mq = q0 + wave * QW + mb * 16 + (lane & 15);
+        const int mq = q0 + qw0 + mb * 16 + (lane & 15);
 #pragma unroll
         for (int t = 0; t < NT4; ++t)
             af[mb][t] = mq < Bq ? *(const float4 *)(a.qp + (int64_t)mq * DP + 16 * t + 4 * (lane >> 4))
                                  : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     if (BATCHED && tid < QM) qpred[tid] = q0 + tid < Bq ? a.preds[q0 + tid] : PredDev{-1, {0}, {0}, {0}};
-    // per-query state (wave-private) and list initialisation
-    for (int i = lane; i < QW; i += 64) {
-        const int q = wave * QW + i;
+    // per-query state (private to the wave group) and list initialisation
+    for (int i = lane; owner && i < QW; i += 64) {
+        const int q = qw0 + i;
         cnt[q] = 0;
         fill[q] = 0;
         const int qa = q0 + q;
@@ -99,11 +110,11 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
     pass_range(a, c0, c1, BR, total, nchunks);
     const float *X = (const float *)a.rows;
 
-    // Tile pipeline: the row ids of tile t+1 (gather: sid) and the per-row
-    // record of tile t+1 (thread r < 64 holds row r's id, predicate columns
-    // and squared norm: ri_*) are fetched while tile t is multiplied, so the
-    // vector loads of a tile never wait on another load.  The vector loads
-    // themselves overlap the other workgroups resident on the CU.
+    // Tile pipeline: the row ids of the next tile whose rows are loaded
+    // (gather: sid) and the per-row record of tile t+1 (thread r < 64 holds
+    // row r's id, predicate columns and squared norm: ri_*) are fetched while
+    // tile t is multiplied, so the vector loads of a tile never wait on
+    // another load.
     const int sr = tid / NV4, sc = tid % NV4;  // staging: row within pass, float4 column
     int sid[PASSES];
     int64_t ri_row = 0;
@@ -131,12 +142,13 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
             ri_n2 = (METRIC == VRS_L2SQ && ri_ok) ? a.norm2[ri_row] : 0.0f;
         }
     };
-    if (GATHER) issue_ids(c0);
-    issue_rowinfo(c0);
-
-    for (int64_t t0 = c0; t0 < c1; t0 += BR) {
-        // ---- tile t0: vector loads (rows known), per-row record -> LDS
-        float4 w[PASSES];
+    // In the small-batch form (G > 1) the vector loads of tile t+1 are issued
+    // as soon as tile t is in LDS, so they are in flight during tile t's
+    // product and epilogue (the registers this costs would cost the wide form
+    // a resident workgroup); the wide form loads a tile when it starts it.
+    constexpr bool PF = G > 1;
+    float4 w[PASSES];
+    auto issue_rows = [&](int64_t t0) {
 #pragma unroll
         for (int p = 0; p < PASSES; ++p) {
             const int64_t pos = t0 + p * RP + sr;
@@ -144,7 +156,20 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
             w[p] = pos < c1 ? load_x((const float4 *)(X + row * DP) + sc, a.shared_rows)
                             : make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        if (GATHER && t0 + BR < c1) issue_ids(t0 + BR);
+    };
+    if (GATHER) issue_ids(c0);
+    issue_rowinfo(c0);
+    if (PF) {
+        issue_rows(c0);
+        if (GATHER && c0 + BR < c1) issue_ids(c0 + BR);
+    }
+
+    for (int64_t t0 = c0; t0 < c1; t0 += BR) {
+        if (!PF) {
+            issue_rows(t0);
+            if (GATHER && t0 + BR < c1) issue_ids(t0 + BR);
+        }
+        // ---- tile t0: per-row record and rows -> LDS
         bool mine = false;
         if (tid < BR) {
             bool ok = ri_ok;
@@ -162,24 +187,29 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
         if (t0 + BR < c1) issue_rowinfo(t0 + BR);
 #pragma unroll
         for (int p = 0; p < PASSES; ++p) *(float4 *)(xs + (p * RP + sr) * LDX + 4 * sc) = w[p];
-        if (!__syncthreads_or(mine)) continue;
+        const int any = __syncthreads_or(mine);
+        if (PF && t0 + BR < c1) {
+            issue_rows(t0 + BR);
+            if (GATHER && t0 + 2 * BR < c1) issue_ids(t0 + 2 * BR);
+        }
+        if (!any) continue;
 
         // A wave whose queries all lie past the batch (a partial query
         // tile) skips the product and the epilogue; it still stages rows
         // and meets every barrier.
-        if (q0 + wave * QW < Bq) {
-            // ---- Q X^T for the wave's QW queries x 64 rows
-            f4v acc[MB][4];
+        if (q0 + qw0 < Bq) {
+            // ---- Q X^T for the group's QW queries x the wave's NBW * 16 rows
+            f4v acc[MB][NBW];
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = (f4v){0.f, 0.f, 0.f, 0.f};
+                for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = (f4v){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int t = 0; t < NT4; ++t) {
-                float4 bv[4];
+                float4 bv[NBW];
 #pragma unroll
-                for (int nb = 0; nb < 4; ++nb)
-                    bv[nb] = *(const float4 *)(xs + (nb * 16 + (lane & 15)) * LDX + 16 * t + 4 * (lane >> 4));
+                for (int nb = 0; nb < NBW; ++nb)
+                    bv[nb] = *(const float4 *)(xs + ((nb0 + nb) * 16 + (lane & 15)) * LDX + 16 * t + 4 * (lane >> 4));
                 // independent accumulators back to back: no MFMA waits on the
                 // result of the previous one
 #pragma unroll
@@ -187,23 +217,24 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
 #pragma unroll
                     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                        for (int nb = 0; nb < 4; ++nb)
+                        for (int nb = 0; nb < NBW; ++nb)
                             acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb][t][c], bv[nb][c], acc[mb][nb], 0, 0, 0);
             }
 
-            // ---- epilogue: lane holds queries QW*w + 16mb + 4(lane/16) + i, rows 16nb + lane%16
-            if ((((t0 - c0) / BR) & 15) == 15) {
+            // ---- epilogue: lane holds queries qw0 + 16mb + 4(lane/16) + i, rows
+            // 16(nb0 + nb) + lane%16
+            if (owner && (((t0 - c0) / BR) & 15) == 15) {
                 for (int i = lane; i < QW; i += 64) {
-                    const int qa = q0 + wave * QW + i;
+                    const int qa = q0 + qw0 + i;
                     if (qa < Bq) {
                         const uint64_t g = __atomic_load_n((const unsigned long long *)(a.gthr + qa), __ATOMIC_RELAXED);
-                        if (g < thr[wave * QW + i]) thr[wave * QW + i] = g;
+                        if (g < thr[qw0 + i]) thr[qw0 + i] = g;
                     }
                 }
             }
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
-                const int qb = wave * QW + mb * 16 + 4 * (lane >> 4);
+                const int qb = qw0 + mb * 16 + 4 * (lane >> 4);
                 uint64_t th[4];
                 float qn[4], thf[4];
 #pragma unroll
@@ -213,8 +244,8 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
                     qn[i] = qn2[qb + i];
                 }
 #pragma unroll
-                for (int nb = 0; nb < 4; ++nb) {
-                    const int r = nb * 16 + (lane & 15);
+                for (int nb = 0; nb < NBW; ++nb) {
+                    const int r = (nb0 + nb) * 16 + (lane & 15);
                     if (!rq[r]) continue;
                     const int row = rid[r];
 #pragma unroll
@@ -234,15 +265,18 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
                 }
             }
         }
-        // ---- flush the wave's queries whose buffer could overflow next tile
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        {
-            const int myc = lane < QW ? cnt[wave * QW + lane] : 0;
+        // ---- flush the group's queries whose buffer could overflow next tile
+        if (G == 1)
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        else
+            __syncthreads();  // every wave of the group has appended its candidates
+        if (owner) {
+            const int myc = lane < QW ? cnt[qw0 + lane] : 0;
             uint64_t full = __ballot(lane < QW && myc > CBq - BR);
             while (full) {
                 const int j = __ffsll((long long)full) - 1;
                 full &= full - 1;
-                const int q = wave * QW + j, qa = q0 + q;
+                const int q = qw0 + j, qa = q0 + q;
                 const int64_t base = (int64_t)qa * nchunks + chunk;
                 const int nq = cnt[q], fq = fill[q], Kq = list_len(a, qa, K);
                 flush_fit<E>(a.partials + base * K, a.cbuf + base * CBq, nq, Kq, fq, &thr[q], a.gthr + qa);
@@ -254,14 +288,15 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
         }
         __syncthreads();  // the LDS tile is reused
     }
-    // ---- final flush of every pending buffer
+    // ---- final flush of every pending buffer (by each group's first wave)
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    const int myc = lane < QW ? cnt[wave * QW + lane] : 0;
-    uint64_t pend = __ballot(lane < QW && myc > 0 && q0 + wave * QW + lane < Bq);
+    if (!owner) return;
+    const int myc = lane < QW ? cnt[qw0 + lane] : 0;
+    uint64_t pend = __ballot(lane < QW && myc > 0 && q0 + qw0 + lane < Bq);
     while (pend) {
         const int j = __ffsll((long long)pend) - 1;
         pend &= pend - 1;
-        const int q = wave * QW + j, qa = q0 + q;
+        const int q = qw0 + j, qa = q0 + q;
         const int64_t base = (int64_t)qa * nchunks + chunk;
         const int nq = cnt[q], fq = fill[q], Kq = list_len(a, qa, K);
         flush_fit<E>(a.partials + base * K, a.cbuf + base * CBq, nq, Kq, fq, &thr[q], a.gthr + qa);
@@ -271,22 +306,22 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
     // entries past its keys (the whole list length K)
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     if (a.fills) {
-        if (lane < QW && q0 + wave * QW + lane < Bq)
-            a.fills[(int64_t)(q0 + wave * QW + lane) * nchunks + chunk] = fill[wave * QW + lane];
+        if (lane < QW && q0 + qw0 + lane < Bq)
+            a.fills[(int64_t)(q0 + qw0 + lane) * nchunks + chunk] = fill[qw0 + lane];
     } else {
         for (int j = 0; j < QW; ++j) {
-            const int q = wave * QW + j, qa = q0 + q;
+            const int q = qw0 + j, qa = q0 + q;
             if (qa < Bq) list_tail_inf(a.partials + ((int64_t)qa * nchunks + chunk) * K, fill[q], K);
         }
     }
 }
 
 
-template <int DP, int METRIC, bool GATHER, bool BATCHED, int E, int MB>
-__global__ __launch_bounds__(256, (E <= 8 && MB == 1) ? 3 : 2) void screen_mfma_f32_kernel(ScreenArgs a) {
+template <int DP, int METRIC, bool GATHER, bool BATCHED, int E, int MB, int G>
+__global__ __launch_bounds__(256, (E <= 8 && MB == 1 && G == 1) ? 3 : 2) void screen_mfma_f32_kernel(ScreenArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    f32_tile<DP, METRIC, GATHER, BATCHED, E, MB>(a, blockIdx.x, a.n_chunks, blockIdx.y * (64 * MB), a.B,
-                                                 smem);
+    f32_tile<DP, METRIC, GATHER, BATCHED, E, MB, G>(a, blockIdx.x, a.n_chunks, blockIdx.y * (64 * MB / G), a.B,
+                                                    smem);
 }
 
 // Persistent form (batched uneven launch), queue per XCD: see the bfloat16
@@ -328,19 +363,29 @@ __global__ __launch_bounds__(256, (E <= 8 && MB == 1) ? 3 : 2) void screen_mfma_
 
 template <int DP, int METRIC, int E, int MB>
 hipError_t launch_e(const ScreenArgs &a, hipStream_t s) {
+    const size_t lds = screen_mfma_lds(DP, 64 * MB);
+    if (MB == 1 && !a.preds && a.B <= 16) {
+        // one group of 16 queries shared by the four waves (each takes 16 of
+        // a tile's 64 rows)
+        dim3 grid(a.n_chunks, (a.B + 15) / 16), block(256);
+        auto k = a.gather ? screen_mfma_f32_kernel<DP, METRIC, true, false, E, 1, 4>
+                          : screen_mfma_f32_kernel<DP, METRIC, false, false, E, 1, 4>;
+        ensure_dyn_lds((const void *)k, lds);
+        k<<<grid, block, lds, s>>>(a);
+        return hipGetLastError();
+    }
     constexpr int QM = 64 * MB;
     dim3 grid(a.n_chunks, (a.B + QM - 1) / QM), block(256);
-    const size_t lds = screen_mfma_lds(DP, QM);
     if (a.preds) {
-        auto k = screen_mfma_f32_kernel<DP, METRIC, false, true, E, MB>;
+        auto k = screen_mfma_f32_kernel<DP, METRIC, false, true, E, MB, 1>;
         ensure_dyn_lds((const void *)k, lds);
         k<<<grid, block, lds, s>>>(a);
     } else if (a.gather) {
-        auto k = screen_mfma_f32_kernel<DP, METRIC, true, false, E, MB>;
+        auto k = screen_mfma_f32_kernel<DP, METRIC, true, false, E, MB, 1>;
         ensure_dyn_lds((const void *)k, lds);
         k<<<grid, block, lds, s>>>(a);
     } else {
-        auto k = screen_mfma_f32_kernel<DP, METRIC, false, false, E, MB>;
+        auto k = screen_mfma_f32_kernel<DP, METRIC, false, false, E, MB, 1>;
         ensure_dyn_lds((const void *)k, lds);
         k<<<grid, block, lds, s>>>(a);
     }
@@ -374,7 +419,9 @@ size_t screen_mfma_lds(int dp, int qm) {
     return (size_t)BR * (dp + 4) * 4 + BR * 12 + qm * 12 + 8 + qm * 8 + qm * sizeof(PredDev) + 16;
 }
 
-// Resident workgroups per CU (register budget of the kernel, set by E and MB).
+// Resident workgroups per CU (register budget of the kernel, set by E and the
+// queries per workgroup qm: 64 and 128 for the wide forms, 16 for the
+// small-batch form).
 int screen_mfma_occupancy(int Kp, int CB, int qm) {
     return ((Kp + CB) / 64 <= 8 && qm == 64) ? 3 : 2;
 }

@@ -59,7 +59,9 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
         P.CB = mfma_cb(P.Kp);
         P.qt = t->store == VRS_F32 ? cfg.qt : screen_mfma_bf16_qm();
         P.n_qtiles = (B + P.qt - 1) / P.qt;
-        const int occ = t->store == VRS_F32 ? screen_mfma_occupancy(P.Kp, P.CB, P.qt) : 1;
+        // (float32 batches of at most 16 queries run the small-batch form: one
+        // 16-query group per workgroup)
+        const int occ = t->store == VRS_F32 ? screen_mfma_occupancy(P.Kp, P.CB, B <= 16 ? 16 : P.qt) : 1;
         const int64_t slots = (int64_t)256 * occ * cfg.wg_target / 4;
         const int64_t rows = est_rows < 0 ? t->n : std::min<int64_t>(std::max<int64_t>(est_rows, 1), t->n);
         int64_t max_chunks = std::max<int64_t>(1, rows / 1024);
@@ -107,7 +109,6 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
     P.o_mid = take((size_t)B * ((P.n_chunks + 2047) / 2048) * P.K * 8);
     P.o_merged = take((size_t)B * P.K * 8);
     P.o_rrdist = take((size_t)B * P.K * 8);
-    P.o_rrcnt = take((size_t)B * 4);
     P.o_fail = take((size_t)B * 4);
     P.o_failcnt = take(8);
     P.o_fb = take((size_t)B * P.fb_chunks * kmax * 16);
@@ -435,7 +436,6 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     fa.merge_mid = (uint64_t *)(w + P.o_mid);
     fa.merged = (uint64_t *)(w + P.o_merged);
     fa.rr_dist = (double *)(w + P.o_rrdist);
-    fa.rr_count = (int32_t *)(w + P.o_rrcnt);
     // Screening error bound, FP32 accumulation in any order (both sides of the
     // certificate also carry the FP64 sum's own error):
     //   VALU L2SQ: sum of dp non-negative rounded terms -> relative gamma_{dp+3};

@@ -32,7 +32,7 @@ struct Plan {
     int fb_chunks, fb_rows_per_chunk;
     bool two_pass;       // MFMA screening in two passes (a prefix sample, then everything)
     // workspace offsets (bytes)
-    size_t o_qp, o_qnorm, o_qn2, o_qhl, o_gthr, o_cbuf, o_bitmap, o_blk, o_sel, o_selcnt, o_part, o_heads, o_fills, o_mid, o_merged, o_rrdist, o_rrcnt, o_fail,
+    size_t o_qp, o_qnorm, o_qn2, o_qhl, o_gthr, o_cbuf, o_bitmap, o_blk, o_sel, o_selcnt, o_part, o_heads, o_fills, o_mid, o_merged, o_rrdist, o_fail,
         o_failcnt, o_fb, o_preds, o_kc, o_kps, total;
 };
 
