@@ -242,11 +242,12 @@ def evaluate_recorded(F, Y, params, mean, std):
         al = allowed_arms(f, y, nt)
         a_l = vrs.chooser_pick(f, al)
         a_h = heuristic_arm(f, y, nt)
-        r = []
+        r, t = [], []
         for a in (a_l, a_h):
             tp = math.exp(y[a]) if a >= 0 and np.isfinite(y[a]) else tbest * 100.0
             r.append(tp / tbest - 1.0)
-        rows.append((r[0], r[1], a_l, a_h, int(np.nanargmin(y))))
+            t.append(tp)
+        rows.append((r[0], r[1], a_l, a_h, int(np.nanargmin(y)), tbest, t[0]))
     vrs.chooser_clear()
     return rows
 
@@ -282,11 +283,21 @@ def tail_analysis(F, Y, rows, top=12):
     s = np.exp(Fk[:, 3])
     for lo, hi in ((0, 1e-3), (1e-3, 1e-2), (1e-2, 0.1), (0.1, 0.5), (0.5, 1.01)):
         add(f"sel=[{lo:g},{hi:g})", (s >= lo) & (s < hi))
+    # milliseconds lost to the pick, and how much of the total the tail holds
+    lost = np.array([x[6] - x[5] for x in rows])
+    best = np.array([x[5] for x in rows])
+    tail = reg >= np.percentile(reg, 95)
+    groups["ms_lost"] = {"mean": round(float(lost.mean()), 4), "median": round(float(np.median(lost)), 4),
+                         "tail_p95_mean_best_ms": round(float(best[tail].mean()), 4),
+                         "tail_p95_mean_lost_ms": round(float(lost[tail].mean()), 4),
+                         "all_mean_best_ms": round(float(best.mean()), 4),
+                         "total_lost_over_total_best": round(float(lost.sum() / best.sum()), 4)}
     worst = np.argsort(-reg)[:top]
     w = [{"N": int(round(math.exp(Fk[i, 0]))), "d": int(round(math.exp(Fk[i, 1]))),
           "B": int(round(math.exp(Fk[i, 2]))), "est_sel": float(math.exp(Fk[i, 3])),
           "k": int(round(math.exp(Fk[i, 4]))), "dtype": int(Fk[i, 5]), "regret": round(float(reg[i]), 3),
-          "learned_arm": rows[i][2], "best_arm": rows[i][4]} for i in worst]
+          "learned_arm": rows[i][2], "best_arm": rows[i][4], "best_ms": round(rows[i][5], 4),
+          "learned_ms": round(rows[i][6], 4)} for i in worst]
     return {"groups": groups, "worst": w}
 
 
@@ -367,11 +378,17 @@ def main():
         vrs.chooser_pick(f0, al)
     host_us = (time.perf_counter() - t0) / 10000 * 1e6
     vrs.chooser_clear()
+    # the same Python marshalling around a call that returns at once (no network)
+    t0 = time.perf_counter()
+    for _ in range(10000):
+        vrs.chooser_pick(f0, al)
+    empty_us = (time.perf_counter() - t0) / 10000 * 1e6
     report = {"heldout_workloads": int(Fh.shape[0]), "heldout_timed_arms": int((np.isfinite(Yh) & ~Ch).sum()),
               "heldout_censored_arms": int(Ch.sum()), "collect_heldout_s": round(float(H["collect_s"]), 1),
               "regret": summarize(rows), "tail": tail_analysis(Fh, Yh, rows),
               "inference_us": {"host_pick_incl_python_call": round(host_us, 2),
-                               "hip_forward_one_workload": round(float(H["hip_infer_us"]), 2)},
+                               "host_pick_net_of_python_call": round(host_us - empty_us, 2),
+                               "hip_forward_one_workload_incl_python_launch": round(float(H["hip_infer_us"]), 2)},
               "arms": int(Yh.shape[1])}
     if os.path.exists(args.trainset):
         T = np.load(args.trainset)

@@ -573,20 +573,16 @@ bool chooser_ready() {
 }
 
 // Host inference of the chooser network (same layer formula as the kernels).
-int chooser_pick(const float feats[6], const bool *allowed, int n_arms) {
-    float y = 0.0f;
-    return chooser_pick_value(feats, allowed, n_arms, &y);
-}
-
-int chooser_pick_value(const float feats[6], const bool *allowed, int n_arms, float *value) {
-    std::lock_guard<std::mutex> g(g_ch_mu);
-    if (!g_ch_ready) return -1;
+// The network's forward pass on the host: fmaf per multiply-add (the same
+// correctly rounded operation as the GPU kernel's), compiled twice: with the
+// FMA instruction set when the CPU has it, else through the library call.
+__attribute__((always_inline)) static inline void mlp_host(const float *p, const float *mean, const float *stdv,
+                                                           const float feats[6], float *y) {
     const int NI = VRS_MLP_IN, NH = VRS_MLP_HIDDEN, NO = VRS_MLP_OUT;
-    const float *p = g_ch_p.data();
     const float *W1 = p, *b1 = W1 + NI * NH, *W2 = b1 + NH, *b2 = W2 + NH * NH, *W3 = b2 + NH,
                 *b3 = W3 + NH * NO;
-    float x[NI], h1[NH], h2[NH], y[NO];
-    for (int i = 0; i < NI; ++i) x[i] = (feats[i] - g_ch_mean[i]) / g_ch_std[i];
+    float x[VRS_MLP_IN], h1[VRS_MLP_HIDDEN], h2[VRS_MLP_HIDDEN];
+    for (int i = 0; i < NI; ++i) x[i] = (feats[i] - mean[i]) / stdv[i];
     for (int j = 0; j < NH; ++j) {
         float a = b1[j];
         for (int i = 0; i < NI; ++i) a = fmaf(x[i], W1[i * NH + j], a);
@@ -602,6 +598,30 @@ int chooser_pick_value(const float feats[6], const bool *allowed, int n_arms, fl
         for (int i = 0; i < NH; ++i) a = fmaf(h2[i], W3[i * NO + j], a);
         y[j] = a;
     }
+}
+__attribute__((target("fma"))) static void mlp_host_fma(const float *p, const float *mean, const float *stdv,
+                                                        const float feats[6], float *y) {
+    mlp_host(p, mean, stdv, feats, y);
+}
+static void mlp_host_any(const float *p, const float *mean, const float *stdv, const float feats[6], float *y) {
+    mlp_host(p, mean, stdv, feats, y);
+}
+static const bool g_host_fma = __builtin_cpu_supports("fma");
+
+int chooser_pick(const float feats[6], const bool *allowed, int n_arms) {
+    float y = 0.0f;
+    return chooser_pick_value(feats, allowed, n_arms, &y);
+}
+
+int chooser_pick_value(const float feats[6], const bool *allowed, int n_arms, float *value) {
+    std::lock_guard<std::mutex> g(g_ch_mu);
+    if (!g_ch_ready) return -1;
+    const int NO = VRS_MLP_OUT;
+    float y[VRS_MLP_OUT];
+    if (g_host_fma)
+        mlp_host_fma(g_ch_p.data(), g_ch_mean.data(), g_ch_std.data(), feats, y);
+    else
+        mlp_host_any(g_ch_p.data(), g_ch_mean.data(), g_ch_std.data(), feats, y);
     int best = -1;
     for (int j = 0; j < std::min(n_arms, NO); ++j)
         if (allowed[j] && (best < 0 || y[j] < y[best])) best = j;
