@@ -142,23 +142,41 @@ __device__ __forceinline__ uint64_t group_mask(const BatchArgs &a, const QRange 
     return m;
 }
 
+// Query ranges are read 64 at a time, one per lane (all in flight together),
+// and each query's fields are then taken from its lane (v_readlane: uniform
+// values, no memory access inside the per-query loop).
+__device__ __forceinline__ QRange range_of_lane(const QRange &mine, int t) {
+    QRange r;
+    r.b = __builtin_amdgcn_readlane(mine.b, t);
+    r.kind = __builtin_amdgcn_readlane(mine.kind, t);
+    r.lo0 = __builtin_amdgcn_readlane(mine.lo0, t);
+    r.lo1 = __builtin_amdgcn_readlane(mine.lo1, t);
+    r.span0 = (uint32_t)__builtin_amdgcn_readlane((int)mine.span0, t);
+    r.span1 = (uint32_t)__builtin_amdgcn_readlane((int)mine.span1, t);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine.off, t);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mine.off >> 32), t);
+    r.off = (int64_t)(((uint64_t)hi << 32) | lo);
+    return r;
+}
+
 template <bool FULL>
 __device__ __forceinline__ void count_sub(const BatchArgs &a, int sub, int part, int lane, int64_t row0,
                                           const int32_t (&v0)[GROUPS], const int32_t (&v1)[GROUPS]) {
     const int nc = a.ctl[BC_NCAND];
     const int j0 = (int)((int64_t)nc * part / QSPLIT), j1 = (int)((int64_t)nc * (part + 1) / QSPLIT);
-    if (j0 >= j1) return;
-    QRange rn = a.cands[j0];
-    for (int j = j0; j < j1; ++j) {
-        const QRange r = rn;
-        if (j + 1 < j1) rn = a.cands[j + 1];  // in flight while this query is counted
-        uint32_t c = 0;
-        if (r.kind != 2) {
+    for (int jb = j0; jb < j1; jb += 64) {
+        const QRange mine = jb + lane < j1 ? a.cands[jb + lane] : QRange{0, 2, 0, 0, 0u, 0u, 0};
+        const int m = min(64, j1 - jb);
+        for (int t = 0; t < m; ++t) {
+            const QRange r = range_of_lane(mine, t);
+            uint32_t c = 0;
+            if (r.kind != 2) {
 #pragma unroll
-            for (int g = 0; g < GROUPS; ++g)
-                c += (uint32_t)__popcll(group_mask<FULL>(a, r, v0[g], v1[g], row0, g, lane));
+                for (int g = 0; g < GROUPS; ++g)
+                    c += (uint32_t)__popcll(group_mask<FULL>(a, r, v0[g], v1[g], row0, g, lane));
+            }
+            if (lane == 0) a.subcnt[(int64_t)sub * a.B + r.b] = c;
         }
-        if (lane == 0) a.subcnt[(int64_t)sub * a.B + r.b] = c;
     }
 }
 
@@ -311,23 +329,23 @@ __device__ __forceinline__ void write_sub(const BatchArgs &a, int sub, int part,
     const uint64_t below = (1ull << lane) - 1ull;
     const int ns = a.ctl[BC_NSPARSE];
     const int j0 = (int)((int64_t)ns * part / QSPLIT), j1 = (int)((int64_t)ns * (part + 1) / QSPLIT);
-    if (j0 >= j1) return;
-    QRange rn = a.sq[j0];
-    uint32_t pn = a.subcnt[(int64_t)sub * a.B + rn.b];
-    for (int j = j0; j < j1; ++j) {
-        const QRange r = rn;
-        const uint32_t pre = pn;
-        if (j + 1 < j1) {  // next query's range and slot, in flight meanwhile
-            rn = a.sq[j + 1];
-            pn = a.subcnt[(int64_t)sub * a.B + rn.b];
-        }
-        if (r.kind == 2) continue;
-        int32_t *dst = a.pool + r.off + pre;
+    for (int jb = j0; jb < j1; jb += 64) {
+        // 64 queries' ranges and first slots in this sub-block, one per lane
+        const bool has = jb + lane < j1;
+        const QRange mine = has ? a.sq[jb + lane] : QRange{0, 2, 0, 0, 0u, 0u, 0};
+        const uint32_t mypre = has ? a.subcnt[(int64_t)sub * a.B + mine.b] : 0u;
+        const int m = min(64, j1 - jb);
+        for (int t = 0; t < m; ++t) {
+            const QRange r = range_of_lane(mine, t);
+            if (r.kind == 2) continue;
+            const uint32_t pre = (uint32_t)__builtin_amdgcn_readlane((int)mypre, t);
+            int32_t *dst = a.pool + r.off + pre;
 #pragma unroll
-        for (int g = 0; g < GROUPS; ++g) {
-            const uint64_t m = group_mask<FULL>(a, r, v0[g], v1[g], row0, g, lane);
-            if ((m >> lane) & 1ull) dst[__popcll(m & below)] = (int32_t)(row0 + g * 64 + lane);
-            dst += __popcll(m);
+            for (int g = 0; g < GROUPS; ++g) {
+                const uint64_t mk = group_mask<FULL>(a, r, v0[g], v1[g], row0, g, lane);
+                if ((mk >> lane) & 1ull) dst[__popcll(mk & below)] = (int32_t)(row0 + g * 64 + lane);
+                dst += __popcll(mk);
+            }
         }
     }
 }

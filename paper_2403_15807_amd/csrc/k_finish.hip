@@ -130,9 +130,11 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
     __shared__ int ncol_s;
 
     // phase 1: the K-th smallest head's distance bits bound every key of
-    // the result (keys with the same distance bits are all kept)
-    int m = max(1, min(K, (2 * K + L - 1) / L));
-    if (L * m > MERGE_HMAX) m = max(1, MERGE_HMAX / L);
+    // the result (keys with the same distance bits are all kept).  As many
+    // heads per list as fit are taken: with one per list, lists whose rows
+    // are all near the query (rows of one cluster in one chunk) each put a
+    // single key below the bound and leave many more keys at or under it.
+    const int m = max(1, min(K, MERGE_HMAX / L));
     const int H = min(L * m, MERGE_HMAX);
     // with one head per list, a side array of the lists' first keys (when
     // the screening kernel wrote one) is read instead of the lists
