@@ -158,7 +158,12 @@ vrs_status vrs_select_workspace_bytes(vrs_table t, size_t *bytes);
 vrs_status vrs_select(vrs_table t, const vrs_pred *pred /* host */, int32_t *ids_out,
                       int64_t *count_out, void *ws, size_t ws_bytes, void *stream);
 
-/* Filtered exact top-k for B queries sharing one predicate.
+/* Filtered exact top-k for B queries sharing one predicate: the query of
+ * Section 3, eq. 3 (the k rows of sigma_theta(R) nearest to q, by the exact
+ * distance of the definition, ties by row id), computed by screening in FP32
+ * (the strategy, mask or gather, of Section 3.2; the tensor formulation of
+ * Section 3.1 for batches), an FP64 rerank of the k' survivors and a
+ * certificate, with an exact fallback for an uncertified query.
  *   q:        [B][d] float32 (device), finite.
  *   pred:     host pointer, one conjunction for the whole batch.
  *   1 <= k <= 256.

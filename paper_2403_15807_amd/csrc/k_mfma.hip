@@ -317,11 +317,30 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
 }
 
 
+// Work item of workgroup `id` in a one-dimensional grid of nchunks x nq
+// items.  Workgroups go to the 8 XCDs round-robin (XCD = id mod 8); when
+// nchunks is a multiple of 8, XCD x takes chunks x, x + 8, ... and, for each
+// chunk, its nq query tiles one after another, so that the query tiles of a
+// chunk run at the same time on one XCD and read the chunk's rows through
+// its L2 once.
+__device__ __forceinline__ void xcd_item(int id, int nchunks, int nq, int *chunk, int *qt) {
+    if ((nchunks & 7) == 0) {
+        const int x = id & 7, slot = id >> 3;
+        *chunk = x + 8 * (slot / nq);
+        *qt = slot - (slot / nq) * nq;
+    } else {
+        *chunk = id % nchunks;
+        *qt = id / nchunks;
+    }
+}
+
 template <int DP, int METRIC, bool GATHER, bool BATCHED, int E, int MB, int G>
 __global__ __launch_bounds__(256, (E <= 8 && MB == 1 && G == 1) ? 3 : 2) void screen_mfma_f32_kernel(ScreenArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    f32_tile<DP, METRIC, GATHER, BATCHED, E, MB, G>(a, blockIdx.x, a.n_chunks, blockIdx.y * (64 * MB / G), a.B,
-                                                    smem);
+    constexpr int QM = 64 * MB / G;
+    int chunk, qt;
+    xcd_item(blockIdx.x, a.n_chunks, (a.B + QM - 1) / QM, &chunk, &qt);
+    f32_tile<DP, METRIC, GATHER, BATCHED, E, MB, G>(a, chunk, a.n_chunks, qt * QM, a.B, smem);
 }
 
 // Persistent form (batched uneven launch), queue per XCD: see the bfloat16
@@ -367,7 +386,7 @@ hipError_t launch_e(const ScreenArgs &a, hipStream_t s) {
     if (MB == 1 && !a.preds && a.B <= 16) {
         // one group of 16 queries shared by the four waves (each takes 16 of
         // a tile's 64 rows)
-        dim3 grid(a.n_chunks, (a.B + 15) / 16), block(256);
+        dim3 grid(a.n_chunks * ((a.B + 15) / 16)), block(256);
         auto k = a.gather ? screen_mfma_f32_kernel<DP, METRIC, true, false, E, 1, 4>
                           : screen_mfma_f32_kernel<DP, METRIC, false, false, E, 1, 4>;
         ensure_dyn_lds((const void *)k, lds);
@@ -375,7 +394,7 @@ hipError_t launch_e(const ScreenArgs &a, hipStream_t s) {
         return hipGetLastError();
     }
     constexpr int QM = 64 * MB;
-    dim3 grid(a.n_chunks, (a.B + QM - 1) / QM), block(256);
+    dim3 grid(a.n_chunks * ((a.B + QM - 1) / QM)), block(256);
     if (a.preds) {
         auto k = screen_mfma_f32_kernel<DP, METRIC, false, true, E, MB, 1>;
         ensure_dyn_lds((const void *)k, lds);

@@ -379,10 +379,29 @@ __device__ __forceinline__ void bf16_tile(const ScreenArgs &a, const int chunk, 
     }
 }
 
+// Work item of workgroup `id` in a one-dimensional grid of nchunks x nq
+// items.  Workgroups go to the 8 XCDs round-robin (XCD = id mod 8); when
+// nchunks is a multiple of 8, XCD x takes chunks x, x + 8, ... and, for each
+// chunk, its nq query tiles one after another, so that the query tiles of a
+// chunk run at the same time on one XCD and read the chunk's rows through
+// its L2 once.
+__device__ __forceinline__ void xcd_item(int id, int nchunks, int nq, int *chunk, int *qt) {
+    if ((nchunks & 7) == 0) {
+        const int x = id & 7, slot = id >> 3;
+        *chunk = x + 8 * (slot / nq);
+        *qt = slot - (slot / nq) * nq;
+    } else {
+        *chunk = id % nchunks;
+        *qt = id / nchunks;
+    }
+}
+
 template <int STORE, bool GATHER, bool BATCHED, int E, int KC>
 __global__ __launch_bounds__(NT) void screen_mfma_bf16_kernel(ScreenArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    bf16_tile<STORE, GATHER, BATCHED, E, KC>(a, blockIdx.x, a.n_chunks, blockIdx.y * QM, a.B, smem);
+    int chunk, qt;
+    xcd_item(blockIdx.x, a.n_chunks, (a.B + QM - 1) / QM, &chunk, &qt);
+    bf16_tile<STORE, GATHER, BATCHED, E, KC>(a, chunk, a.n_chunks, qt * QM, a.B, smem);
 }
 
 // Persistent form (batched uneven launch): the dense queries are positions
@@ -428,7 +447,7 @@ __global__ __launch_bounds__(NT) void screen_mfma_bf16_persistent(ScreenArgs a) 
 
 template <int STORE, int E, int KC>
 hipError_t launch_sek(const ScreenArgs &a, hipStream_t s) {
-    dim3 grid(a.n_chunks, (a.B + QM - 1) / QM), block(NT);
+    dim3 grid(a.n_chunks * ((a.B + QM - 1) / QM)), block(NT);
     const size_t lds = screen_mfma_bf16_lds(KC);
     if (a.preds) {
         auto k = screen_mfma_bf16_kernel<STORE, false, true, E, KC>;
