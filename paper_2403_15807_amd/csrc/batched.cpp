@@ -132,7 +132,8 @@ const BatchCfg &batched_cfg(int i) { return kCfgs[i]; }
 bool batched_native(const vrs_table_s *t, int kmax, int metric, const vrs_opts *opts) {
     const int kmult = opts ? opts->kprime_mult : 0;
     const int Kp = next_pow2(kprime_rule(kmax, t->store, kmult) + 1);
-    if (t->store == VRS_F32) return screen_mfma_supported(t->dp, t->store, Kp, mfma_cb(Kp));
+    // (the persistent FP32 kernel keeps whole rows of at most 256 coordinates)
+    if (t->store == VRS_F32) return t->dp <= 256 && screen_mfma_supported(t->dp, t->store, Kp, mfma_cb(Kp));
     return screen_mfma_bf16_supported(t->dp, t->store, metric, Kp, mfma_cb(Kp));
 }
 

@@ -46,6 +46,11 @@ constexpr int BR = 64;  // rows per tile
 // the group's waves split every 64-row tile between them, so that all four
 // SIMDs of the CU run MFMAs for a small batch; the group's candidates are
 // then merged by its first wave after a workgroup barrier.
+// DP = the padded dimension, or 0 for rows wider than 256 coordinates (any
+// multiple of 128, taken from the table): those are multiplied in chunks of
+// 128 coordinates, each chunk staged in LDS while the next one's loads are in
+// flight, with the query fragments of the chunk read from the (L2-resident)
+// prepared queries; the accumulators carry over the chunks.
 // One work item: queries [q0, q0 + QM) (of Bq) against row chunk `chunk` of
 // `nchunks`; its lists are (query, chunk) lists of the partials.
 template <int DP, int METRIC, bool GATHER, bool BATCHED, int E, int MB, int G = 1>
@@ -55,11 +60,15 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
     constexpr int QM = 64 * MB / G;
     constexpr int QW = 16 * MB;            // queries per wave group
     constexpr int NBW = 4 / G;             // 16-row blocks of a tile per wave
-    constexpr int NT4 = DP / 16;           // float4 A-fragments per lane per block
-    constexpr int LDX = DP + 4;            // padded LDS row stride (floats)
-    constexpr int NV4 = DP / 4;            // float4 per row
+    constexpr bool CHK = DP == 0;          // rows in chunks of 128 coordinates
+    constexpr int CH = CHK ? 128 : DP;     // coordinates staged at a time
+    constexpr int NT4 = CH / 16;           // float4 A-fragments per lane per block
+    constexpr int LDX = CH + 4;            // padded LDS row stride (floats)
+    constexpr int NV4 = CH / 4;            // float4 per staged row
     constexpr int RP = 256 / NV4;          // rows staged per pass
     constexpr int PASSES = BR / RP;
+    const int dpr = CHK ? a.dp : DP;       // row stride (floats)
+    const int nch = CHK ? a.dp / CH : 1;   // coordinate chunks per row
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int qw0 = (wave / G) * QW;       // the wave's first query in the workgroup
     const int nb0 = (wave % G) * NBW;      // the wave's first 16-row block of a tile
@@ -80,14 +89,17 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
     // A fragments: lane (m = lane % 16, kq = lane / 16) of wave w holds, for
     // block mb, query q0 + qw0 + 16*mb + m at coordinates 16t + 4kq + c.
     float4 af[MB][NT4];
+    auto load_af = [&](int ch) {
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-        const int mq = q0 + qw0 + mb * 16 + (lane & 15);
+        for (int mb = 0; mb < MB; ++mb) {
+            const int mq = q0 + qw0 + mb * 16 + (lane & 15);
 #pragma unroll
-        for (int t = 0; t < NT4; ++t)
-            af[mb][t] = mq < Bq ? *(const float4 *)(a.qp + (int64_t)mq * DP + 16 * t + 4 * (lane >> 4))
-                                 : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+            for (int t = 0; t < NT4; ++t)
+                af[mb][t] = mq < Bq ? *(const float4 *)(a.qp + (int64_t)mq * dpr + ch * CH + 16 * t + 4 * (lane >> 4))
+                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    if (!CHK) load_af(0);
     if (BATCHED && tid < QM) qpred[tid] = q0 + tid < Bq ? a.preds[q0 + tid] : PredDev{-1, {0}, {0}, {0}};
     // per-query state (private to the wave group) and list initialisation
     for (int i = lane; owner && i < QW; i += 64) {
@@ -146,28 +158,29 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
     // as soon as tile t is in LDS, so they are in flight during tile t's
     // product and epilogue (the registers this costs would cost the wide form
     // a resident workgroup); the wide form loads a tile when it starts it.
-    constexpr bool PF = G > 1;
+    constexpr bool PF = G > 1 && !CHK;
     float4 w[PASSES];
-    auto issue_rows = [&](int64_t t0) {
+    auto issue_rows = [&](int64_t t0, int ch) {
 #pragma unroll
         for (int p = 0; p < PASSES; ++p) {
             const int64_t pos = t0 + p * RP + sr;
             const int64_t row = GATHER ? (int64_t)sid[p] : pos;
-            w[p] = pos < c1 ? load_x((const float4 *)(X + row * DP) + sc, a.shared_rows)
+            w[p] = pos < c1 ? load_x((const float4 *)(X + row * dpr + ch * CH) + sc, a.shared_rows)
                             : make_float4(0.f, 0.f, 0.f, 0.f);
         }
     };
     if (GATHER) issue_ids(c0);
     issue_rowinfo(c0);
     if (PF) {
-        issue_rows(c0);
+        issue_rows(c0, 0);
         if (GATHER && c0 + BR < c1) issue_ids(c0 + BR);
     }
 
     for (int64_t t0 = c0; t0 < c1; t0 += BR) {
         if (!PF) {
-            issue_rows(t0);
-            if (GATHER && t0 + BR < c1) issue_ids(t0 + BR);
+            issue_rows(t0, 0);
+            // (chunked rows still need this tile's ids for their later chunks)
+            if (GATHER && !CHK && t0 + BR < c1) issue_ids(t0 + BR);
         }
         // ---- tile t0: per-row record and rows -> LDS
         bool mine = false;
@@ -189,21 +202,34 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
         for (int p = 0; p < PASSES; ++p) *(float4 *)(xs + (p * RP + sr) * LDX + 4 * sc) = w[p];
         const int any = __syncthreads_or(mine);
         if (PF && t0 + BR < c1) {
-            issue_rows(t0 + BR);
+            issue_rows(t0 + BR, 0);
             if (GATHER && t0 + 2 * BR < c1) issue_ids(t0 + 2 * BR);
         }
-        if (!any) continue;
+        if (!any) {
+            if (GATHER && CHK && t0 + BR < c1) issue_ids(t0 + BR);
+            continue;
+        }
 
         // A wave whose queries all lie past the batch (a partial query
         // tile) skips the product and the epilogue; it still stages rows
         // and meets every barrier.
-        if (q0 + qw0 < Bq) {
-            // ---- Q X^T for the group's QW queries x the wave's NBW * 16 rows
-            f4v acc[MB][NBW];
+        const bool act = q0 + qw0 < Bq;
+        // ---- Q X^T for the group's QW queries x the wave's NBW * 16 rows
+        f4v acc[MB][NBW];
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
+        for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = (f4v){0.f, 0.f, 0.f, 0.f};
+            for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = (f4v){0.f, 0.f, 0.f, 0.f};
+        for (int ch = 0; ch < nch; ++ch) {
+            if (CHK && ch > 0) {
+                __syncthreads();  // every wave is done with chunk ch - 1
+#pragma unroll
+                for (int p = 0; p < PASSES; ++p) *(float4 *)(xs + (p * RP + sr) * LDX + 4 * sc) = w[p];
+                __syncthreads();
+            }
+            if (CHK && ch + 1 < nch) issue_rows(t0, ch + 1);  // in flight during this chunk's product
+            if (!act) continue;
+            if (CHK) load_af(ch);
 #pragma unroll
             for (int t = 0; t < NT4; ++t) {
                 float4 bv[NBW];
@@ -220,7 +246,9 @@ __device__ __forceinline__ void f32_tile(const ScreenArgs &a, const int chunk, c
                         for (int nb = 0; nb < NBW; ++nb)
                             acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb][t][c], bv[nb][c], acc[mb][nb], 0, 0, 0);
             }
-
+        }
+        if (GATHER && CHK && t0 + BR < c1) issue_ids(t0 + BR);
+        if (act) {
             // ---- epilogue: lane holds queries qw0 + 16mb + 4(lane/16) + i, rows
             // 16(nb0 + nb) + lane%16
             if (owner && (((t0 - c0) / BR) & 15) == 15) {
@@ -382,7 +410,7 @@ __global__ __launch_bounds__(256, (E <= 8 && MB == 1) ? 3 : 2) void screen_mfma_
 
 template <int DP, int METRIC, int E, int MB>
 hipError_t launch_e(const ScreenArgs &a, hipStream_t s) {
-    const size_t lds = screen_mfma_lds(DP, 64 * MB);
+    const size_t lds = screen_mfma_lds(DP ? DP : a.dp, 64 * MB);  // (DP = 0: chunked rows of a.dp)
     if (MB == 1 && !a.preds && a.B <= 16) {
         // one group of 16 queries shared by the four waves (each takes 16 of
         // a tile's 64 rows)
@@ -428,14 +456,17 @@ hipError_t launch_m(const ScreenArgs &a, hipStream_t s) {
     case 64: return launch_dp<64, METRIC, MB>(a, s);
     case 128: return launch_dp<128, METRIC, MB>(a, s);
     case 256: return launch_dp<256, METRIC, MB>(a, s);
-    default: return hipErrorInvalidValue;
+    default:
+        if (a.dp > 256 && a.dp % 128 == 0) return launch_dp<0, METRIC, MB>(a, s);  // chunked rows
+        return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
 size_t screen_mfma_lds(int dp, int qm) {
-    return (size_t)BR * (dp + 4) * 4 + BR * 12 + qm * 12 + 8 + qm * 8 + qm * sizeof(PredDev) + 16;
+    const int ch = dp > 256 ? 128 : dp;  // coordinates staged at a time
+    return (size_t)BR * (ch + 4) * 4 + BR * 12 + qm * 12 + 8 + qm * 8 + qm * sizeof(PredDev) + 16;
 }
 
 // Resident workgroups per CU (register budget of the kernel, set by E and the
@@ -447,7 +478,7 @@ int screen_mfma_occupancy(int Kp, int CB, int qm) {
 
 bool screen_mfma_supported(int dp, vrs_dtype store, int Kp, int CB) {
     const int E = (Kp + CB) / 64;
-    return store == VRS_F32 && (dp == 32 || dp == 64 || dp == 128 || dp == 256) &&
+    return store == VRS_F32 && (dp == 32 || dp == 64 || dp == 128 || dp == 256 || (dp > 256 && dp % 128 == 0)) &&
            (E == 4 || E == 8 || E == 16 || E == 32) && (Kp + CB) == 64 * E;
 }
 

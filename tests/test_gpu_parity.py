@@ -177,6 +177,28 @@ def test_mfma_query_tiles(B, metric):
                 _check(r, ref, f"B {B} metric {metric} k {k} strategy {strategy} tile {tile}")
 
 
+@pytest.mark.parametrize("d", [384, 768, 1536])
+@pytest.mark.parametrize("B", [5, 16, 70])
+def test_mfma_f32_wide_rows_in_coordinate_chunks(d, B):
+    # float32 rows wider than 256 coordinates: the FP32 MFMA screen takes
+    # them 128 coordinates at a time (B <= 16: the small-batch form)
+    n = 12001
+    x = inputs.table(13, n, d, 100)
+    a = inputs.attributes(13, n, 1, 1000)
+    q = inputs.queries(13, B, d, 100)
+    for metric in (vrs.L2SQ, vrs.IP):
+        T = vrs.Table(_dev(x), _dev(a), normalize=(metric == vrs.IP))
+        ot = O.Table.build(x, a, O.F32, normalize=(metric == vrs.IP))
+        pred = [(0, 0, 700)]
+        for k in (1, 100):
+            ref = O.scan_topk(ot, q, pred, k, metric)
+            for strategy in (vrs.STRATEGY_MASK, vrs.STRATEGY_GATHER):
+                _, su, tu = T.plan(B, pred, k, metric, strategy=strategy, tile=4, chooser=vrs.CHOOSER_HEURISTIC)
+                assert (su, tu) == (strategy, 4), "the FP32 MFMA tile must be available"
+                r = T.scan_topk(_dev(q), pred, k, metric, strategy=strategy, tile=4)
+                _check(r, ref, f"d {d} B {B} metric {metric} k {k} strategy {strategy}")
+
+
 def test_fewer_qualifying_rows_than_k_and_empty():
     x, a, q = _config0(n=5000, B=3)
     T = vrs.Table(_dev(x), _dev(a))

@@ -117,3 +117,30 @@ def test_probe_low_precision_ip_equals_the_oracle(store, ostore):
         assert np.array_equal(gt2.cpu().numpy(), ref[2])
         assert np.array_equal(gi2.cpu().numpy(), ref[0])
         assert np.array_equal(gd2.cpu().numpy().view(np.uint32), ref[1].view(np.uint32))
+
+
+def test_probe_many_partitions_equals_the_oracle():
+    # more centroids than the coarse scan sorts at once (4096): the running
+    # top list orders the walk; two predicate terms, inner product on f32
+    n, d, nlist = 40000, 32, 5000
+    x = inputs.table(12, n, d, 300)
+    a = inputs.attributes(12, n, 2, 50)
+    T = vrs.Table(_dev(x), _dev(a))
+    ix = vrs.Index(T, nlist, iters=2)
+    ot = O.Table(O.F32, x, a)
+    cent, _, off, ids = O.ivf_build(ot, nlist, 2)
+    gc, go, gi = ix.export()
+    torch.cuda.synchronize()
+    assert np.array_equal(gc.cpu().numpy().view(np.uint32), cent.view(np.uint32))
+    assert np.array_equal(go.cpu().numpy(), off)
+    q = inputs.queries(12, 9, d, 300)
+    pred = [(0, 5, 40), (1, 0, 30)]
+    for metric, om in ((vrs.L2SQ, O.L2SQ), (vrs.IP, O.IP)):
+        for nprobe, min_cand, cap_c in ((3, 200, 10 ** 6), (256, 1, 2000)):
+            ref = O.ivf_probe(ot, cent, off, ids, q, pred, 25, om, nprobe, min_cand, cap_c)
+            gi2, gd2, gt2 = ix.probe_topk(_dev(q), pred, 25, metric, nprobe, min_cand, cap_c)
+            torch.cuda.synchronize()
+            what = f"metric {metric} nprobe {nprobe} min_cand {min_cand} cap {cap_c}"
+            assert np.array_equal(gt2.cpu().numpy(), ref[2]), what
+            assert np.array_equal(gi2.cpu().numpy(), ref[0]), what
+            assert np.array_equal(gd2.cpu().numpy().view(np.uint32), ref[1].view(np.uint32)), what
