@@ -363,6 +363,8 @@ __device__ __forceinline__ void xcd_item(int id, int nchunks, int nq, int *chunk
 }
 
 template <int DP, int METRIC, bool GATHER, bool BATCHED, int E, int MB, int G>
+// (the chunked form at 3 workgroups per CU spills a few registers outside its
+// inner loop; with the registers for 2 it measured 10 % slower on 4M x 768)
 __global__ __launch_bounds__(256, (E <= 8 && MB == 1 && G == 1) ? 3 : 2) void screen_mfma_f32_kernel(ScreenArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int QM = 64 * MB / G;

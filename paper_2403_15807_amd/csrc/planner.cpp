@@ -25,6 +25,7 @@ const TileCfg kTiles[] = {
     {1, 64, 4}, {1, 128, 4}, {1, 64, 8}, {1, 128, 8},
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+constexpr int kChooserMaxB = 4096;  // largest batch of the chooser's training workloads
 constexpr size_t LDS_BUDGET = 64 * 1024;  // several workgroups per CU
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -287,7 +288,7 @@ static void chooser_arms(const vrs_table_s *t, int B, int k, int metric, bool ba
 }
 
 double plan_predict_ms(const vrs_table_s *t, int B, const PredDev &p, int k, int metric) {
-    if (!chooser_ready()) return -1.0;
+    if (!chooser_ready() || B > kChooserMaxB) return -1.0;
     const double est_sel = estimate_selectivity(t, p);
     float feats[6];
     plan_features(t, B, est_sel, k, feats);
@@ -304,7 +305,10 @@ void plan_decide(const vrs_table_s *t, int B, const PredDev &p, bool batched, in
     plan_features(t, B, est_sel, k, feats);
     const int want_s = opts ? opts->strategy : VRS_STRATEGY_AUTO;
     const int want_t = opts ? opts->tile : -1;
-    const bool learned = (!opts || opts->chooser == VRS_CHOOSER_LEARNED) && chooser_ready();
+    // The network is trained on batches of 1 to kChooserMaxB queries; larger
+    // ones (e.g. a join's batches of R rows) take the heuristic rather than an
+    // extrapolation.
+    const bool learned = (!opts || opts->chooser == VRS_CHOOSER_LEARNED) && chooser_ready() && B <= kChooserMaxB;
     if (learned && (want_s == VRS_STRATEGY_AUTO || want_t < 0)) {
         bool allowed[2 * kNumTiles];
         chooser_arms(t, B, k, metric, batched, est_sel, opts, allowed);
