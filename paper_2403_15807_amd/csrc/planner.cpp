@@ -125,7 +125,14 @@ bool tile_ok(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int ti
     if (kTiles[tile].kind == 0) return true;
     const int kmult = opts ? opts->kprime_mult : 0;
     const int Kp = next_pow2(kprime_rule(kmax, t->store, kmult) + 1);
-    if (t->store == VRS_F32) return screen_mfma_supported(t->dp, t->store, Kp, mfma_cb(Kp));
+    // Rows wider than 256 coordinates are multiplied in chunks, and every
+    // 64-row tile re-reads its queries' slice of the chunk: offered only while
+    // the batch's prepared queries fit one XCD's 4 MB L2 (at 1536 coordinates
+    // and 2000 queries the chunked form ran 2.4x slower than the streaming
+    // kernel).
+    if (t->store == VRS_F32)
+        return screen_mfma_supported(t->dp, t->store, Kp, mfma_cb(Kp)) &&
+               (t->dp <= 256 || (int64_t)B * t->dp * 4 <= ((int64_t)4 << 20));
     return screen_mfma_bf16_supported(t->dp, t->store, metric, Kp, mfma_cb(Kp));
 }
 
