@@ -249,8 +249,16 @@ __device__ uint32_t block_kth_u32(const uint32_t (&v)[S], int H, int K, uint32_t
         for (int i = tid; i < 256; i += T) hist[i] = 0;
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < S; ++e)
-            if (e * T + tid < H && (v[e] & mask) == prefix) atomicAdd(&hist[(v[e] >> shift) & 255u], 1u);
+        for (int e = 0; e < S; ++e) {
+            // all-ones values (the distance bits of an empty key, often most
+            // of the inputs) are counted per wave: one atomic instead of one
+            // per lane on the same bin
+            const bool act = e * T + tid < H && (v[e] & mask) == prefix;
+            const bool ones = act && v[e] == 0xffffffffu;
+            const uint64_t bo = __ballot(ones);
+            if (act && !ones) atomicAdd(&hist[(v[e] >> shift) & 255u], 1u);
+            if ((tid & 63) == 0 && bo != 0ull) atomicAdd(&hist[255], (uint32_t)__popcll(bo));
+        }
         __syncthreads();
         if (tid < 64) {
             uint32_t c[4], sum = 0;

@@ -339,6 +339,7 @@ struct FinishArgs {
     uint64_t *merge_mid;           // [B][ceil(n_chunks/2048)][K] (two-level merge)
     uint64_t *merged;              // [B][K]
     const int32_t *merge_limit;    // positions >= *merge_limit get an empty merged list (or null)
+    int32_t merge_one_head;        // the merge's bound starts from one head per list (dense predicates)
     double *rr_dist;               // [B][K] exact distances of the candidates
     double rel, abs_ip, abs_l2, max_norm;  // screening error model
     int32_t *fail_list;            // [B]

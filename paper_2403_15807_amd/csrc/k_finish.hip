@@ -104,7 +104,8 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
                                                               const int32_t *__restrict__ nlists,
                                                               const uint64_t *__restrict__ heads,
                                                               const int32_t *__restrict__ limit,
-                                                              const int32_t *__restrict__ fills) {
+                                                              const int32_t *__restrict__ fills,
+                                                              int one_head) {
     constexpr int T = MERGE_THREADS;
     const int g = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -130,96 +131,112 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
     __shared__ int ncol_s;
 
     // phase 1: the K-th smallest head's distance bits bound every key of
-    // the result (keys with the same distance bits are all kept).  As many
-    // heads per list as fit are taken: with one per list, lists whose rows
-    // are all near the query (rows of one cluster in one chunk) each put a
-    // single key below the bound and leave many more keys at or under it.
-    const int m = max(1, min(K, MERGE_HMAX / L));
-    const int H = min(L * m, MERGE_HMAX);
-    // with one head per list, a side array of the lists' first keys (when
-    // the screening kernel wrote one) is read instead of the lists
-    const uint64_t *hd = (heads && m == 1) ? heads + first + l0 : nullptr;
-    if (tid == 0) ncol_s = 0;
-    if (H < K) {
-        if (tid == 0) bound_s = 0xffffffffu;
-    } else {
-        constexpr int S = MERGE_HMAX / T;
-        uint32_t v[S];
+    // the result (keys with the same distance bits are all kept).  With
+    // one_head, first one head per list (few lists: a few), from the
+    // screening kernel's side array of first keys when it wrote one; if that
+    // collects more keys than the ranking takes, and otherwise from the
+    // start, the bound comes from as many heads per list as fit (lists whose
+    // rows are all near the query, e.g. the few selected rows of one chunk
+    // from one cluster, each put a single key below a one-head bound and
+    // leave many more at or under it).
+    const int m_max = max(1, min(K, MERGE_HMAX / L));
+    int m = m_max;
+    if (one_head) {
+        m = max(1, min(K, (2 * K + L - 1) / L));
+        if (L * m > MERGE_HMAX) m = max(1, MERGE_HMAX / L);
+    }
+    uint64_t bound = 0;
+    int C = 0;
+    for (int attempt = 0;; ++attempt) {
+        const int H = min(L * m, MERGE_HMAX);
+        // with one head per list, a side array of the lists' first keys (when
+        // the screening kernel wrote one) is read instead of the lists
+        const uint64_t *hd = (heads && m == 1) ? heads + first + l0 : nullptr;
+        if (tid == 0) ncol_s = 0;
+        if (H < K) {
+            if (tid == 0) bound_s = 0xffffffffu;
+        } else {
+            constexpr int S = MERGE_HMAX / T;
+            uint32_t v[S];
 #pragma unroll
-        for (int e = 0; e < S; ++e) {
-            const int i = min(e * T + tid, H - 1);
-            const int li = i / m, lj = i - li * m;
-            const uint64_t key = hd ? hd[i] : ((!fl || lj < fl[li]) ? lists[(int64_t)li * K + lj] : KEY_INF);
-            v[e] = (uint32_t)(key >> 32);
+            for (int e = 0; e < S; ++e) {
+                const int i = min(e * T + tid, H - 1);
+                const int li = i / m, lj = i - li * m;
+                const uint64_t key = hd ? hd[i] : ((!fl || lj < fl[li]) ? lists[(int64_t)li * K + lj] : KEY_INF);
+                v[e] = (uint32_t)(key >> 32);
+            }
+            uint32_t *hist = (uint32_t *)keys;  // the collection area is free until phase 2
+            const uint32_t bd = block_kth_u32<S, T>(v, H, K, hist, hist + 256);
+            if (tid == 0) bound_s = bd;
         }
-        uint32_t *hist = (uint32_t *)keys;  // the collection area is free until phase 2
-        const uint32_t bd = block_kth_u32<S, T>(v, H, K, hist, hist + 256);
-        if (tid == 0) bound_s = bd;
-    }
-    __syncthreads();
-    const uint64_t bound = ((uint64_t)bound_s << 32) | 0xffffffffu;
+        __syncthreads();
+        bound = ((uint64_t)bound_s << 32) | 0xffffffffu;
 
-    // phase 2: collect every list prefix at or below the bound.  Thread tid
-    // owns lists tid + j*T (j < 4, since G <= 4T); each round it reads the
-    // next two entries of up to two of its lists, so most lists cost one
-    // round.
-    int pos[4] = {0, 0, 0, 0};
-    int len[4];
-    bool live[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int l = tid + j * T;
-        len[j] = (fl && l < L) ? fl[l] : K;
-        live[j] = l < L && len[j] > 0 && (!hd || hd[min(l, L - 1)] <= bound);
-    }
-    for (;;) {
-        int sel0 = -1, sel1 = -1;
+        // phase 2: collect every list prefix at or below the bound.  Thread tid
+        // owns lists tid + j*T (j < 4, since G <= 4T); each round it reads the
+        // next two entries of up to two of its lists, so most lists cost one
+        // round.
+        int pos[4] = {0, 0, 0, 0};
+        int len[4];
+        bool live[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            if (live[j] && sel0 < 0) sel0 = j;
-            else if (live[j] && sel1 < 0) sel1 = j;
+            const int l = tid + j * T;
+            len[j] = (fl && l < L) ? fl[l] : K;
+            live[j] = l < L && len[j] > 0 && (!hd || hd[min(l, L - 1)] <= bound);
         }
-        uint64_t v[2][2];
+        for (;;) {
+            int sel0 = -1, sel1 = -1;
 #pragma unroll
-        for (int x = 0; x < 2; ++x) {
-            const int j = x == 0 ? sel0 : sel1;
-            int n = 0;
+            for (int j = 0; j < 4; ++j) {
+                if (live[j] && sel0 < 0) sel0 = j;
+                else if (live[j] && sel1 < 0) sel1 = j;
+            }
+            uint64_t v[2][2];
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj)
-                if (jj == j) n = len[jj];
-            const int p = j >= 0 ? pos[j] : K;
-            const uint64_t *lp = lists + (int64_t)(tid + max(j, 0) * T) * K;
-            v[x][0] = (j >= 0 && p < n) ? lp[p] : KEY_INF;
-            v[x][1] = (j >= 0 && p + 1 < n) ? lp[p + 1] : KEY_INF;
-        }
+            for (int x = 0; x < 2; ++x) {
+                const int j = x == 0 ? sel0 : sel1;
+                int n = 0;
 #pragma unroll
-        for (int x = 0; x < 2; ++x) {
-            const int j = x == 0 ? sel0 : sel1;
-            if (j < 0) continue;
-            bool keep = true;
-#pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const uint64_t key = v[x][e];
-                if (keep && key != KEY_INF && key <= bound) {
-                    const int slot = atomicAdd(&ncol_s, 1);
-                    if (slot < region) keys[slot] = key;
-                } else {
-                    keep = false;
-                }
+                for (int jj = 0; jj < 4; ++jj)
+                    if (jj == j) n = len[jj];
+                const int p = j >= 0 ? pos[j] : K;
+                const uint64_t *lp = lists + (int64_t)(tid + max(j, 0) * T) * K;
+                v[x][0] = (j >= 0 && p < n) ? lp[p] : KEY_INF;
+                v[x][1] = (j >= 0 && p + 1 < n) ? lp[p + 1] : KEY_INF;
             }
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj)
-                if (jj == j) {
-                    pos[jj] += 2;
-                    live[jj] = keep && pos[jj] < len[jj];
-                }
-        }
-        bool any = false;
+            for (int x = 0; x < 2; ++x) {
+                const int j = x == 0 ? sel0 : sel1;
+                if (j < 0) continue;
+                bool keep = true;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) any = any || live[j];
-        if (!__syncthreads_or(any)) break;
+                for (int e = 0; e < 2; ++e) {
+                    const uint64_t key = v[x][e];
+                    if (keep && key != KEY_INF && key <= bound) {
+                        const int slot = atomicAdd(&ncol_s, 1);
+                        if (slot < region) keys[slot] = key;
+                    } else {
+                        keep = false;
+                    }
+                }
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+                    if (jj == j) {
+                        pos[jj] += 2;
+                        live[jj] = keep && pos[jj] < len[jj];
+                    }
+            }
+            bool any = false;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) any = any || live[j];
+            if (!__syncthreads_or(any)) break;
+        }
+        C = ncol_s;
+        if (C <= MERGE_RANK_MAX || m >= m_max || attempt > 0) break;
+        m = m_max;
+        __syncthreads();  // every thread has read the count before it is reset
     }
-    const int C = ncol_s;
     if (C <= MERGE_RANK_MAX) {
         // keys are distinct (each row has one), so a key's rank among the
         // collected ones is its place in the result
@@ -257,6 +274,8 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const uint64_t *__
     __syncthreads();
     TopkLds<uint64_t> tk{keys, cnt, thr, 1, K, Kp, CB};
     tk.init(tid, T);
+    int pos[4];
+    bool live[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         pos[j] = 0;
@@ -695,7 +714,7 @@ hipError_t launch_merge(const FinishArgs &a, hipStream_t s) {
     if (a.n_chunks <= G) {
         merge_kernel<<<dim3(1, a.B), MERGE_THREADS, lds, s>>>(a.partials, a.n_chunks, G, a.K, Kp,
                                                              CB, a.merged, 1, a.list_off, a.nlists,
-                                                             a.heads, a.merge_limit, a.fills);
+                                                             a.heads, a.merge_limit, a.fills, a.merge_one_head);
         return hipGetLastError();
     }
     // two levels: groups of G lists, then the group results
@@ -703,10 +722,10 @@ hipError_t launch_merge(const FinishArgs &a, hipStream_t s) {
     uint64_t *mid = a.merge_mid;
     merge_kernel<<<dim3(ng, a.B), MERGE_THREADS, lds, s>>>(a.partials, a.n_chunks, G, a.K, Kp, CB,
                                                           mid, ng, a.list_off, a.nlists, a.heads,
-                                                          a.merge_limit, a.fills);
+                                                          a.merge_limit, a.fills, a.merge_one_head);
     merge_kernel<<<dim3(1, a.B), MERGE_THREADS, lds, s>>>(mid, ng, ng, a.K, Kp, CB, a.merged, 1,
                                                          nullptr, nullptr, nullptr,
-                                                         a.merge_limit, nullptr);
+                                                         a.merge_limit, nullptr, a.merge_one_head);
     return hipGetLastError();
 }
 
