@@ -357,6 +357,19 @@ vrs_status vrs_batched_graph_create(vrs_table t, const float *q, int32_t B, cons
                                     const int32_t *ks, int32_t k_max, vrs_metric metric,
                                     int64_t *out_idx, float *out_dist, void *ws, size_t ws_bytes,
                                     const vrs_opts *opts, void *stream, vrs_graph *out);
+/* The launch sequence of vrs_scan_topk (Section 3, eq. 3; arguments as
+ * there) for these buffers (queries, outputs, workspace and the opts
+ * pointers) and this predicate, k and opts, with the access path the planner
+ * picks now, captured once into a graph that vrs_graph_launch replays: one
+ * launch instead of one per kernel, for callers that repeat a call (a
+ * serving loop over new query vectors written into q).  The caller may
+ * rewrite the buffers' contents between replays, not their addresses; the
+ * table must not change.  Creation runs the call once eagerly (its results
+ * land in the outputs) and synchronizes `stream`.  The buffers and the table
+ * must stay allocated while the graph exists.  vrs_graph_config returns -1. */
+vrs_status vrs_scan_graph_create(vrs_table t, const float *q, int32_t B, const vrs_pred *pred, int32_t k,
+                                 vrs_metric metric, int64_t *out_idx, float *out_dist, void *ws,
+                                 size_t ws_bytes, const vrs_opts *opts, void *stream, vrs_graph *out);
 /* Enqueue one replay on `stream` (asynchronous). */
 vrs_status vrs_graph_launch(vrs_graph g, void *stream);
 /* The configuration a graph was captured with. */

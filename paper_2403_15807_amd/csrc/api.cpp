@@ -741,6 +741,50 @@ vrs_status vrs_batched_graph_create(vrs_table t, const float *q, int32_t B, cons
     return ok();
 }
 
+vrs_status vrs_scan_graph_create(vrs_table t, const float *q, int32_t B, const vrs_pred *pred, int32_t k,
+                                 vrs_metric metric, int64_t *out_idx, float *out_dist, void *ws,
+                                 size_t ws_bytes, const vrs_opts *opts, void *stream, vrs_graph *out) {
+    if (!out) return fail(VRS_E_ARG, "out is NULL");
+    *out = nullptr;
+    // one eager run: checks the arguments, sets kernel attributes outside the
+    // capture, and leaves this call's results in the outputs
+    vrs_status st = scan_common(t, q, B, pred, nullptr, nullptr, k, metric, out_idx, out_dist, ws, ws_bytes,
+                                opts, stream);
+    if (st != VRS_OK) return st;
+    PredDev p;
+    st = fold_pred(pred, t->n_attr, &p);
+    if (st != VRS_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(VRS_E_HIP, "scan graph warm-up failed: %s", hipGetErrorString(e));
+    auto *g = new vrs_graph_s();
+    g->cfg = -1;
+    HIP_TRY(hipGetDevice(&g->device));
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+        prof_quiet(true);
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t er = run_scan(t, q, B, p, nullptr, nullptr, k, metric, out_idx, out_dist, ws, opts, cs);
+            e = hipStreamEndCapture(cs, &g->graph);
+            if (er != hipSuccess) e = er;
+        }
+        prof_quiet(false);
+        (void)hipStreamDestroy(cs);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return fail(VRS_E_HIP, "scan graph capture failed: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return ok();
+}
+
 vrs_status vrs_graph_launch(vrs_graph g, void *stream) {
     if (!g) return fail(VRS_E_ARG, "graph is NULL");
     HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));

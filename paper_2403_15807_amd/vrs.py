@@ -38,6 +38,7 @@ EXPORTS = [
     "vrs_range_workspace_bytes", "vrs_scan_range", "vrs_join_workspace_bytes", "vrs_join_topk",
     "vrs_index_build", "vrs_index_destroy", "vrs_index_info", "vrs_index_export", "vrs_probe_workspace_bytes",
     "vrs_probe_topk", "vrs_plan_access", "vrs_scan_topk_noalloc", "vrs_chooser_pick",
+    "vrs_scan_graph_create",
 ]
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 6, 64, 16, 5648
 NUM_STAGES = 6
@@ -114,6 +115,7 @@ def lib() -> C.CDLL:
             "vrs_batched_num_configs": [],
             "vrs_batched_tune": [P, P, I32, P, P, I32, I32, P, P, P, S, P, P, P, P],
             "vrs_batched_graph_create": [P, P, I32, P, P, I32, I32, P, P, P, S, P, P, P],
+            "vrs_scan_graph_create": [P, P, I32, P, I32, I32, P, P, P, S, P, P, P],
             "vrs_graph_launch": [P, P],
             "vrs_graph_config": [P],
             "vrs_graph_destroy": [P],
@@ -307,6 +309,30 @@ class Table:
                                    _ptr(ws), ws.numel(), C.byref(o), _stream(stream)))
         return ScanResult(idx, dist, nv, cert, er)
 
+    def scan_graph(self, q: torch.Tensor, terms, k: int, metric: int = L2SQ, strategy: int = STRATEGY_AUTO,
+                   tile: int = -1, chooser: int = CHOOSER_LEARNED, kprime_mult: int = 0,
+                   ws: torch.Tensor | None = None, out: tuple | None = None, stream=None,
+                   passes: int = 0) -> "BatchedGraph":
+        """Capture ``scan_topk`` for these buffers into a HIP graph
+        (``vrs_scan_graph_create``); ``launch()`` replays it.  Write new query
+        vectors into ``q`` between replays; the results land in ``result``."""
+        q = q.contiguous()
+        B = q.shape[0]
+        if out is None:
+            out = (torch.empty((B, k), dtype=torch.int64, device="cuda"),
+                   torch.empty((B, k), dtype=torch.float32, device="cuda"),
+                   torch.empty(B, dtype=torch.int32, device="cuda"),
+                   torch.empty(B, dtype=torch.uint8, device="cuda"))
+        idx, dist, nv, cert = out
+        o = self._opts(B, strategy, tile, chooser, kprime_mult, nv, cert, passes)
+        if ws is None:
+            ws = self.workspace(B, k, o)
+        p = make_pred(terms)
+        h = C.c_void_p()
+        _check(lib().vrs_scan_graph_create(self._h, _ptr(q), B, C.byref(p), k, metric, _ptr(idx), _ptr(dist),
+                                           _ptr(ws), ws.numel(), C.byref(o), _stream(stream), C.byref(h)))
+        return BatchedGraph(h, (q, ws, self, o), ScanResult(idx, dist, nv, cert))
+
     def range_workspace_bytes(self, B: int, cap: int) -> int:
         out = C.c_size_t()
         _check(lib().vrs_range_workspace_bytes(self._h, B, cap, C.byref(out)))
@@ -488,8 +514,9 @@ class Index:
 
 
 class BatchedGraph:
-    """A captured batched launch; ``launch()`` replays it on a stream.  The
-    buffers it was captured with are kept alive here."""
+    """A captured launch sequence (batched form or single-predicate scan);
+    ``launch()`` replays it on a stream.  The buffers it was captured with
+    are kept alive here."""
 
     def __init__(self, h, keep, result: ScanResult):
         self._h = h
