@@ -82,18 +82,43 @@ __global__ __launch_bounds__(256) void range_screen_kernel(RangeArgs a) {
     const int nblk = (int)(row_bytes / 128);
     const char *base = (const char *)a.rows;
     const uint64_t lt = (1ull << lane) - 1ull;
+    // the next step's rows (gather: their ids; mask: their predicate
+    // columns) are fetched while this step's rows are loaded and multiplied
+    int64_t prow[U];
+    bool pin[U];
+    int32_t pav[U][4];
+    auto fetch = [&](int64_t t) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t pos = t + u * 32 + wave * 8 + r;
+            pin[u] = pos < c1;
+            prow[u] = GATHER ? (pin[u] ? (int64_t)a.sel_ids[pos] : 0) : (pin[u] ? pos : 0);
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt)
+                pav[u][tt] = (!GATHER && pin[u] && tt < a.pred.nterms)
+                                 ? a.attr[(int64_t)a.pred.col[tt] * a.an + prow[u]]
+                                 : 0;
+        }
+    };
+    fetch(c0);
     for (int64_t t0 = c0; t0 < c1; t0 += STEP) {
         int64_t row[U];
         bool ok[U];
         bool any = false;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t pos = t0 + u * 32 + wave * 8 + r;
-            ok[u] = pos < c1;
-            row[u] = GATHER ? (ok[u] ? (int64_t)a.sel_ids[pos] : 0) : (ok[u] ? pos : 0);
-            if (!GATHER && ok[u]) ok[u] = pred_eval(a.pred, a.attr, a.an, row[u]);
-            any = any || ok[u];
+            row[u] = prow[u];
+            bool q = pin[u];
+            if (!GATHER) {
+                q = q && a.pred.nterms >= 0;
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+                    if (tt < a.pred.nterms) q = q && pav[u][tt] >= a.pred.lo[tt] && pav[u][tt] <= a.pred.hi[tt];
+            }
+            ok[u] = q;
+            any = any || q;
         }
+        if (t0 + STEP < c1) fetch(t0 + STEP);
         if (__ballot(any) == 0) continue;  // (wave-uniform)
         float acc[U][QT];
 #pragma unroll
@@ -106,8 +131,14 @@ __global__ __launch_bounds__(256) void range_screen_kernel(RangeArgs a) {
             for (int u = 0; u < U; ++u)
 #pragma unroll
                 for (int k = 0; k < NB; ++k)
-                    if (blk + k < nblk)
-                        w[u][k] = *(const uint4 *)(base + row[u] * row_bytes + (int64_t)(blk + k) * 128 + sl * 16);
+                    if (blk + k < nblk) {  // (non-temporal: each row is read once;
+                        w[u][k] = make_uint4(0u, 0u, 0u, 0u);  //  rows the predicate drops are not read)
+                        if (ok[u]) {
+                            const x64_u32x4 v = __builtin_nontemporal_load(
+                                (const x64_u32x4 *)(base + row[u] * row_bytes + (int64_t)(blk + k) * 128 + sl * 16));
+                            w[u][k] = make_uint4(v.x, v.y, v.z, v.w);
+                        }
+                    }
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
                 if (blk + k >= nblk) break;
