@@ -44,8 +44,8 @@ struct BPlan {
     int64_t dense_lists, lists;
     int fb_chunks, fb_rows_per_chunk;
     bool two_pass;  // dense side in two passes (prefix of every chunk, merged bound, all rows)
-    size_t o_qp, o_qnorm, o_qn2, o_qhl, o_gthr, o_ctl, o_pred_o, o_pred_p, o_qr, o_cands, o_sq, o_kc_o, o_kps_o, o_kc_p,
-        o_kps_p, o_cand, o_subcnt, o_tot, o_perm, o_spoff, o_spcnt, o_segpre, o_listoff, o_nlists,
+    size_t o_qp, o_qnorm, o_qn2, o_qhl, o_gthr, o_ctl, o_pred_o, o_pred_p, o_qr, o_cands, o_kc_o, o_kps_o, o_kc_p,
+        o_kps_p, o_cand, o_tot, o_perm, o_spoff, o_spcnt, o_segpre, o_listoff, o_nlists,
         o_pool, o_part, o_cbuf, o_merged, o_rrdist, o_fail, o_failcnt, o_fb, total;
 };
 
@@ -91,13 +91,11 @@ BPlan make_bplan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, in
     P.o_pred_p = take((size_t)B * sizeof(PredDev));
     P.o_qr = take((size_t)B * sizeof(QRange));
     P.o_cands = take((size_t)B * sizeof(QRange));
-    P.o_sq = take((size_t)B * sizeof(QRange));
     P.o_kc_o = take((size_t)B * 4);
     P.o_kps_o = take((size_t)B * 4);
     P.o_kc_p = take((size_t)B * 4);
     P.o_kps_p = take((size_t)B * 4);
     P.o_cand = take((size_t)B);
-    P.o_subcnt = take(P.rows_cap > 0 ? (size_t)P.nsub * B * 4 : 0);
     P.o_tot = take((size_t)B * 4);
     P.o_perm = take((size_t)B * 4);
     P.o_spoff = take((size_t)B * 8);
@@ -189,11 +187,9 @@ hipError_t run_batched(const vrs_table_s *t, const float *q, int B, const vrs_pr
     ba.pred_o = (PredDev *)(w + P.o_pred_o);
     ba.qr = (QRange *)(w + P.o_qr);
     ba.cands = (QRange *)(w + P.o_cands);
-    ba.sq = (QRange *)(w + P.o_sq);
     ba.kc_o = (int32_t *)(w + P.o_kc_o);
     ba.kps_o = (int32_t *)(w + P.o_kps_o);
     ba.cand = (uint8_t *)(w + P.o_cand);
-    ba.subcnt = (uint32_t *)(w + P.o_subcnt);
     ba.tot = (int32_t *)(w + P.o_tot);
     ba.perm = (int32_t *)(w + P.o_perm);
     ba.sp_off = (int64_t *)(w + P.o_spoff);
@@ -213,7 +209,7 @@ hipError_t run_batched(const vrs_table_s *t, const float *q, int B, const vrs_pr
     PredDev *pred_p = (PredDev *)(w + P.o_pred_p);
     int32_t *kc_p = (int32_t *)(w + P.o_kc_p), *kps_p = (int32_t *)(w + P.o_kps_p);
 
-    // predicate passes: split, order, selection vectors of the sparse queries
+    // predicate passes: selection vectors of the candidates, split, order
     prof_begin(1, s);
     hipError_t e = launch_batch_classify(ba, s);
     if (e != hipSuccess) return e;
@@ -223,10 +219,6 @@ hipError_t run_batched(const vrs_table_s *t, const float *q, int B, const vrs_pr
                              qhl, gthr, fail_count, pred_p, kc_p, kps_p, s);
     if (e != hipSuccess) return e;
     prof_end(0, s);
-    prof_begin(1, s);
-    e = launch_batch_lists(ba, s);
-    if (e != hipSuccess) return e;
-    prof_end(1, s);
 
     ScreenArgs sa{};
     sa.rows = t->rows;

@@ -187,7 +187,6 @@ struct QRange {
     int32_t kind;
     int32_t lo0, lo1;
     uint32_t span0, span1;
-    int64_t off;                   // write pass: first slot of the query's selection vector
 };
 hipError_t launch_screen_stream(const ScreenArgs &a, int qt, hipStream_t s);
 size_t screen_stream_lds(int qt, int Kp, int CB, int dp);
@@ -239,7 +238,6 @@ __device__ inline QRange range_form(int b, const PredDev &o) {
     QRange r;
     r.b = b;
     r.kind = 0;
-    r.off = 0;
     int32_t lo[2] = {INT32_MIN, INT32_MIN}, hi[2] = {INT32_MAX, INT32_MAX};
     bool none = o.nterms < 0;
     for (int t = 0; t < 4; ++t) {
@@ -289,22 +287,19 @@ struct BatchArgs {
     PredDev *pred_o;               // [B] folded predicates, by query
     QRange *qr;                    // [B] range form, by query
     QRange *cands;                 // [B] range form of the sparse candidates (any order)
-    QRange *sq;                    // [B] range form of the sparse queries, by sparse index
     int32_t *kc_o, *kps_o;         // [B] clamped k and k', by query
     uint8_t *cand;                 // [B] sparse candidate by the estimate
-    uint32_t *subcnt;              // [nsub][B] qualifying rows per sub-block, then prefix
-    int32_t *tot;                  // [B] qualifying rows (-1: not counted)
+    int32_t *tot;                  // [B] qualifying rows (-1: not a candidate)
     int32_t *perm;                 // [B] position -> query
     int64_t *sp_off;               // [B] by position
     int32_t *sp_cnt;               // [B] by position
     int32_t *seg_pre;              // [B + 1]
     int64_t *list_off;             // [B] by position: first list in the partials
     int32_t *nlists;               // [B] by position: lists in the partials
-    int32_t *pool;                 // sparse id lists
+    int32_t *pool;                 // [B][rows_cap] sparse id lists, one region per query
     int32_t *ctl;                  // BatchCtl words
 };
 hipError_t launch_batch_classify(const BatchArgs &b, hipStream_t s);
-hipError_t launch_batch_lists(const BatchArgs &b, hipStream_t s);
 hipError_t launch_screen_sparse(const ScreenArgs &a, int grid, hipStream_t s);
 size_t screen_sparse_lds(int K, int dp);
 

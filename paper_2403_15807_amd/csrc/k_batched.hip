@@ -13,16 +13,19 @@
 //   * sparse queries (few qualifying rows) get their own selection vector
 //     and a gather-then-compute VALU pass over exactly those rows.
 // The split is decided on the device: a histogram estimate proposes the
-// sparse candidates, an exact count confirms them (a query whose count
+// sparse candidates, one selection pass writes every candidate's qualifying
+// row ids (up to the cap) and counts them exactly (a query whose count
 // exceeds the cap goes dense), and the queries are permuted so that the
 // dense ones occupy positions [0, n_dense).
 //
-// Passes over the attribute columns are organised by 1024-row sub-blocks;
-// the queries of a sub-block are split over 8 waves, each of which keeps
-// its rows' values of the first two columns in registers and walks its
-// share of the queries, so the columns are read a few times per pass
-// however many queries there are; qualifying rows are found 64 at a time
-// with one ballot per row group.
+// The selection pass is organised by 1024-row sub-blocks; the candidates
+// are split over 8 waves per sub-block, each of which keeps its rows'
+// values of the first two columns in registers and walks its share of the
+// candidates, so the columns are read a few times however many queries
+// there are; qualifying rows are found 64 at a time with one ballot per row
+// group and term.  A candidate's list is its own region of the pool, filled
+// in sub-block runs (ascending within a run, runs in the order their waves
+// reserve them): the gather screening does not depend on the order.
 #include "internal.h"
 
 namespace vrs {
@@ -96,7 +99,7 @@ __global__ __launch_bounds__(256) void batch_prepare_kernel(BatchArgs a) {
             cand = est_fraction(a.dstats, a.n_attr, o) * (double)a.n <= 4.0 * (double)a.rows_cap + 1024.0;
     }
     a.cand[b] = cand;
-    a.tot[b] = -1;
+    a.tot[b] = cand ? 0 : -1;  // (candidates: the selection pass adds its counts)
     if (cand) a.cands[atomicAdd(&a.ctl[BC_NCAND], 1)] = r;
 }
 
@@ -118,9 +121,8 @@ __device__ __forceinline__ void load_sub(const BatchArgs &a, int64_t row0, int l
 // Lane mask of the qualifying rows of 64-row group g; `valid` is the mask
 // of rows inside the table.
 __device__ __forceinline__ uint64_t range_mask(const QRange &r, int32_t v0, int32_t v1) {
-    const bool q0 = (uint32_t)(v0 - r.lo0) <= r.span0;
-    const bool q1 = (uint32_t)(v1 - r.lo1) <= r.span1;
-    return __ballot(q0 & q1);
+    // (one ballot per term: each compare writes its lane mask directly)
+    return __ballot((uint32_t)(v0 - r.lo0) <= r.span0) & __ballot((uint32_t)(v1 - r.lo1) <= r.span1);
 }
 
 __device__ __forceinline__ uint64_t general_mask(const BatchArgs &a, const QRange &r, int32_t v0,
@@ -153,36 +155,75 @@ __device__ __forceinline__ QRange range_of_lane(const QRange &mine, int t) {
     r.lo1 = __builtin_amdgcn_readlane(mine.lo1, t);
     r.span0 = (uint32_t)__builtin_amdgcn_readlane((int)mine.span0, t);
     r.span1 = (uint32_t)__builtin_amdgcn_readlane((int)mine.span1, t);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine.off, t);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mine.off >> 32), t);
-    r.off = (int64_t)(((uint64_t)hi << 32) | lo);
     return r;
 }
 
+// Rows of the sub-block that satisfy query r (the kind test is taken once,
+// so the 16 row groups of the range form are independent instructions).
 template <bool FULL>
-__device__ __forceinline__ void count_sub(const BatchArgs &a, int sub, int part, int lane, int64_t row0,
-                                          const int32_t (&v0)[GROUPS], const int32_t (&v1)[GROUPS]) {
+__device__ __forceinline__ uint32_t count_query(const BatchArgs &a, const QRange &r, int64_t row0, int lane,
+                                                const int32_t (&v0)[GROUPS], const int32_t (&v1)[GROUPS]) {
+    uint32_t c = 0;
+    if (r.kind == 0) {
+#pragma unroll
+        for (int g = 0; g < GROUPS; ++g) {
+            uint64_t m = range_mask(r, v0[g], v1[g]);
+            if (!FULL) {
+                const int64_t in = a.n - row0 - g * 64;
+                if (in < 64) m &= in <= 0 ? 0ull : ((1ull << in) - 1ull);
+            }
+            c += (uint32_t)__popcll(m);
+        }
+    } else if (r.kind == 1) {
+#pragma unroll
+        for (int g = 0; g < GROUPS; ++g) c += (uint32_t)__popcll(group_mask<FULL>(a, r, v0[g], v1[g], row0, g, lane));
+    }
+    return c;
+}
+
+// The selection pass of one wave: its share of the candidates against its
+// sub-block, 64 candidates at a time: the count of each (lane t keeps
+// candidate t's), one atomic per candidate with rows here for the first of
+// its slots (the atomic also makes tot[b] the candidate's exact count once
+// every sub-block has added its own), then the ids, slots past the cap
+// dropped.
+template <bool FULL>
+__device__ __forceinline__ void select_sub(const BatchArgs &a, int part, int lane, int64_t row0,
+                                           const int32_t (&v0)[GROUPS], const int32_t (&v1)[GROUPS]) {
+    const uint64_t below = (1ull << lane) - 1ull;
     const int nc = a.ctl[BC_NCAND];
     const int j0 = (int)((int64_t)nc * part / QSPLIT), j1 = (int)((int64_t)nc * (part + 1) / QSPLIT);
     for (int jb = j0; jb < j1; jb += 64) {
-        const QRange mine = jb + lane < j1 ? a.cands[jb + lane] : QRange{0, 2, 0, 0, 0u, 0u, 0};
+        const QRange mine = jb + lane < j1 ? a.cands[jb + lane] : QRange{0, 2, 0, 0, 0u, 0u};
         const int m = min(64, j1 - jb);
+        uint32_t myc = 0;
         for (int t = 0; t < m; ++t) {
+            const uint32_t c = count_query<FULL>(a, range_of_lane(mine, t), row0, lane, v0, v1);
+            myc = lane == t ? c : myc;
+        }
+        uint32_t base = 0;
+        if (myc > 0) base = (uint32_t)atomicAdd(&a.tot[mine.b], (int32_t)myc);
+        uint64_t todo = __ballot(myc > 0);
+        while (todo) {
+            const int t = __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
             const QRange r = range_of_lane(mine, t);
-            uint32_t c = 0;
-            if (r.kind != 2) {
+            uint32_t pos = (uint32_t)__builtin_amdgcn_readlane((int)base, t);
+            int32_t *dst = a.pool + (int64_t)r.b * a.rows_cap;
 #pragma unroll
-                for (int g = 0; g < GROUPS; ++g)
-                    c += (uint32_t)__popcll(group_mask<FULL>(a, r, v0[g], v1[g], row0, g, lane));
+            for (int g = 0; g < GROUPS; ++g) {
+                const uint64_t mk = group_mask<FULL>(a, r, v0[g], v1[g], row0, g, lane);
+                const uint32_t p = pos + (uint32_t)__popcll(mk & below);
+                if (((mk >> lane) & 1ull) && p < (uint32_t)a.rows_cap) dst[p] = (int32_t)(row0 + g * 64 + lane);
+                pos += (uint32_t)__popcll(mk);
             }
-            if (lane == 0) a.subcnt[(int64_t)sub * a.B + r.b] = c;
         }
     }
 }
 
-// Qualifying rows of every sparse candidate in every sub-block: wave
-// (sub-block, part) counts part `part` of the candidate list.
-__global__ __launch_bounds__(256, 3) void batch_count_kernel(BatchArgs a) {
+// Selection pass: wave (sub-block, part) takes part `part` of the candidate
+// list.
+__global__ __launch_bounds__(256, 3) void batch_select_kernel(BatchArgs a) {
     const int lane = threadIdx.x & 63;
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int sub = w / QSPLIT, part = w % QSPLIT;
@@ -191,46 +232,9 @@ __global__ __launch_bounds__(256, 3) void batch_count_kernel(BatchArgs a) {
     int32_t v0[GROUPS], v1[GROUPS];
     load_sub(a, row0, lane, v0, v1);
     if (row0 + BSUB_ROWS <= a.n)
-        count_sub<true>(a, sub, part, lane, row0, v0, v1);
+        select_sub<true>(a, part, lane, row0, v0, v1);
     else
-        count_sub<false>(a, sub, part, lane, row0, v0, v1);
-}
-
-// Per candidate: total count, and the sub-block counts turned into
-// exclusive prefix sums (each sub-block's first slot in the query's list).
-// Workgroup = 64 consecutive queries (one per lane, so every access is a
-// coalesced row of the [sub-block][query] array) x 16 waves, wave w taking
-// the w-th sixteenth of the sub-blocks: a pass of sums, a prefix across the
-// waves in LDS, then a pass writing the prefixes.
-constexpr int TOT_WAVES = 16;
-__global__ __launch_bounds__(64 * TOT_WAVES) void batch_total_kernel(BatchArgs a) {
-    __shared__ uint32_t part[TOT_WAVES][64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int b = blockIdx.x * 64 + lane;
-    const bool act = b < a.B && a.cand[b];
-    const int per = (a.nsub + TOT_WAVES - 1) / TOT_WAVES;
-    const int s0 = wave * per, s1 = min(a.nsub, s0 + per);
-    uint32_t sum = 0;
-    if (act)
-        for (int sub = s0; sub < s1; ++sub) sum += a.subcnt[(int64_t)sub * a.B + b];
-    part[wave][lane] = sum;
-    __syncthreads();
-    uint32_t run = 0;
-    for (int w = 0; w < wave; ++w) run += part[w][lane];
-    if (act) {
-        constexpr int G = 16;  // reads issued before the writes that follow them
-        for (int sub = s0; sub < s1; sub += G) {
-            uint32_t c[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) c[g] = sub + g < s1 ? a.subcnt[(int64_t)(sub + g) * a.B + b] : 0u;
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                if (sub + g < s1) a.subcnt[(int64_t)(sub + g) * a.B + b] = run;
-                run += c[g];
-            }
-        }
-        if (wave == TOT_WAVES - 1) a.tot[b] = (int32_t)run;
-    }
+        select_sub<false>(a, part, lane, row0, v0, v1);
 }
 
 // Exclusive prefix sum over the 1024 threads of the block; returns the total.
@@ -261,7 +265,6 @@ __device__ T block_scan_1024(T v, T &excl, T *wsum /* [16] LDS */) {
 // order), list layout, sparse list offsets and work-item prefix sums.
 __global__ __launch_bounds__(1024) void batch_order_kernel(BatchArgs a) {
     __shared__ int32_t ws32[16];
-    __shared__ long long ws64[16];
     const int tid = threadIdx.x;
     auto is_sparse = [&](int b) { return a.cand[b] && a.tot[b] >= 0 && (int64_t)a.tot[b] <= a.rows_cap; };
     int32_t ns = 0;
@@ -276,7 +279,6 @@ __global__ __launch_bounds__(1024) void batch_order_kernel(BatchArgs a) {
     nc = nc / 8 * 8;
     nc = max(8, min(a.nc_cap, nc));
     int32_t run_d = 0, run_s = 0, run_seg = 0;
-    long long run_off = 0;
     for (int c0 = 0; c0 < a.B; c0 += 1024) {
         const int b = c0 + tid;
         const bool in = b < a.B;
@@ -284,11 +286,9 @@ __global__ __launch_bounds__(1024) void batch_order_kernel(BatchArgs a) {
         const int32_t cnt = sp ? a.tot[b] : 0;
         const int32_t segs = cnt == 0 ? 0 : min(a.seg_max, (cnt + a.seg_rows - 1) / a.seg_rows);
         int32_t rd, rs, rseg;
-        long long roff;
         const int32_t td = block_scan_1024<int32_t>(in && !sp ? 1 : 0, rd, ws32);
         const int32_t ts = block_scan_1024<int32_t>(sp ? 1 : 0, rs, ws32);
         const int32_t tseg = block_scan_1024<int32_t>(segs, rseg, ws32);
-        const long long toff = block_scan_1024<long long>((long long)cnt, roff, ws64);
         if (in) {
             if (!sp) {
                 const int pos = run_d + rd;
@@ -300,10 +300,7 @@ __global__ __launch_bounds__(1024) void batch_order_kernel(BatchArgs a) {
             } else {
                 const int j = run_s + rs, pos = nd + j;
                 a.perm[pos] = b;
-                a.sp_off[pos] = run_off + roff;
-                QRange r = a.qr[b];
-                r.off = run_off + roff;
-                a.sq[j] = r;
+                a.sp_off[pos] = (int64_t)b * a.rows_cap;  // (the query's own pool region)
                 a.sp_cnt[pos] = cnt;
                 a.seg_pre[j] = run_seg + rseg;
                 a.list_off[pos] = (int64_t)nd * nc + run_seg + rseg;
@@ -313,7 +310,6 @@ __global__ __launch_bounds__(1024) void batch_order_kernel(BatchArgs a) {
         run_d += td;
         run_s += ts;
         run_seg += tseg;
-        run_off += toff;
     }
     if (tid == 0) {
         a.seg_pre[ns] = run_seg;
@@ -321,49 +317,6 @@ __global__ __launch_bounds__(1024) void batch_order_kernel(BatchArgs a) {
         a.ctl[BC_NSPARSE] = ns;
         a.ctl[BC_NC] = nc;
     }
-}
-
-template <bool FULL>
-__device__ __forceinline__ void write_sub(const BatchArgs &a, int sub, int part, int lane, int64_t row0,
-                                          const int32_t (&v0)[GROUPS], const int32_t (&v1)[GROUPS]) {
-    const uint64_t below = (1ull << lane) - 1ull;
-    const int ns = a.ctl[BC_NSPARSE];
-    const int j0 = (int)((int64_t)ns * part / QSPLIT), j1 = (int)((int64_t)ns * (part + 1) / QSPLIT);
-    for (int jb = j0; jb < j1; jb += 64) {
-        // 64 queries' ranges and first slots in this sub-block, one per lane
-        const bool has = jb + lane < j1;
-        const QRange mine = has ? a.sq[jb + lane] : QRange{0, 2, 0, 0, 0u, 0u, 0};
-        const uint32_t mypre = has ? a.subcnt[(int64_t)sub * a.B + mine.b] : 0u;
-        const int m = min(64, j1 - jb);
-        for (int t = 0; t < m; ++t) {
-            const QRange r = range_of_lane(mine, t);
-            if (r.kind == 2) continue;
-            const uint32_t pre = (uint32_t)__builtin_amdgcn_readlane((int)mypre, t);
-            int32_t *dst = a.pool + r.off + pre;
-#pragma unroll
-            for (int g = 0; g < GROUPS; ++g) {
-                const uint64_t mk = group_mask<FULL>(a, r, v0[g], v1[g], row0, g, lane);
-                if ((mk >> lane) & 1ull) dst[__popcll(mk & below)] = (int32_t)(row0 + g * 64 + lane);
-                dst += __popcll(mk);
-            }
-        }
-    }
-}
-
-// Selection vectors of the sparse queries: ascending row ids per query;
-// wave (sub-block, part) writes part `part` of the sparse queries.
-__global__ __launch_bounds__(256, 3) void batch_write_kernel(BatchArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int sub = w / QSPLIT, part = w % QSPLIT;
-    if (sub >= a.nsub || a.n_attr == 0 || a.ctl[BC_NSPARSE] == 0) return;
-    const int64_t row0 = (int64_t)sub * BSUB_ROWS;
-    int32_t v0[GROUPS], v1[GROUPS];
-    load_sub(a, row0, lane, v0, v1);
-    if (row0 + BSUB_ROWS <= a.n)
-        write_sub<true>(a, sub, part, lane, row0, v0, v1);
-    else
-        write_sub<false>(a, sub, part, lane, row0, v0, v1);
 }
 
 // ------------------------------------------------- sparse gather screening
@@ -507,16 +460,8 @@ __global__ __launch_bounds__(256) void screen_sparse_kernel(ScreenArgs a) {
 hipError_t launch_batch_classify(const BatchArgs &b, hipStream_t s) {
     batch_reset_kernel<<<1, 64, 0, s>>>(b.ctl);
     batch_prepare_kernel<<<(b.B + 255) / 256, 256, 0, s>>>(b);
-    if (b.rows_cap > 0) {
-        batch_count_kernel<<<(b.nsub * QSPLIT + 3) / 4, 256, 0, s>>>(b);
-        batch_total_kernel<<<(b.B + 63) / 64, 64 * TOT_WAVES, 0, s>>>(b);
-    }
+    if (b.rows_cap > 0) batch_select_kernel<<<(b.nsub * QSPLIT + 3) / 4, 256, 0, s>>>(b);
     batch_order_kernel<<<1, 1024, 0, s>>>(b);
-    return hipGetLastError();
-}
-
-hipError_t launch_batch_lists(const BatchArgs &b, hipStream_t s) {
-    if (b.rows_cap > 0) batch_write_kernel<<<(b.nsub * QSPLIT + 3) / 4, 256, 0, s>>>(b);
     return hipGetLastError();
 }
 
