@@ -424,6 +424,8 @@ struct ProbeArgs {
     int32_t B, k;
     const void *cent_rows;         // centroid table rows [nlist][cdp] float32
     int32_t cdp, nlist;
+    void *ckeys;                   // [B][next_pow2(nlist)] (distance, centroid) keys of the
+                                   // coarse scan (nlist <= PROBE_SORT_MAX), or null
     int64_t *coarse_out;           // [B][walk] partitions in centroid order (-1 pads)
     const int64_t *coarse;         // (the same array, read by the walk)
     int32_t walk;                  // partitions ordered per query: min(nlist, 256)

@@ -213,6 +213,7 @@ __device__ __forceinline__ void select_sub(const BatchArgs &a, int part, int lan
 #pragma unroll
             for (int g = 0; g < GROUPS; ++g) {
                 const uint64_t mk = group_mask<FULL>(a, r, v0[g], v1[g], row0, g, lane);
+                if (mk == 0) continue;  // (uniform: most groups of a selective query are empty)
                 const uint32_t p = pos + (uint32_t)__popcll(mk & below);
                 if (((mk >> lane) & 1ull) && p < (uint32_t)a.rows_cap) dst[p] = (int32_t)(row0 + g * 64 + lane);
                 pos += (uint32_t)__popcll(mk);

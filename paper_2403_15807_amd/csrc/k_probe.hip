@@ -124,12 +124,111 @@ __global__ __launch_bounds__(256) void centroid_mean_kernel(const float *__restr
     }
 }
 
-// Workgroup b: the exact FP64 squared-L2 distance of query b to every
-// centroid (64 centroids per wave, one per lane), and the `walk` smallest by
-// (distance, centroid id), in order, into coarse[b].  Up to PROBE_SORT_MAX
-// centroids the keys of all of them are sorted at once in LDS; beyond, a
-// running top-`walk` list keeps the smallest.
-template <bool ALL>
+// Workgroup (x, b): the exact FP64 squared distances of query b to
+// centroids [256 x, 256 x + 256) (64 per wave, one per lane) as (distance,
+// centroid id) keys: with at most PROBE_SORT_MAX centroids the coarse scan is
+// spread over ceil(nlist / 256) workgroups per query, so every query's
+// centroid rows are read at once rather than 256 at a time by one
+// workgroup.
+__global__ __launch_bounds__(256) void probe_cdist_kernel(ProbeArgs a) {
+    const int b = blockIdx.y, tid = threadIdx.x, wave = tid >> 6;
+    extern __shared__ __align__(16) unsigned char smem[];
+    x64_u32x4 *stage = (x64_u32x4 *)(smem + (size_t)wave * X64_WAVE_LDS);
+    double *qd = (double *)(smem + 4 * X64_WAVE_LDS);
+    for (int j = tid; j < a.cdp; j += 256) qd[j] = j < a.d ? (double)a.q[(int64_t)b * a.d + j] : 0.0;
+    __syncthreads();
+    const int c = blockIdx.x * 256 + tid;
+    const bool has = c < a.nlist;
+    if (__ballot(has) == 0) return;  // (wave-uniform; no barrier follows)
+    const double dv = exact64_wave<VRS_F32, VRS_L2SQ>(a.cent_rows, nullptr, has ? c : 0, has, qd, a.cdp, stage);
+    if (has) ((Key128 *)a.ckeys)[(int64_t)b * next_pow2(a.nlist) + c] = Key128{ord64(dv), (uint64_t)c};
+}
+
+// Compare-exchange: afterwards x <= y if up, y <= x otherwise.
+__device__ __forceinline__ void key_ce(Key128 &x, Key128 &y, bool up) {
+    const bool sw = up ? KeyOps<Key128>::less(y, x) : KeyOps<Key128>::less(x, y);
+    if (sw) {
+        const Key128 t = x;
+        x = y;
+        y = t;
+    }
+}
+
+// Ascending bitonic sort of 256 R keys held by the 256 threads of a
+// workgroup, thread t holding positions R t .. R t + R - 1 in k[] (on entry
+// and on exit).  Pairs at a distance below R are in one thread, below 64 R
+// in one wave (exchanged by shuffles); only the larger distances go through
+// LDS (lds: 256 R keys) with workgroup barriers.
+template <int R>
+__device__ void block_sort_keys(Key128 (&k)[R], Key128 *lds) {
+    const int tid = threadIdx.x;
+    constexpr int P = 256 * R;
+#pragma unroll
+    for (int size = 2; size <= P; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride < R) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (!(r & stride)) key_ce(k[r], k[r | stride], ((R * tid + r) & size) == 0);
+                continue;
+            }
+            if (stride >= 64 * R) {
+                __syncthreads();  // (the previous stage's readers are done)
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[R * tid + r] = k[r];
+                __syncthreads();
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = R * tid + r;
+                Key128 y;
+                if (stride >= 64 * R) {
+                    y = lds[i ^ stride];
+                } else {
+                    y.hi = __shfl_xor(k[r].hi, stride / R);
+                    y.lo = __shfl_xor(k[r].lo, stride / R);
+                }
+                // the lower position of an ascending pair (or the upper one
+                // of a descending pair) keeps the smaller key
+                const bool keep_min = ((i & stride) == 0) == ((i & size) == 0);
+                const bool y_less = KeyOps<Key128>::less(y, k[r]);
+                if (keep_min ? y_less : !y_less) k[r] = y;
+            }
+        }
+    }
+}
+
+// Workgroup b: the `walk` centroids nearest to query b, in order of
+// (distance, centroid id), into coarse[b], from the keys of every centroid
+// (probe_cdist_kernel; at most PROBE_SORT_MAX of them, padded with
+// KEY_INF keys to 256 R).
+template <int R>
+__global__ __launch_bounds__(256) void probe_sort_kernel(ProbeArgs a) {
+    const int b = blockIdx.x, tid = threadIdx.x;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int P = next_pow2(a.nlist);
+    const Key128 *ck = (const Key128 *)a.ckeys + (int64_t)b * P;
+    Key128 k[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int c = R * tid + r;
+        k[r] = c < a.nlist ? ck[c] : Key128{KEY_INF, KEY_INF};
+    }
+    block_sort_keys<R>(k, (Key128 *)smem);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = R * tid + r;
+        if (i < a.walk)
+            a.coarse_out[(int64_t)b * a.walk + i] =
+                (k[r].hi == KEY_INF && k[r].lo == KEY_INF) ? -1 : (int64_t)k[r].lo;
+    }
+}
+
+// Workgroup b, more than PROBE_SORT_MAX centroids: the exact FP64
+// squared-L2 distance of query b to every centroid (64 centroids per wave,
+// one per lane) into a running top-`walk` list, and the `walk` nearest by
+// (distance, centroid id), in order, into coarse[b].
 __global__ __launch_bounds__(256) void probe_coarse_kernel(ProbeArgs a) {
     const int b = blockIdx.x, tid = threadIdx.x, wave = tid >> 6;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -137,41 +236,24 @@ __global__ __launch_bounds__(256) void probe_coarse_kernel(ProbeArgs a) {
     double *qd = (double *)(smem + 4 * X64_WAVE_LDS);
     Key128 *keys = (Key128 *)(qd + a.cdp);
     for (int j = tid; j < a.cdp; j += 256) qd[j] = j < a.d ? (double)a.q[(int64_t)b * a.d + j] : 0.0;
-    if (ALL) {
-        const int P = next_pow2(a.nlist);
-        for (int c = a.nlist + tid; c < P; c += 256) keys[c] = Key128{KEY_INF, KEY_INF};
-        __syncthreads();
-        for (int c0 = 0; c0 < a.nlist; c0 += 256) {
-            const int c = c0 + tid;
-            const bool has = c < a.nlist;
-            if (__ballot(has) != 0) {  // (wave-uniform)
-                const double dv = exact64_wave<VRS_F32, VRS_L2SQ>(a.cent_rows, nullptr, has ? c : 0, has, qd,
-                                                                  a.cdp, stage);
-                if (has) keys[c] = Key128{ord64(dv), (uint64_t)c};
-            }
+    const int Kp = next_pow2(a.walk);
+    const int M = next_pow2(Kp + 256);
+    Key128 *thr = keys + M;
+    int *cnt = (int *)(thr + 1);
+    TopkLds<Key128> tk{keys, cnt, thr, 1, a.walk, Kp, M - Kp};
+    tk.init(tid, 256);  // (includes a barrier)
+    for (int c0 = 0; c0 < a.nlist; c0 += 256) {
+        const int c = c0 + tid;
+        const bool has = c < a.nlist;
+        if (__ballot(has) != 0) {  // (wave-uniform)
+            const double dv = exact64_wave<VRS_F32, VRS_L2SQ>(a.cent_rows, nullptr, has ? c : 0, has, qd,
+                                                              a.cdp, stage);
+            if (has) tk.push(0, Key128{ord64(dv), (uint64_t)c});
         }
         __syncthreads();
-        lds_bitonic_sort<Key128>(keys, 1, P, tid, 256);  // (ends with a barrier)
-    } else {
-        const int Kp = next_pow2(a.walk);
-        const int M = next_pow2(Kp + 256);
-        Key128 *thr = keys + M;
-        int *cnt = (int *)(thr + 1);
-        TopkLds<Key128> tk{keys, cnt, thr, 1, a.walk, Kp, M - Kp};
-        tk.init(tid, 256);  // (includes a barrier)
-        for (int c0 = 0; c0 < a.nlist; c0 += 256) {
-            const int c = c0 + tid;
-            const bool has = c < a.nlist;
-            if (__ballot(has) != 0) {  // (wave-uniform)
-                const double dv = exact64_wave<VRS_F32, VRS_L2SQ>(a.cent_rows, nullptr, has ? c : 0, has, qd,
-                                                                  a.cdp, stage);
-                if (has) tk.push(0, Key128{ord64(dv), (uint64_t)c});
-            }
-            __syncthreads();
-            if (tk.need_flush(256)) tk.flush(tid, 256);
-        }
-        if (tk.need_flush(M - Kp)) tk.flush(tid, 256);
+        if (tk.need_flush(256)) tk.flush(tid, 256);
     }
+    if (tk.need_flush(M - Kp)) tk.flush(tid, 256);
     for (int i = tid; i < a.walk; i += 256) {
         const Key128 kk = keys[i];
         a.coarse_out[(int64_t)b * a.walk + i] = (kk.hi == KEY_INF && kk.lo == KEY_INF) ? -1 : (int64_t)kk.lo;
@@ -576,14 +658,27 @@ hipError_t launch_centroid_mean(const float *x32, int nlist, int d, const int64_
 
 hipError_t launch_probe(const ProbeArgs &a, hipStream_t s) {
     if (a.nlist <= PROBE_SORT_MAX) {
-        const size_t lds = 4 * X64_WAVE_LDS + (size_t)a.cdp * 8 + (size_t)next_pow2(a.nlist) * sizeof(Key128);
-        ensure_dyn_lds((const void *)probe_coarse_kernel<true>, lds);
-        probe_coarse_kernel<true><<<a.B, 256, lds, s>>>(a);
+        const size_t ldsd = 4 * X64_WAVE_LDS + (size_t)a.cdp * 8;
+        ensure_dyn_lds((const void *)probe_cdist_kernel, ldsd);
+        probe_cdist_kernel<<<dim3((a.nlist + 255) / 256, a.B), 256, ldsd, s>>>(a);
+        const int R = std::max(1, next_pow2(a.nlist) / 256);
+        const size_t lds = (size_t)256 * R * sizeof(Key128);
+        auto launch_sort = [&](auto kern) {
+            ensure_dyn_lds((const void *)kern, lds);
+            kern<<<a.B, 256, lds, s>>>(a);
+        };
+        switch (R) {
+        case 1: launch_sort(probe_sort_kernel<1>); break;
+        case 2: launch_sort(probe_sort_kernel<2>); break;
+        case 4: launch_sort(probe_sort_kernel<4>); break;
+        case 8: launch_sort(probe_sort_kernel<8>); break;
+        default: launch_sort(probe_sort_kernel<16>);
+        }
     } else {
         const int Kp = next_pow2(a.walk), M = next_pow2(Kp + 256);
         const size_t lds = 4 * X64_WAVE_LDS + (size_t)a.cdp * 8 + (size_t)M * sizeof(Key128) + sizeof(Key128) + 16;
-        ensure_dyn_lds((const void *)probe_coarse_kernel<false>, lds);
-        probe_coarse_kernel<false><<<a.B, 256, lds, s>>>(a);
+        ensure_dyn_lds((const void *)probe_coarse_kernel, lds);
+        probe_coarse_kernel<<<a.B, 256, lds, s>>>(a);
     }
     probe_prefix_kernel<<<a.B, PROBE_MAX_WALK, 0, s>>>(a);
     // Rounds of the walk: positions [0, nprobe), then windows growing fourfold

@@ -23,7 +23,7 @@ constexpr double PROBE_FIT[4] = {0.175, 2.75e-3, 1.48, 0.438};
 struct ProbePlan {
     int gc, gs, srows;  // counting / scoring workgroups per query, rows per scoring step
     bool two_level;     // partial lists merged in groups of PROBE_FAN first
-    size_t o_cidx, o_pre, o_cnt, o_state, o_part, o_part2, total;
+    size_t o_ckeys, o_cidx, o_pre, o_cnt, o_state, o_part, o_part2, total;
 };
 
 // Launch shape of the probe: small batches split a query's rows over many
@@ -45,6 +45,7 @@ ProbePlan probe_plan(const vrs_index_s *ix, int B, int k, int nprobe, int64_t ca
         o += a256(bytes);
         return r;
     };
+    P.o_ckeys = take(ix->nlist <= PROBE_SORT_MAX ? (size_t)B * next_pow2(ix->nlist) * 16 : 0);
     P.o_cidx = take((size_t)B * walk * 8);
     P.o_pre = take((size_t)B * (walk + 1) * 8);
     P.o_cnt = take((size_t)B * walk * 4);
@@ -202,6 +203,7 @@ hipError_t run_probe(const vrs_index_s *ix, const float *q, int B, const PredDev
     a.cent_rows = ix->cent_tab->rows;
     a.cdp = ix->cent_tab->dp;
     a.nlist = ix->nlist;
+    a.ckeys = ix->nlist <= PROBE_SORT_MAX ? (void *)(w + P.o_ckeys) : nullptr;
     a.coarse_out = cidx;
     a.coarse = cidx;
     a.walk = std::min(ix->nlist, PROBE_MAX_WALK);

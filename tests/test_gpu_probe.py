@@ -144,3 +144,28 @@ def test_probe_many_partitions_equals_the_oracle():
             assert np.array_equal(gt2.cpu().numpy(), ref[2]), what
             assert np.array_equal(gi2.cpu().numpy(), ref[0]), what
             assert np.array_equal(gd2.cpu().numpy().view(np.uint32), ref[1].view(np.uint32)), what
+
+
+@pytest.mark.parametrize("nlist", [300, 1500, 3000])
+def test_probe_coarse_sort_widths_equal_the_oracle(nlist):
+    # the coarse scan's sort of every centroid key at 512, 2048 and 4096
+    # keys (two, eight and sixteen per thread), padded past nlist
+    n, d = 24000, 16
+    x = inputs.table(13, n, d, 200)
+    a = inputs.attributes(13, n, 1, 100)
+    T = vrs.Table(_dev(x), _dev(a))
+    ix = vrs.Index(T, nlist, iters=2)
+    ot = O.Table(O.F32, x, a)
+    cent, _, off, ids = O.ivf_build(ot, nlist, 2)
+    gc, go, gi = ix.export()
+    torch.cuda.synchronize()
+    assert np.array_equal(gc.cpu().numpy().view(np.uint32), cent.view(np.uint32))
+    q = inputs.queries(13, 5, d, 200)
+    pred = [(0, 0, 40)]
+    for nprobe, min_cand in ((6, 100), (256, 1)):
+        ref = O.ivf_probe(ot, cent, off, ids, q, pred, 10, O.L2SQ, nprobe, min_cand, 10 ** 6)
+        gi2, gd2, gt2 = ix.probe_topk(_dev(q), pred, 10, vrs.L2SQ, nprobe, min_cand, 10 ** 6)
+        torch.cuda.synchronize()
+        assert np.array_equal(gt2.cpu().numpy(), ref[2]), (nlist, nprobe)
+        assert np.array_equal(gi2.cpu().numpy(), ref[0]), (nlist, nprobe)
+        assert np.array_equal(gd2.cpu().numpy().view(np.uint32), ref[1].view(np.uint32)), (nlist, nprobe)
