@@ -513,11 +513,55 @@ __global__ __launch_bounds__(256) void probe_score_kernel(ProbeArgs a) {
     }
 }
 
+// The k smallest keys of F2 (a power of two) ascending lists of k keys in
+// LDS (list l at L + l k), into list 0: pairwise merges, each list truncated
+// to its k smallest (the k smallest of a union are among the k smallest of
+// each part); output t of a pair is found by a binary search along the merge
+// path (how many of the first t outputs come from the first list).
+constexpr int PROBE_MERGE_KEYS = 4096;  // lists x k held in LDS at once
+__device__ void merge_sorted_lists(Key128 *L, int F2, int k) {
+    constexpr int MAXO = PROBE_MERGE_KEYS / 2 / 256;  // outputs per thread and level
+    const int tid = threadIdx.x;
+    for (int w = 1; w < F2; w <<= 1) {
+        const int tasks = (F2 / (2 * w)) * k;
+        Key128 out[MAXO];
+#pragma unroll
+        for (int r = 0; r < MAXO; ++r) {
+            const int task = tid + r * 256;
+            if (task >= tasks) continue;
+            const int pr = task / k, t = task - pr * k;
+            const Key128 *A = L + (size_t)(2 * w * pr) * k, *Bl = A + (size_t)w * k;
+            // lo = the j in [0, t] where A[j] < B[t - 1 - j] stops holding:
+            // a fixed number of halving steps (t < k <= 256), so that the
+            // searches of a thread's outputs run side by side
+            int lo = 0;
+#pragma unroll
+            for (int step = 256; step > 0; step >>= 1) {
+                const int j = lo + step - 1;
+                if (j < t && KeyOps<Key128>::less(A[j], Bl[t - 1 - j])) lo += step;
+            }
+            const Key128 x = A[lo], y = Bl[t - lo];
+            out[r] = KeyOps<Key128>::less(y, x) ? y : x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < MAXO; ++r) {
+            const int task = tid + r * 256;
+            if (task >= tasks) continue;
+            const int pr = task / k, t = task - pr * k;
+            L[(size_t)(2 * w * pr) * k + t] = out[r];
+        }
+        __syncthreads();
+    }
+}
+
 // Workgroup (j, b): the k smallest keys of query b's partial lists
 // [j * fan, (j + 1) * fan) (level 0: the scoring tasks' lists; level 1: the
 // merged groups of PROBE_FAN of them), into dst, or, when dst is null (one
-// workgroup per query over all lists), into the outputs.  Keys are read four
-// per thread before they are offered to the running list.
+// workgroup per query over all lists), into the outputs.  Every list is
+// ascending (a running list's final state); when they fit in LDS together
+// they are merged pairwise (merge_sorted_lists), otherwise their keys are
+// offered to a running list, four per thread at a time.
 __global__ __launch_bounds__(256) void probe_merge_kernel(ProbeArgs a, const uint64_t *src, int src_stride,
                                                           int level, int fan, uint64_t *dst, int dst_stride) {
     const int j = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
@@ -528,31 +572,39 @@ __global__ __launch_bounds__(256) void probe_merge_kernel(ProbeArgs a, const uin
     const int l0 = dst ? j * fan : 0, l1 = dst ? min(n_in, (j + 1) * fan) : n_in;
     if (dst && l0 >= l1) return;  // (uniform)
     extern __shared__ __align__(16) unsigned char smem[];
-    const int Kp = next_pow2(a.k);
-    const int M = next_pow2(Kp + 256);
     Key128 *keys = (Key128 *)smem;
-    Key128 *thr = keys + M;
-    int *cnt = (int *)(thr + 1);
-    TopkLds<Key128> tk{keys, cnt, thr, 1, a.k, Kp, M - Kp};
-    tk.init(tid, 256);
     const uint64_t *s0 = src + ((int64_t)b * src_stride + l0) * a.k * 2;
-    const int64_t tot = (int64_t)(l1 - l0) * a.k;
-    constexpr int RM = 4;
-    for (int64_t p0 = 0; p0 < tot; p0 += 256 * RM) {
-        Key128 kk[RM];
+    const int F = max(0, l1 - l0), F2 = next_pow2(max(F, 1));
+    if (F2 * a.k <= PROBE_MERGE_KEYS && a.k <= 256) {
+        for (int p = tid; p < F2 * a.k; p += 256)
+            keys[p] = p < F * a.k ? Key128{s0[2 * p], s0[2 * p + 1]} : Key128{KEY_INF, KEY_INF};
+        __syncthreads();
+        merge_sorted_lists(keys, F2, a.k);
+    } else {
+        const int Kp = next_pow2(a.k);
+        const int M = next_pow2(Kp + 256);
+        Key128 *thr = keys + M;
+        int *cnt = (int *)(thr + 1);
+        TopkLds<Key128> tk{keys, cnt, thr, 1, a.k, Kp, M - Kp};
+        tk.init(tid, 256);
+        const int64_t tot = (int64_t)F * a.k;
+        constexpr int RM = 4;
+        for (int64_t p0 = 0; p0 < tot; p0 += 256 * RM) {
+            Key128 kk[RM];
 #pragma unroll
-        for (int r = 0; r < RM; ++r) {
-            const int64_t pi = p0 + r * 256 + tid;
-            kk[r] = pi < tot ? Key128{s0[2 * pi], s0[2 * pi + 1]} : Key128{KEY_INF, KEY_INF};
-        }
+            for (int r = 0; r < RM; ++r) {
+                const int64_t pi = p0 + r * 256 + tid;
+                kk[r] = pi < tot ? Key128{s0[2 * pi], s0[2 * pi + 1]} : Key128{KEY_INF, KEY_INF};
+            }
 #pragma unroll
-        for (int r = 0; r < RM; ++r) {
-            if (kk[r].hi != KEY_INF || kk[r].lo != KEY_INF) tk.push(0, kk[r]);
-            __syncthreads();
-            if (tk.need_flush(256)) tk.flush(tid, 256);
+            for (int r = 0; r < RM; ++r) {
+                if (kk[r].hi != KEY_INF || kk[r].lo != KEY_INF) tk.push(0, kk[r]);
+                __syncthreads();
+                if (tk.need_flush(256)) tk.flush(tid, 256);
+            }
         }
+        if (tk.need_flush(M - Kp)) tk.flush(tid, 256);
     }
-    if (tk.need_flush(M - Kp)) tk.flush(tid, 256);
     if (dst) {
         uint64_t *o = dst + ((int64_t)b * dst_stride + j) * a.k * 2;
         for (int i = tid; i < a.k; i += 256) {
@@ -682,7 +734,9 @@ hipError_t launch_probe(const ProbeArgs &a, hipStream_t s) {
     }
     probe_prefix_kernel<<<a.B, PROBE_MAX_WALK, 0, s>>>(a);
     // Rounds of the walk: positions [0, nprobe), then windows growing fourfold
-    // up to the walk's end; a query leaves the rounds once its walk is decided.
+    // up to the walk's end (at most 16 queries: the rest of the walk in one
+    // window, since each round costs two launches and a few queries' rows
+    // are few); a query leaves the rounds once its walk is decided.
     ProbeArgs r = a;
     r.w0 = 0;
     r.w1 = std::min(a.nprobe, a.walk);
@@ -691,7 +745,7 @@ hipError_t launch_probe(const ProbeArgs &a, hipStream_t s) {
         probe_decide_kernel<<<(a.B + 255) / 256, 256, 0, s>>>(r);
         if (r.w1 >= a.walk) break;
         r.w0 = r.w1;
-        r.w1 = std::min(a.walk, 4 * r.w1);
+        r.w1 = a.B <= 16 ? a.walk : std::min(a.walk, 4 * r.w1);
     }
     hipError_t e;
     if (a.metric == VRS_L2SQ) {
@@ -705,7 +759,9 @@ hipError_t launch_probe(const ProbeArgs &a, hipStream_t s) {
     }
     if (e != hipSuccess) return e;
     const int Kp = next_pow2(a.k), M = next_pow2(Kp + 256);
-    const size_t lds = (size_t)M * sizeof(Key128) + sizeof(Key128) + 16;
+    const size_t lds = std::max((size_t)M * sizeof(Key128) + sizeof(Key128) + 16,
+                                (size_t)PROBE_MERGE_KEYS * sizeof(Key128));
+    ensure_dyn_lds((const void *)probe_merge_kernel, lds);
     if (a.part2) {  // groups of PROBE_FAN lists first, then one list per query
         const int g2 = (a.gs + PROBE_FAN - 1) / PROBE_FAN;
         probe_merge_kernel<<<dim3(g2, a.B), 256, lds, s>>>(a, a.part, a.gs, 0, PROBE_FAN, a.part2, g2);

@@ -169,3 +169,38 @@ def test_probe_coarse_sort_widths_equal_the_oracle(nlist):
         assert np.array_equal(gt2.cpu().numpy(), ref[2]), (nlist, nprobe)
         assert np.array_equal(gi2.cpu().numpy(), ref[0]), (nlist, nprobe)
         assert np.array_equal(gd2.cpu().numpy().view(np.uint32), ref[1].view(np.uint32)), (nlist, nprobe)
+
+
+def test_probe_k_extremes_equal_the_oracle(built):
+    # k = 1: single-key partial lists
+    x, a, T, ix, ot, (cent, assign, off, ids) = built
+    q = inputs.queries(9, 3, x.shape[1], 200, stream_offset=3)
+    pred = [(0, 0, 60)]
+    for nprobe, min_cand in ((8, 10), (64, 1)):
+        ref = O.ivf_probe(ot, cent, off, ids, q, pred, 1, O.L2SQ, nprobe, min_cand, 10 ** 6)
+        gi, gd, gt = ix.probe_topk(_dev(q), pred, 1, vrs.L2SQ, nprobe, min_cand, 10 ** 6)
+        torch.cuda.synchronize()
+        assert np.array_equal(gt.cpu().numpy(), ref[2]), nprobe
+        assert np.array_equal(gi.cpu().numpy(), ref[0]), nprobe
+        assert np.array_equal(gd.cpu().numpy().view(np.uint32), ref[1].view(np.uint32)), nprobe
+
+
+def test_probe_largest_k_many_lists_equals_the_oracle():
+    # k = 256 over 300,000 visited rows: 512 scoring lists, merged in groups
+    # of 16 and then 32 groups of 256 keys, more than the pairwise merge
+    # holds in LDS (the running-list path)
+    n, d, nlist = 300000, 16, 64
+    x = inputs.table(14, n, d, 100)
+    a = inputs.attributes(14, n, 1, 100)
+    T = vrs.Table(_dev(x), _dev(a))
+    ix = vrs.Index(T, nlist, iters=2)
+    ot = O.Table(O.F32, x, a)
+    cent, _, off, ids = O.ivf_build(ot, nlist, 2)
+    q = inputs.queries(14, 1, d, 100)
+    pred = [(0, 0, 80)]
+    ref = O.ivf_probe(ot, cent, off, ids, q, pred, 256, O.L2SQ, 64, 1, 10 ** 6)
+    gi, gd, gt = ix.probe_topk(_dev(q), pred, 256, vrs.L2SQ, 64, 1, 10 ** 6)
+    torch.cuda.synchronize()
+    assert np.array_equal(gt.cpu().numpy(), ref[2])
+    assert np.array_equal(gi.cpu().numpy(), ref[0])
+    assert np.array_equal(gd.cpu().numpy().view(np.uint32), ref[1].view(np.uint32))
