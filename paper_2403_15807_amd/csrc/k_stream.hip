@@ -87,7 +87,11 @@ __global__ __launch_bounds__(256) void screen_stream_kernel(ScreenArgs a) {
 
     const int64_t total = GATHER ? *a.sel_count : a.n;
     int64_t per = (total + a.n_chunks - 1) / a.n_chunks;
-    per = (per + TILE - 1) / TILE * TILE;
+    // (masked rows: whole tiles per chunk, so that row loads stay aligned;
+    // gathered rows are scattered anyway, and a selective predicate's few
+    // ids then spread over every chunk instead of filling a few chunks'
+    // lists, which the merge would read a few keys at a time)
+    if (!GATHER) per = (per + TILE - 1) / TILE * TILE;
     const int64_t c0 = (int64_t)chunk * per;
     const int64_t c1 = min(total, c0 + per);
     const int eb = (STORE == VRS_F32) ? 4 : (STORE == VRS_BF16 ? 2 : 1);
