@@ -48,7 +48,7 @@ ATTR = 10 ** 6
 # Sources that make up each screening kernel (a traffic figure measured on an
 # older version of them is not reported).
 KERNEL_SOURCES = {
-    "screen_stream": ["k_stream.hip"],
+    "screen_stream": ["k_stream.hip", "topk_sized.h"],
     "screen_mfma_f32": ["k_mfma.hip", "wave_topk.h"],
     "screen_mfma_bf16": ["k_mfma_bf16.hip", "wave_topk.h"],
     "range_screen": ["k_range.hip", "exact64.h"],

@@ -27,6 +27,7 @@
 // in sub-block runs (ascending within a run, runs in the order their waves
 // reserve them): the gather screening does not depend on the order.
 #include "internal.h"
+#include "topk_sized.h"
 
 namespace vrs {
 
@@ -440,7 +441,7 @@ __global__ __launch_bounds__(256) void screen_sparse_kernel(ScreenArgs a) {
             }
             __syncthreads();
             if (tk.need_flush(STILE)) {
-                tk.flush(tid, 256);
+                flush_sized<uint64_t, 256>(tk, tid);
                 if (tid == 0 && thr[0] != KEY_INF) {
                     const uint64_t prev = atomicMin((unsigned long long *)(a.gthr + pos),
                                                     (unsigned long long)thr[0]);
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(256) void screen_sparse_kernel(ScreenArgs a) {
                 __syncthreads();
             }
         }
-        if (tk.need_flush(M - Kp)) tk.flush(tid, 256);
+        if (tk.need_flush(M - Kp)) flush_sized<uint64_t, 256>(tk, tid);
         uint64_t *dst = a.partials + ((int64_t)nd * nc + a.seg_pre[j] + seg) * a.K;
         for (int i = tid; i < a.K; i += 256) dst[i] = i < Kq ? keys[i] : KEY_INF;
         __syncthreads();  // LDS and item_s are reused by the next item

@@ -26,6 +26,7 @@
 //   probe_merge: per query the k smallest of its workgroups' keys, written
 //       out.
 #include "exact64.h"
+#include "topk_sized.h"
 
 namespace vrs {
 
@@ -494,7 +495,7 @@ __global__ __launch_bounds__(256) void probe_score_kernel(ProbeArgs a) {
                     if (has) tk.push(0, Key128{ord64(dv), (uint64_t)(uint32_t)a.ids[pos]});
                 }
                 __syncthreads();
-                if (tk.need_flush(256)) tk.flush(tid, 256);
+                if (tk.need_flush(256)) flush_sized<Key128, 256>(tk, tid);
             }
             // the fewer than 256 rows left over move to the front of the list
             const int rem = nl - nfull;
@@ -505,7 +506,7 @@ __global__ __launch_bounds__(256) void probe_score_kernel(ProbeArgs a) {
             __syncthreads();
         }
     }
-    if (tk.need_flush(M - Kp)) tk.flush(tid, 256);
+    if (tk.need_flush(M - Kp)) flush_sized<Key128, 256>(tk, tid);
     uint64_t *dst = a.part + ((int64_t)b * a.gs + g) * a.k * 2;
     for (int i = tid; i < a.k; i += 256) {
         dst[2 * i] = keys[i].hi;

@@ -11,6 +11,7 @@
 // that is merged into the query's sorted list when it fills (TopkLds).  The
 // chunk's K smallest keys are written out sorted for the cross-chunk merge.
 #include "internal.h"
+#include "topk_sized.h"
 
 namespace vrs {
 
@@ -21,75 +22,6 @@ constexpr int TILE = 4 * 8 * U;      // rows per workgroup iteration
 constexpr int NB = 4;                // 128-byte column blocks loaded together
 
 typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
-
-// TopkLds::flush with a sort only as wide as the keys held: when every
-// list's keys (its first `fill` entries; the rest of a list is +inf) and its
-// buffer fit in the list's Kp entries, the buffer is appended to the keys
-// and the first S = next_pow2(max fill + cnt) entries of each list are
-// sorted (bitonic, lists at stride M), instead of all M entries of every
-// list.  Same result as flush().  The 256 threads of the workgroup call it;
-// at most 8 lists.
-__device__ void flush_sized(TopkLds<uint64_t> &tk, int tid) {
-    constexpr int NT = 256;
-    __shared__ int fill_s[8];
-    const int nq = tk.nq, Kp = tk.Kp, M = tk.M();
-    uint64_t *keys = tk.keys;
-    if (nq > 8) {
-        tk.flush(tid, NT);
-        return;
-    }
-    if (tid < nq) fill_s[tid] = Kp;
-    __syncthreads();
-    for (int p = tid; p < nq * Kp; p += NT) {
-        const int b = p / Kp, i = p - b * Kp;
-        const uint64_t *l = keys + (size_t)b * M;
-        if (l[i] == KEY_INF && (i == 0 || l[i - 1] != KEY_INF)) fill_s[b] = i;  // the first +inf entry
-    }
-    __syncthreads();
-    int S = 2;
-    bool fits = true;
-    for (int b = 0; b < nq; ++b) {
-        const int need = fill_s[b] + tk.cnt[b];
-        fits = fits && need <= Kp;
-        while (S < need) S <<= 1;
-    }
-    if (!fits || S >= M) {  // (uniform)
-        tk.flush(tid, NT);
-        return;
-    }
-    for (int p = tid; p < nq * tk.CB; p += NT) {
-        const int b = p / tk.CB, i = p - b * tk.CB;
-        if (i < tk.cnt[b]) keys[(size_t)b * M + fill_s[b] + i] = keys[(size_t)b * M + Kp + i];
-    }
-    __syncthreads();
-    const int half = S >> 1, lgh = __ffs(half) - 1;
-    for (int size = 2; size <= S; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const int lgs = __ffs(stride) - 1;
-            for (int p = tid; p < nq * half; p += NT) {
-                const int seg = p >> lgh, pi = p & (half - 1);
-                const int i = ((pi >> lgs) << (lgs + 1)) + (pi & (stride - 1)), j = i + stride;
-                uint64_t *sg = keys + (size_t)seg * M;
-                const uint64_t x = sg[i], y = sg[j];
-                if ((i & size) == 0 ? y < x : x < y) {
-                    sg[i] = y;
-                    sg[j] = x;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int p = tid; p < nq * (Kp - tk.Kkeep); p += NT) {
-        const int b = p / (Kp - tk.Kkeep), i = p - b * (Kp - tk.Kkeep);
-        keys[(size_t)b * M + tk.Kkeep + i] = KEY_INF;
-    }
-    __syncthreads();
-    for (int b = tid; b < nq; b += NT) {
-        tk.thr[b] = keys[(size_t)b * M + tk.Kkeep - 1];
-        tk.cnt[b] = 0;
-    }
-    __syncthreads();
-}
 
 // One-query workgroups: publish this chunk's best key (its list's first)
 // in the query's row of heads, then take the K-th smallest distance of all
@@ -295,7 +227,7 @@ __global__ __launch_bounds__(256) void screen_stream_kernel(ScreenArgs a) {
         decide(nvd, nav, qual);
         __syncthreads();
         if (tk.need_flush(TILE)) {
-            flush_sized(tk, tid);
+            flush_sized<uint64_t, 256>(tk, tid);
             // publish this chunk's K-th key per query and adopt the best one
             if (tid < QT && qt0 + tid < a.B && thr[tid] != KEY_INF) {
                 const uint64_t prev = atomicMin((unsigned long long *)(a.gthr + qt0 + tid),
@@ -307,7 +239,7 @@ __global__ __launch_bounds__(256) void screen_stream_kernel(ScreenArgs a) {
             __syncthreads();
         }
     }
-    if (tk.need_flush(a.CB)) flush_sized(tk, tid);  // any pending candidate
+    if (tk.need_flush(a.CB)) flush_sized<uint64_t, 256>(tk, tid);  // any pending candidate
     for (int i = tid; i < QT * a.K; i += 256) {
         int b = i / a.K, j = i - b * a.K;
         if (qt0 + b < a.B)
