@@ -47,16 +47,25 @@ __global__ __launch_bounds__(256) void select_bitmap_kernel(const int32_t *__res
             q[s] = ok;
         }
     }
+    // step s's 64-bit mask goes to lane s, and the wave's 32 masks are
+    // written by one store instruction (instead of 64 single-lane stores)
+    static_assert(SEL_STEPS <= 64, "one lane per step");
     uint32_t mycount = 0;
+    uint64_t mine = 0;
 #pragma unroll
     for (int s = 0; s < SEL_STEPS; ++s) {
         const uint64_t m = __ballot(q[s]);
-        const int64_t row0 = (int64_t)blockIdx.x * SEL_BLOCK_ROWS + s * 256 + wave * 64;
-        if (lane == 0 && row0 < n) {
+        mine = lane == s ? m : mine;
+        mycount += (uint32_t)__popcll(m);  // (rows past n never qualify)
+    }
+    {
+        const int64_t row0 = (int64_t)blockIdx.x * SEL_BLOCK_ROWS + lane * 256 + wave * 64;
+        if (lane < SEL_STEPS && row0 < n) {
             const int64_t w = row0 >> 5;  // row0 is a multiple of 64
-            bitmap[w] = (uint32_t)m;
-            if (row0 + 32 < n) bitmap[w + 1] = (uint32_t)(m >> 32);
-            mycount += (uint32_t)__popcll(m);
+            if (row0 + 32 < n)
+                *(uint2 *)(bitmap + w) = make_uint2((uint32_t)mine, (uint32_t)(mine >> 32));
+            else
+                bitmap[w] = (uint32_t)mine;
         }
     }
     __shared__ uint32_t wc[4];
