@@ -65,6 +65,8 @@ Plan make_plan(const vrs_table_s *t, int B, int kmax, const vrs_opts *opts, int 
         const int occ = t->store == VRS_F32 ? screen_mfma_occupancy(P.Kp, P.CB, B <= 16 ? 16 : P.qt) : 1;
         const int64_t slots = (int64_t)256 * occ * cfg.wg_target / 4;
         const int64_t rows = est_rows < 0 ? t->n : std::min<int64_t>(std::max<int64_t>(est_rows, 1), t->n);
+        // at least 256 rows per chunk: a small selection still spreads over
+        // many workgroups (with 1024 a 10,000-row selection ran as 8 chunks)
         int64_t max_chunks = std::max<int64_t>(1, rows / 256);
         int64_t nc = std::max<int64_t>(1, std::min<int64_t>(max_chunks, slots / P.n_qtiles));
         if (nc >= 8) nc = nc / 8 * 8;  // whole XCD groups: a row chunk's query tiles share an L2
