@@ -447,9 +447,12 @@ hipError_t run_scan(const vrs_table_s *t, const float *q, int B, const PredDev &
     fa.heads = sa.heads;
     fa.fills = sa.fills;
     // with a dense predicate the chunk lists are full and one head per list
-    // bounds the merge well; with a selective one a chunk's few rows come
-    // from one neighbourhood and several heads per list are needed
-    fa.merge_one_head = feats[3] >= (float)std::log(0.05);
+    // bounds the merge well; with a selective one a chunk's rows come from
+    // one neighbourhood and several heads per list are needed, unless the
+    // lists hold few keys each (at most 128 qualifying rows per chunk
+    // expected: gathered rows spread over the streaming kernel's many chunks)
+    const double keys_per_list = std::exp((double)feats[3]) * (double)t->n / std::max(1, P.n_chunks);
+    fa.merge_one_head = feats[3] >= (float)std::log(0.05) || keys_per_list <= 128.0;
     fa.merge_mid = (uint64_t *)(w + P.o_mid);
     fa.merged = (uint64_t *)(w + P.o_merged);
     fa.rr_dist = (double *)(w + P.o_rrdist);
