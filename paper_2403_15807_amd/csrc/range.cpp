@@ -101,7 +101,9 @@ hipError_t run_range(const vrs_table_s *t, const float *q, int B, const PredDev 
     const int qt = B >= 8 ? 8 : (B >= 4 ? 4 : (B >= 2 ? 2 : 1));
     const int qg = (B + qt - 1) / qt;
     const int64_t rows = gather ? std::max<int64_t>(1, (int64_t)(estimate_selectivity(t, p) * t->n)) : t->n;
-    a.n_chunks = (int)std::max<int64_t>(1, std::min<int64_t>((rows + 1023) / 1024, 2048 / qg));
+    // (at most 1024 workgroups per query group: 2048 ran as one full round
+    // of resident workgroups and a partial second one, 2 % slower)
+    a.n_chunks = (int)std::max<int64_t>(1, std::min<int64_t>((rows + 1023) / 1024, 1024 / qg));
     a.cap_c = P.cap_c;
     a.cnt = (uint32_t *)(w + P.o_cnt);
     a.cand = (int32_t *)(w + P.o_cand);
